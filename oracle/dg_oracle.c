@@ -1,0 +1,1077 @@
+/*
+ * dg_oracle.c -- plain FP64 CPU reference of the RKDG step with the compact
+ * subcell WENO (CSWENO) limiter of Kochi & Ramakrishna, "A compact subcell
+ * WENO limiting strategy using immediate neighbors for Runge-Kutta
+ * Discontinuous Galerkin Methods" (arXiv 1904.11147).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle the HIP path is checked
+ * against.  Only the tests, the smoke check and the benchmark's CPU-baseline
+ * leg may load it; the product library never does.  It shares no source,
+ * header, table or generator with the HIP path: every coefficient it uses is
+ * derived here, at run time, from the definitions in the paper.
+ *
+ * Style: straightforward loops, no blocking or fusion, double precision,
+ * built without fast-math and without FMA contraction.  Where the paper is
+ * silent or garbled the reading taken is stated at the point of use.
+ *
+ * Layout of a state: U[v][q][j][i] (i fastest), q = m + (N+1)*n where m is
+ * the x-degree and n the y-degree of the tensor Legendre mode (1D: q = m).
+ *
+ * Parity pins: quadrature, P2 tables, P1 tables, residual, TVB and limiter
+ * invariants are pinned by tests/test_oracle_*.py.  The P3 treatment of the
+ * negative linear weights is "parity unpinned" (the paper does not say what
+ * it does with them; see orc_weno_point).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAXN 3
+#define ORC_MAXP 4  /* N+1 */
+#define ORC_MAXS 7  /* 2N+1 stencil cells */
+#define ORC_MAXG 4  /* reconstruction points */
+#define ORC_MAXV 4  /* variables */
+#define ORC_MAXM 16 /* modes per cell */
+#define ORC_MAXPQ 10 /* projection nodes per direction: 2 panels x (N+2) */
+
+enum { ORC_BURGERS = 0, ORC_EULER = 1 };
+enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1 };
+enum { ORC_LIM_NONE = 0, ORC_LIM_CSWENO = 1 };
+enum { ORC_IND_TVB = 0, ORC_IND_ALL = 1 };
+enum { ORC_NEGW_SPLIT = 0, ORC_NEGW_RAW = 1 };
+enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_NONPHYSICAL = -5, ORC_ERR_TABLE = -6 };
+
+typedef struct {
+  int32_t dim, equation, order, nx, ny;
+  int32_t bc[4]; /* W, E, S, N */
+  int32_t limiter, indicator, negw_mode;
+  double gamma, x0, x1, y0, y1, tvb_M, weno_eps, cfl;
+} orc_config;
+
+/* ------------------------------------------------------------------------ */
+/* Section 2: orthonormal Legendre basis on the reference cell r in [-1,1]. */
+/* ------------------------------------------------------------------------ */
+
+static double leg(int n, double r) {
+  /* Bonnet recurrence (k+1) P_{k+1} = (2k+1) r P_k - k P_{k-1}. */
+  if (n == 0) return 1.0;
+  double p0 = 1.0, p1 = r;
+  for (int k = 1; k < n; ++k) {
+    double p2 = ((2.0 * k + 1.0) * r * p1 - k * p0) / (k + 1.0);
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+
+static double dleg(int n, double r) {
+  /* P_n' = sum over k = n-1, n-3, ... >= 0 of (2k+1) P_k. */
+  double s = 0.0;
+  for (int k = n - 1; k >= 0; k -= 2) s += (2.0 * k + 1.0) * leg(k, r);
+  return s;
+}
+
+static double psi(int n, double r) { return sqrt((2.0 * n + 1.0) / 2.0) * leg(n, r); }
+static double dpsi(int n, double r) { return sqrt((2.0 * n + 1.0) / 2.0) * dleg(n, r); }
+
+/* n-point Gauss-Legendre rule on [-1,1], ascending nodes, by Newton on P_n. */
+static void gauss_rule(int n, double *x, double *w) {
+  for (int i = 0; i < n; ++i) {
+    double r = -cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double d = leg(n, r) / dleg(n, r);
+      r -= d;
+      if (fabs(d) < 1e-17) break;
+    }
+    double dp = dleg(n, r);
+    x[i] = r;
+    w[i] = 2.0 / ((1.0 - r * r) * dp * dp);
+  }
+}
+
+/* n-point Gauss-Lobatto rule: end points and the roots of P_{n-1}'. */
+static void gauss_lobatto_rule(int n, double *x, double *w) {
+  x[0] = -1.0;
+  x[n - 1] = 1.0;
+  for (int i = 1; i < n - 1; ++i) {
+    double r = -cos(M_PI * i / (n - 1.0));
+    for (int it = 0; it < 100; ++it) {
+      /* Legendre ODE: (1-r^2) P'' = 2 r P' - k(k+1) P with k = n-1. */
+      int k = n - 1;
+      double f = dleg(k, r);
+      double fp = (2.0 * r * dleg(k, r) - k * (k + 1.0) * leg(k, r)) / (1.0 - r * r);
+      double d = f / fp;
+      r -= d;
+      if (fabs(d) < 1e-17) break;
+    }
+    x[i] = r;
+  }
+  for (int i = 0; i < n; ++i) {
+    double p = leg(n - 1, x[i]);
+    w[i] = 2.0 / (n * (n - 1.0) * p * p);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Small dense linear algebra (Gaussian elimination with partial pivoting). */
+/* ------------------------------------------------------------------------ */
+
+static int solve_dense(int n, double *A, double *b) { /* A row-major n x n, b overwritten */
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (fabs(A[r * n + c]) > fabs(A[p * n + c])) p = r;
+    if (A[p * n + c] == 0.0) return -1;
+    if (p != c) {
+      for (int k = 0; k < n; ++k) {
+        double t = A[c * n + k];
+        A[c * n + k] = A[p * n + k];
+        A[p * n + k] = t;
+      }
+      double t = b[c];
+      b[c] = b[p];
+      b[p] = t;
+    }
+    for (int r = c + 1; r < n; ++r) {
+      double f = A[r * n + c] / A[c * n + c];
+      for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    double s = b[r];
+    for (int k = r + 1; k < n; ++k) s -= A[r * n + k] * b[k];
+    b[r] = s / A[r * n + r];
+  }
+  return 0;
+}
+
+/* Mean of xi^d over [a,b]. */
+static double mono_mean(int d, double a, double b) {
+  return (pow(b, d + 1) - pow(a, d + 1)) / ((d + 1.0) * (b - a));
+}
+
+/* Integral of xi^d over the troubled cell [-1/2, 1/2]. */
+static double mono_int_centre(int d) { return (pow(0.5, d + 1) - pow(-0.5, d + 1)) / (d + 1.0); }
+
+/* ------------------------------------------------------------------------ */
+/* Section 3: CSWENO tables, derived in the order of steps 1-3.              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int N, np;
+  double rq[ORC_MAXP], wq[ORC_MAXP]; /* (N+1)-point Gauss: volume and edge rule */
+  int ng;
+  double rg[ORC_MAXG], wg[ORC_MAXG]; /* reconstruction rule (step 1) */
+  double cl[ORC_MAXS], cr[ORC_MAXS]; /* stencil cells in xi = (x - x_j)/h_j */
+  double Ainv[ORC_MAXP][ORC_MAXP][ORC_MAXP]; /* [i][d][k]: coefficient d of p_i from average k of S_i */
+  double gam[ORC_MAXG][ORC_MAXP];            /* linear weights (step 3) */
+  double gam_resid;                          /* max residual of the linear-weight system */
+  int split[ORC_MAXG];                       /* point has a negative linear weight */
+  double sub[ORC_MAXP][ORC_MAXP];            /* [k][n]: mean of psi_n over subcell k of [-1,1] */
+  int npq;
+  double rpq[ORC_MAXPQ], wpq[ORC_MAXPQ]; /* projection rule for initial data */
+  /* basis values at the points the method evaluates: [n][point] */
+  double bq[ORC_MAXP][ORC_MAXP], dbq[ORC_MAXP][ORC_MAXP]; /* psi_n, psi_n' at rq */
+  double bm[ORC_MAXP], bp[ORC_MAXP], b0[ORC_MAXP];        /* psi_n(-1), psi_n(+1), psi_n(0) */
+  double bg[ORC_MAXP][ORC_MAXG];                          /* psi_n at rg */
+  double bpq[ORC_MAXP][ORC_MAXPQ];                        /* psi_n at rpq */
+} orc_tables;
+
+static orc_tables g_tab[ORC_MAXN + 1];
+static int g_tab_ready[ORC_MAXN + 1];
+
+static int build_tables(int N) {
+  orc_tables *T = &g_tab[N];
+  memset(T, 0, sizeof(*T));
+  T->N = N;
+  T->np = N + 1;
+  gauss_rule(N + 1, T->rq, T->wq);
+
+  /* Step 1: a rule exact to the order the reconstruction needs.  P1: 2-point
+   * Gauss; P2: 4-point Gauss-Lobatto; P3: 4-point Gauss. */
+  if (N == 1) {
+    T->ng = 2;
+    gauss_rule(2, T->rg, T->wg);
+  } else if (N == 2) {
+    T->ng = 4;
+    gauss_lobatto_rule(4, T->rg, T->wg);
+  } else {
+    T->ng = 4;
+    gauss_rule(4, T->rg, T->wg);
+  }
+
+  /* Compact stencil: each immediate neighbour is cut into N equal subcells;
+   * the troubled cell stays whole (for N = 1 the neighbours stay whole too).
+   * Cells are numbered left to right. */
+  int ns = 2 * N + 1;
+  for (int k = 0; k < N; ++k) {
+    T->cl[k] = -1.5 + (double)k / N;
+    T->cr[k] = -1.5 + (double)(k + 1) / N;
+    T->cl[N + 1 + k] = 0.5 + (double)k / N;
+    T->cr[N + 1 + k] = 0.5 + (double)(k + 1) / N;
+  }
+  T->cl[N] = -0.5;
+  T->cr[N] = 0.5;
+
+  /* Step 2: p_i of degree N whose means on the N+1 cells of S_i = cells
+   * i..i+N equal the data, and Q of degree 2N on all 2N+1 cells. */
+  for (int i = 0; i <= N; ++i) {
+    for (int k = 0; k <= N; ++k) {
+      double A[ORC_MAXP * ORC_MAXP], e[ORC_MAXP];
+      for (int r = 0; r <= N; ++r)
+        for (int d = 0; d <= N; ++d) A[r * (N + 1) + d] = mono_mean(d, T->cl[i + r], T->cr[i + r]);
+      for (int r = 0; r <= N; ++r) e[r] = (r == k) ? 1.0 : 0.0;
+      if (solve_dense(N + 1, A, e)) return ORC_ERR_TABLE;
+      for (int d = 0; d <= N; ++d) T->Ainv[i][d][k] = e[d];
+    }
+  }
+  double AQinv[ORC_MAXS][ORC_MAXS];
+  for (int k = 0; k < ns; ++k) {
+    double A[ORC_MAXS * ORC_MAXS], e[ORC_MAXS];
+    for (int r = 0; r < ns; ++r)
+      for (int d = 0; d < ns; ++d) A[r * ns + d] = mono_mean(d, T->cl[r], T->cr[r]);
+    for (int r = 0; r < ns; ++r) e[r] = (r == k) ? 1.0 : 0.0;
+    if (solve_dense(ns, A, e)) return ORC_ERR_TABLE;
+    for (int d = 0; d < ns; ++d) AQinv[d][k] = e[d];
+  }
+
+  /* Step 3: linear weights with Q(x_G) = sum_i gamma_i p_i(x_G) for every
+   * data vector, i.e. 2N+1 equations in N+1 unknowns, solved in the least
+   * squares sense; the residual is recorded and must vanish. */
+  T->gam_resid = 0.0;
+  for (int G = 0; G < T->ng; ++G) {
+    double xi = 0.5 * T->rg[G];
+    double M[ORC_MAXS][ORC_MAXP], rhs[ORC_MAXS];
+    for (int k = 0; k < ns; ++k) {
+      double q = 0.0;
+      for (int d = 0; d < ns; ++d) q += AQinv[d][k] * pow(xi, d);
+      rhs[k] = q;
+      for (int i = 0; i <= N; ++i) {
+        double t = 0.0;
+        if (k >= i && k <= i + N)
+          for (int d = 0; d <= N; ++d) t += T->Ainv[i][d][k - i] * pow(xi, d);
+        M[k][i] = t;
+      }
+    }
+    double NtN[ORC_MAXP * ORC_MAXP], Ntb[ORC_MAXP];
+    for (int a = 0; a <= N; ++a) {
+      Ntb[a] = 0.0;
+      for (int k = 0; k < ns; ++k) Ntb[a] += M[k][a] * rhs[k];
+      for (int b = 0; b <= N; ++b) {
+        double s = 0.0;
+        for (int k = 0; k < ns; ++k) s += M[k][a] * M[k][b];
+        NtN[a * (N + 1) + b] = s;
+      }
+    }
+    if (solve_dense(N + 1, NtN, Ntb)) return ORC_ERR_TABLE;
+    int neg = 0;
+    for (int i = 0; i <= N; ++i) {
+      T->gam[G][i] = Ntb[i];
+      if (Ntb[i] < 0.0) neg = 1;
+    }
+    T->split[G] = neg;
+    for (int k = 0; k < ns; ++k) {
+      double s = -rhs[k];
+      for (int i = 0; i <= N; ++i) s += M[k][i] * T->gam[G][i];
+      if (fabs(s) > T->gam_resid) T->gam_resid = fabs(s);
+    }
+  }
+  if (T->gam_resid > 1e-10) return ORC_ERR_TABLE;
+
+  /* Means of psi_n over the N equal subcells of [-1,1] (N+1-point Gauss on
+   * each subcell integrates psi_n exactly). */
+  for (int k = 0; k < N; ++k) {
+    double a = -1.0 + 2.0 * k / N, b = -1.0 + 2.0 * (k + 1) / N;
+    for (int n = 0; n <= N; ++n) {
+      double s = 0.0;
+      for (int q = 0; q <= N; ++q) {
+        double r = 0.5 * (a + b) + 0.5 * (b - a) * T->rq[q];
+        s += 0.5 * T->wq[q] * psi(n, r);
+      }
+      T->sub[k][n] = s; /* (1/(b-a)) * (b-a)/2 * sum w psi */
+    }
+  }
+
+  /* Projection of initial data: two panels [-1,0] and [0,1], each with an
+   * (N+2)-point Gauss rule (exact to degree 2N+3 per panel), so a jump at a
+   * cell face or a cell centre is integrated piecewise. */
+  double px[ORC_MAXPQ], pw[ORC_MAXPQ];
+  int m = N + 2;
+  gauss_rule(m, px, pw);
+  T->npq = 2 * m;
+  for (int k = 0; k < m; ++k) {
+    T->rpq[k] = -0.5 + 0.5 * px[k];
+    T->wpq[k] = 0.5 * pw[k];
+    T->rpq[m + k] = 0.5 + 0.5 * px[k];
+    T->wpq[m + k] = 0.5 * pw[k];
+  }
+  for (int n = 0; n <= N; ++n) {
+    for (int q = 0; q <= N; ++q) {
+      T->bq[n][q] = psi(n, T->rq[q]);
+      T->dbq[n][q] = dpsi(n, T->rq[q]);
+    }
+    T->bm[n] = psi(n, -1.0);
+    T->bp[n] = psi(n, 1.0);
+    T->b0[n] = psi(n, 0.0);
+    for (int G = 0; G < T->ng; ++G) T->bg[n][G] = psi(n, T->rg[G]);
+    for (int a = 0; a < T->npq; ++a) T->bpq[n][a] = psi(n, T->rpq[a]);
+  }
+  g_tab_ready[N] = 1;
+  return ORC_OK;
+}
+
+static const orc_tables *tables(int N) {
+  if (N < 1 || N > ORC_MAXN) return NULL;
+  if (!g_tab_ready[N] && build_tables(N) != ORC_OK) return NULL;
+  return &g_tab[N];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Steps 2, 4, 5: one WENO reconstruction at point G from the 2N+1 stencil   */
+/* means a[] (left to right).                                               */
+/* ------------------------------------------------------------------------ */
+
+static void small_poly(const orc_tables *T, int i, const double *a, double *c) {
+  for (int d = 0; d <= T->N; ++d) {
+    double s = 0.0;
+    for (int k = 0; k <= T->N; ++k) s += T->Ainv[i][d][k] * a[i + k];
+    c[d] = s;
+  }
+}
+
+/* beta_i = sum_{l=1..N} int_{I_j} dx^{2l-1} (d^l p_i / dx^l)^2 dx, which in
+ * the unit variable xi is sum_l int_{-1/2}^{1/2} (p_i^{(l)}(xi))^2 dxi. */
+static double smoothness(int N, const double *c) {
+  double beta = 0.0;
+  for (int l = 1; l <= N; ++l) {
+    double e[ORC_MAXP];
+    int ne = N + 1 - l;
+    for (int d = 0; d < ne; ++d) {
+      double f = 1.0;
+      for (int t = 0; t < l; ++t) f *= (double)(d + l - t);
+      e[d] = c[d + l] * f;
+    }
+    for (int d1 = 0; d1 < ne; ++d1)
+      for (int d2 = 0; d2 < ne; ++d2) beta += e[d1] * e[d2] * mono_int_centre(d1 + d2);
+  }
+  return beta;
+}
+
+static double orc_weno_point(const orc_tables *T, int G, const double *a, double eps, int negw_mode) {
+  int N = T->N;
+  double xi = 0.5 * T->rg[G];
+  double p[ORC_MAXP], beta[ORC_MAXP];
+  for (int i = 0; i <= N; ++i) {
+    double c[ORC_MAXP];
+    small_poly(T, i, a, c);
+    double v = 0.0;
+    for (int d = 0; d <= N; ++d) v += c[d] * pow(xi, d);
+    p[i] = v;
+    beta[i] = smoothness(N, c);
+  }
+  if (!T->split[G] || negw_mode == ORC_NEGW_RAW) {
+    /* Step 5 with the nonlinear weights normalised to sum to one:
+     * wbar_i = gamma_i / (eps + beta_i)^2. */
+    double wsum = 0.0, usum = 0.0;
+    for (int i = 0; i <= N; ++i) {
+      double wb = T->gam[G][i] / ((eps + beta[i]) * (eps + beta[i]));
+      wsum += wb;
+      usum += wb * p[i];
+    }
+    return usum / wsum;
+  }
+  /* A point with a negative linear weight (P3 only): the paper is silent.
+   * Reading taken: split the linear weights into a positive and a negative
+   * group with theta = 3 (Shi, Hu and Shu, J. Comput. Phys. 175 (2002)),
+   * form nonlinear weights within each group and combine
+   * u = sigma+ u+ - sigma- u-.  Parity unpinned against the paper. */
+  const double theta = 3.0;
+  double gp[ORC_MAXP], gm[ORC_MAXP], sp = 0.0, sm = 0.0;
+  for (int i = 0; i <= N; ++i) {
+    double g = T->gam[G][i];
+    gp[i] = 0.5 * (g + theta * fabs(g));
+    gm[i] = gp[i] - g;
+    sp += gp[i];
+    sm += gm[i];
+  }
+  double wps = 0.0, ups = 0.0, wms = 0.0, ums = 0.0;
+  for (int i = 0; i <= N; ++i) {
+    double den = (eps + beta[i]) * (eps + beta[i]);
+    double wp = (gp[i] / sp) / den, wm = (gm[i] / sm) / den;
+    wps += wp;
+    ups += wp * p[i];
+    wms += wm;
+    ums += wm * p[i];
+  }
+  return sp * (ups / wps) - sm * (ums / wms);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Problem helpers                                                          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  const orc_config *c;
+  const orc_tables *T;
+  int N, np, nm, nv, nx, ny;
+  double hx, hy;
+} orc_ctx;
+
+static int make_ctx(const orc_config *c, orc_ctx *x) {
+  if (!c || c->dim < 1 || c->dim > 2 || c->order < 1 || c->order > ORC_MAXN || c->nx < 1 || c->ny < 1)
+    return ORC_ERR_ARG;
+  if (c->dim == 1 && c->ny != 1) return ORC_ERR_ARG;
+  if (c->equation != ORC_BURGERS && c->equation != ORC_EULER) return ORC_ERR_ARG;
+  x->c = c;
+  x->T = tables(c->order);
+  if (!x->T) return ORC_ERR_TABLE;
+  x->N = c->order;
+  x->np = c->order + 1;
+  x->nm = c->dim == 1 ? x->np : x->np * x->np;
+  x->nv = c->equation == ORC_BURGERS ? 1 : c->dim + 2;
+  x->nx = c->nx;
+  x->ny = c->ny;
+  x->hx = (c->x1 - c->x0) / c->nx;
+  x->hy = c->dim == 2 ? (c->y1 - c->y0) / c->ny : 1.0;
+  return ORC_OK;
+}
+
+static size_t at(const orc_ctx *x, int v, int q, int j, int i) {
+  return (((size_t)v * x->nm + q) * x->ny + j) * x->nx + i;
+}
+
+/* Modes of cell (i,j), i in [-1,nx], j in [-1,ny], with the boundary
+ * conditions: periodic wrap, or transmissive as an even reflection of the
+ * adjacent interior cell (odd modes in the normal direction change sign). */
+static void fetch_cell(const orc_ctx *x, const double *U, int i, int j, double out[ORC_MAXV][ORC_MAXM]) {
+  int fx = 0, fy = 0;
+  if (i < 0) {
+    if (x->c->bc[0] == ORC_BC_PERIODIC) i += x->nx; else { i = 0; fx = 1; }
+  } else if (i >= x->nx) {
+    if (x->c->bc[1] == ORC_BC_PERIODIC) i -= x->nx; else { i = x->nx - 1; fx = 1; }
+  }
+  if (x->c->dim == 2) {
+    if (j < 0) {
+      if (x->c->bc[2] == ORC_BC_PERIODIC) j += x->ny; else { j = 0; fy = 1; }
+    } else if (j >= x->ny) {
+      if (x->c->bc[3] == ORC_BC_PERIODIC) j -= x->ny; else { j = x->ny - 1; fy = 1; }
+    }
+  }
+  for (int v = 0; v < x->nv; ++v)
+    for (int q = 0; q < x->nm; ++q) {
+      int m = q % x->np, n = q / x->np;
+      double s = U[at(x, v, q, j, i)];
+      if (fx && (m & 1)) s = -s;
+      if (fy && (n & 1)) s = -s;
+      out[v][q] = s;
+    }
+}
+
+/* Value of the cell polynomial at (r,s), given the basis values br[m] =
+ * psi_m(r) and bs[n] = psi_n(s) (1D: bs ignored). */
+static void point_value(const orc_ctx *x, double C[ORC_MAXV][ORC_MAXM], const double *br, const double *bs,
+                        double *u) {
+  for (int v = 0; v < x->nv; ++v) {
+    double acc = 0.0;
+    for (int q = 0; q < x->nm; ++q) {
+      int m = q % x->np, n = q / x->np;
+      double b = br[m];
+      if (x->c->dim == 2) b *= bs[n];
+      acc += C[v][q] * b;
+    }
+    u[v] = acc;
+  }
+}
+
+static double cell_mean_factor(const orc_ctx *x) {
+  /* mean over the cell of the lowest mode's basis function */
+  return x->c->dim == 1 ? x->T->b0[0] : x->T->b0[0] * x->T->b0[0];
+}
+
+/* Physical flux in direction dir (0: x, 1: y) and its spectral radius. */
+static int phys_flux(const orc_ctx *x, int dir, const double *u, double *f) {
+  if (x->c->equation == ORC_BURGERS) {
+    f[0] = 0.5 * u[0] * u[0];
+    return 0;
+  }
+  double g = x->c->gamma;
+  if (x->c->dim == 1) {
+    double rho = u[0], vx = u[1] / rho;
+    double p = (g - 1.0) * (u[2] - 0.5 * rho * vx * vx);
+    f[0] = u[1];
+    f[1] = u[1] * vx + p;
+    f[2] = (u[2] + p) * vx;
+    return !(rho > 0.0 && p > 0.0);
+  }
+  double rho = u[0], vx = u[1] / rho, vy = u[2] / rho;
+  double p = (g - 1.0) * (u[3] - 0.5 * rho * (vx * vx + vy * vy));
+  double vn = dir == 0 ? vx : vy;
+  f[0] = dir == 0 ? u[1] : u[2];
+  f[1] = u[1] * vn + (dir == 0 ? p : 0.0);
+  f[2] = u[2] * vn + (dir == 1 ? p : 0.0);
+  f[3] = (u[3] + p) * vn;
+  return !(rho > 0.0 && p > 0.0);
+}
+
+static double spectral_radius(const orc_ctx *x, int dir, const double *u, int *bad) {
+  if (x->c->equation == ORC_BURGERS) return fabs(u[0]);
+  double g = x->c->gamma, rho = u[0];
+  if (x->c->dim == 1) {
+    double vx = u[1] / rho, p = (g - 1.0) * (u[2] - 0.5 * rho * vx * vx);
+    if (!(rho > 0.0 && p > 0.0)) *bad = 1;
+    return fabs(vx) + sqrt(g * p / rho);
+  }
+  double vx = u[1] / rho, vy = u[2] / rho;
+  double p = (g - 1.0) * (u[3] - 0.5 * rho * (vx * vx + vy * vy));
+  if (!(rho > 0.0 && p > 0.0)) *bad = 1;
+  return fabs(dir == 0 ? vx : vy) + sqrt(g * p / rho);
+}
+
+/* Local Lax-Friedrichs flux between the left/lower state a and right/upper b,
+ * with the dissipation coefficient taken pointwise from the two states. */
+static void llf(const orc_ctx *x, int dir, const double *a, const double *b, double *F, int *bad) {
+  double fa[ORC_MAXV], fb[ORC_MAXV];
+  if (phys_flux(x, dir, a, fa)) *bad = 1;
+  if (phys_flux(x, dir, b, fb)) *bad = 1;
+  double al = fmax(spectral_radius(x, dir, a, bad), spectral_radius(x, dir, b, bad));
+  for (int v = 0; v < x->nv; ++v) F[v] = 0.5 * (fa[v] + fb[v]) - 0.5 * al * (b[v] - a[v]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section 2, weak form: dU/dt = L(U) per cell in the orthonormal modal      */
+/* basis (M = (h/2) I in each direction, so M^{-1} is the factor 2/h).       */
+/* ------------------------------------------------------------------------ */
+
+static int residual_cell(const orc_ctx *x, const double *U, int i, int j, double L[ORC_MAXV][ORC_MAXM]) {
+  const orc_tables *T = x->T;
+  int np = x->np, nv = x->nv, bad = 0;
+  double C[ORC_MAXV][ORC_MAXM], Nb[ORC_MAXV][ORC_MAXM];
+  double a[ORC_MAXV], b[ORC_MAXV], F[ORC_MAXV], f[ORC_MAXV], g[ORC_MAXV];
+  double br[ORC_MAXP], bs[ORC_MAXP], dbr[ORC_MAXP], dbs[ORC_MAXP];
+  fetch_cell(x, U, i, j, C);
+  for (int v = 0; v < nv; ++v)
+    for (int q = 0; q < x->nm; ++q) L[v][q] = 0.0;
+
+  if (x->c->dim == 1) {
+    double sx = 2.0 / x->hx;
+    for (int q = 0; q < np; ++q) { /* volume term: sum_q w_q f(u_q) psi_n'(r_q) */
+      for (int n = 0; n < np; ++n) br[n] = T->bq[n][q];
+      point_value(x, C, br, NULL, a);
+      if (phys_flux(x, 0, a, f)) bad = 1;
+      for (int v = 0; v < nv; ++v)
+        for (int n = 0; n < np; ++n) L[v][n] += sx * T->wq[q] * f[v] * T->dbq[n][q];
+    }
+    /* right face x_{i+1/2} */
+    fetch_cell(x, U, i + 1, j, Nb);
+    point_value(x, C, T->bp, NULL, a);
+    point_value(x, Nb, T->bm, NULL, b);
+    llf(x, 0, a, b, F, &bad);
+    for (int v = 0; v < nv; ++v)
+      for (int n = 0; n < np; ++n) L[v][n] -= sx * F[v] * T->bp[n];
+    /* left face x_{i-1/2} */
+    fetch_cell(x, U, i - 1, j, Nb);
+    point_value(x, Nb, T->bp, NULL, a);
+    point_value(x, C, T->bm, NULL, b);
+    llf(x, 0, a, b, F, &bad);
+    for (int v = 0; v < nv; ++v)
+      for (int n = 0; n < np; ++n) L[v][n] += sx * F[v] * T->bm[n];
+    return bad;
+  }
+
+  double sx = 2.0 / x->hx, sy = 2.0 / x->hy;
+  for (int qx = 0; qx < np; ++qx)
+    for (int qy = 0; qy < np; ++qy) {
+      double w = T->wq[qx] * T->wq[qy];
+      for (int n = 0; n < np; ++n) {
+        br[n] = T->bq[n][qx];
+        dbr[n] = T->dbq[n][qx];
+        bs[n] = T->bq[n][qy];
+        dbs[n] = T->dbq[n][qy];
+      }
+      point_value(x, C, br, bs, a);
+      if (phys_flux(x, 0, a, f)) bad = 1;
+      if (phys_flux(x, 1, a, g)) bad = 1;
+      for (int v = 0; v < nv; ++v)
+        for (int q = 0; q < x->nm; ++q) {
+          int m = q % np, n = q / np;
+          L[v][q] += w * (sx * f[v] * dbr[m] * bs[n] + sy * g[v] * br[m] * dbs[n]);
+        }
+    }
+  double Ce[ORC_MAXV][ORC_MAXM], Cw[ORC_MAXV][ORC_MAXM], Cn[ORC_MAXV][ORC_MAXM], Cs[ORC_MAXV][ORC_MAXM];
+  fetch_cell(x, U, i + 1, j, Ce);
+  fetch_cell(x, U, i - 1, j, Cw);
+  fetch_cell(x, U, i, j + 1, Cn);
+  fetch_cell(x, U, i, j - 1, Cs);
+  for (int e = 0; e < np; ++e) {
+    double w = T->wq[e], bt[ORC_MAXP];
+    for (int n = 0; n < np; ++n) bt[n] = T->bq[n][e]; /* basis at the edge point */
+    /* east face */
+    point_value(x, C, T->bp, bt, a);
+    point_value(x, Ce, T->bm, bt, b);
+    llf(x, 0, a, b, F, &bad);
+    for (int v = 0; v < nv; ++v)
+      for (int q = 0; q < x->nm; ++q) L[v][q] -= sx * w * F[v] * T->bp[q % np] * bt[q / np];
+    /* west face */
+    point_value(x, Cw, T->bp, bt, a);
+    point_value(x, C, T->bm, bt, b);
+    llf(x, 0, a, b, F, &bad);
+    for (int v = 0; v < nv; ++v)
+      for (int q = 0; q < x->nm; ++q) L[v][q] += sx * w * F[v] * T->bm[q % np] * bt[q / np];
+    /* north face */
+    point_value(x, C, bt, T->bp, a);
+    point_value(x, Cn, bt, T->bm, b);
+    llf(x, 1, a, b, F, &bad);
+    for (int v = 0; v < nv; ++v)
+      for (int q = 0; q < x->nm; ++q) L[v][q] -= sy * w * F[v] * bt[q % np] * T->bp[q / np];
+    /* south face */
+    point_value(x, Cs, bt, T->bp, a);
+    point_value(x, C, bt, T->bm, b);
+    llf(x, 1, a, b, F, &bad);
+    for (int v = 0; v < nv; ++v)
+      for (int q = 0; q < x->nm; ++q) L[v][q] += sy * w * F[v] * bt[q % np] * T->bm[q / np];
+  }
+  return bad;
+}
+
+int orc_residual(const orc_config *c, const double *U, double *Lout) {
+  orc_ctx x;
+  int rc = make_ctx(c, &x);
+  if (rc) return rc;
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+  for (int j = 0; j < x.ny; ++j)
+    for (int i = 0; i < x.nx; ++i) {
+      double L[ORC_MAXV][ORC_MAXM];
+      bad |= residual_cell(&x, U, i, j, L);
+      for (int v = 0; v < x.nv; ++v)
+        for (int q = 0; q < x.nm; ++q) Lout[at(&x, v, q, j, i)] = L[v][q];
+    }
+  return bad ? ORC_ERR_NONPHYSICAL : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Troubled-cell indicator: TVB-modified minmod (Cockburn and Shu).          */
+/* ------------------------------------------------------------------------ */
+
+static double minmod3(double a, double b, double c) {
+  if (a > 0.0 && b > 0.0 && c > 0.0) return fmin(a, fmin(b, c));
+  if (a < 0.0 && b < 0.0 && c < 0.0) return fmax(a, fmax(b, c));
+  return 0.0;
+}
+
+/* One test: flagged when the modified minmod does not return a unchanged.
+ * The margin is a lower bound on how far a, dp or dm must move to change
+ * the outcome. */
+static int tvb_test(double a, double dp, double dm, double Mh2, double *margin) {
+  double aa = fabs(a);
+  if (aa <= Mh2) {
+    *margin = Mh2 - aa;
+    return 0;
+  }
+  double m = fmin(aa - Mh2, fmin(fabs(aa - fabs(dp)), fabs(aa - fabs(dm))));
+  *margin = m;
+  return minmod3(a, dp, dm) != a;
+}
+
+static int indicator_cell(const orc_ctx *x, const double *U, int i, int j, double *margin) {
+  double C[ORC_MAXV][ORC_MAXM], Nb[ORC_MAXV][ORC_MAXM], up[ORC_MAXV], um[ORC_MAXV];
+  double mean[ORC_MAXV], mp[ORC_MAXV], mm[ORC_MAXV];
+  double k0 = cell_mean_factor(x);
+  int flag = 0;
+  double mg = INFINITY, t;
+  fetch_cell(x, U, i, j, C);
+  for (int v = 0; v < x->nv; ++v) mean[v] = C[v][0] * k0;
+  int ndir = x->c->dim;
+  for (int dir = 0; dir < ndir; ++dir) {
+    double h = dir == 0 ? x->hx : x->hy, Mh2 = x->c->tvb_M * h * h;
+    /* traces at the face midpoints of this direction */
+    if (dir == 0) {
+      point_value(x, C, x->T->bp, x->T->b0, up);
+      point_value(x, C, x->T->bm, x->T->b0, um);
+      fetch_cell(x, U, i + 1, j, Nb);
+      for (int v = 0; v < x->nv; ++v) mp[v] = Nb[v][0] * k0;
+      fetch_cell(x, U, i - 1, j, Nb);
+      for (int v = 0; v < x->nv; ++v) mm[v] = Nb[v][0] * k0;
+    } else {
+      point_value(x, C, x->T->b0, x->T->bp, up);
+      point_value(x, C, x->T->b0, x->T->bm, um);
+      fetch_cell(x, U, i, j + 1, Nb);
+      for (int v = 0; v < x->nv; ++v) mp[v] = Nb[v][0] * k0;
+      fetch_cell(x, U, i, j - 1, Nb);
+      for (int v = 0; v < x->nv; ++v) mm[v] = Nb[v][0] * k0;
+    }
+    for (int v = 0; v < x->nv; ++v) {
+      double dp = mp[v] - mean[v], dm = mean[v] - mm[v];
+      flag |= tvb_test(up[v] - mean[v], dp, dm, Mh2, &t);
+      mg = fmin(mg, t);
+      flag |= tvb_test(mean[v] - um[v], dp, dm, Mh2, &t);
+      mg = fmin(mg, t);
+    }
+  }
+  *margin = mg;
+  return flag;
+}
+
+int orc_indicator(const orc_config *c, const double *U, uint8_t *flags, double *margin) {
+  orc_ctx x;
+  int rc = make_ctx(c, &x);
+  if (rc) return rc;
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < x.ny; ++j)
+    for (int i = 0; i < x.nx; ++i) {
+      double m;
+      int f = indicator_cell(&x, U, i, j, &m);
+      size_t k = (size_t)j * x.nx + i;
+      if (flags) flags[k] = (uint8_t)f;
+      if (margin) margin[k] = m;
+    }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section 3: CSWENO limiting of one troubled cell (all variables).         */
+/* ------------------------------------------------------------------------ */
+
+/* Mean of psi_n over stencil interval k of the compact stencil, measured in
+ * the reference coordinate of the cell that interval belongs to. */
+static double interval_mean(const orc_tables *T, int k, int n) {
+  int N = T->N;
+  if (k == N) return n == 0 ? T->b0[0] : 0.0; /* whole troubled cell */
+  int sub = k < N ? k : k - N - 1;
+  return T->sub[sub][n];
+}
+
+static void limit_cell(const orc_ctx *x, const double *Uin, int i, int j, double *Uout) {
+  const orc_tables *T = x->T;
+  int N = x->N, np = x->np, ns = 2 * N + 1, ng = T->ng;
+  double eps = x->c->weno_eps;
+  int negw = x->c->negw_mode;
+  if (x->c->dim == 1) {
+    double Cm[ORC_MAXV][ORC_MAXM], C0[ORC_MAXV][ORC_MAXM], Cp[ORC_MAXV][ORC_MAXM];
+    fetch_cell(x, Uin, i - 1, j, Cm);
+    fetch_cell(x, Uin, i, j, C0);
+    fetch_cell(x, Uin, i + 1, j, Cp);
+    for (int v = 0; v < x->nv; ++v) {
+      double a[ORC_MAXS], uG[ORC_MAXG];
+      for (int k = 0; k < ns; ++k) {
+        double (*src)[ORC_MAXM] = k < N ? Cm : (k == N ? C0 : Cp);
+        double s = 0.0;
+        for (int n = 0; n < np; ++n) s += src[v][n] * interval_mean(T, k, n);
+        a[k] = s;
+      }
+      for (int G = 0; G < ng; ++G) uG[G] = orc_weno_point(T, G, a, eps, negw);
+      /* Step 6: the mean is kept, the other moments are re-projected. */
+      for (int n = 1; n < np; ++n) {
+        double s = 0.0;
+        for (int G = 0; G < ng; ++G) s += T->wg[G] * uG[G] * T->bg[n][G];
+        Uout[at(x, v, n, j, i)] = s;
+      }
+    }
+    return;
+  }
+  /* 2D, dimension by dimension: the 3x3 block gives (2N+1)^2 sub-rectangle
+   * means; x-sweeps on every y-interval reconstruct y-interval means at the
+   * x-points, then y-sweeps at every x-point give the tensor point values. */
+  double B[3][3][ORC_MAXV][ORC_MAXM];
+  for (int dy = -1; dy <= 1; ++dy)
+    for (int dx = -1; dx <= 1; ++dx) fetch_cell(x, Uin, i + dx, j + dy, B[dy + 1][dx + 1]);
+  for (int v = 0; v < x->nv; ++v) {
+    double a[ORC_MAXS][ORC_MAXS]; /* [iy][ix] */
+    for (int iy = 0; iy < ns; ++iy)
+      for (int ix = 0; ix < ns; ++ix) {
+        int cx = ix < N ? 0 : (ix == N ? 1 : 2), cy = iy < N ? 0 : (iy == N ? 1 : 2);
+        double s = 0.0;
+        for (int q = 0; q < x->nm; ++q) {
+          int m = q % np, n = q / np;
+          s += B[cy][cx][v][q] * interval_mean(T, ix, m) * interval_mean(T, iy, n);
+        }
+        a[iy][ix] = s;
+      }
+    double vy[ORC_MAXS][ORC_MAXG]; /* y-interval means at the x-points */
+    for (int iy = 0; iy < ns; ++iy)
+      for (int G = 0; G < ng; ++G) vy[iy][G] = orc_weno_point(T, G, a[iy], eps, negw);
+    double u[ORC_MAXG][ORC_MAXG]; /* [G: x-point][H: y-point] */
+    for (int G = 0; G < ng; ++G) {
+      double col[ORC_MAXS];
+      for (int iy = 0; iy < ns; ++iy) col[iy] = vy[iy][G];
+      for (int H = 0; H < ng; ++H) u[G][H] = orc_weno_point(T, H, col, eps, negw);
+    }
+    for (int q = 1; q < x->nm; ++q) {
+      int m = q % np, n = q / np;
+      double s = 0.0;
+      for (int G = 0; G < ng; ++G)
+        for (int H = 0; H < ng; ++H) s += T->wg[G] * T->wg[H] * u[G][H] * T->bg[m][G] * T->bg[n][H];
+      Uout[at(x, v, q, j, i)] = s;
+    }
+  }
+}
+
+/* Indicator + CSWENO with Jacobi semantics: every decision and every
+ * reconstruction reads the state as it was before this call. */
+static int limit_state(const orc_ctx *x, double *U, double *work, uint8_t *flags_out, double *margin_out,
+                       const uint8_t *flags_in) {
+  size_t n = (size_t)x->nv * x->nm * x->ny * x->nx;
+  memcpy(work, U, n * sizeof(double));
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int j = 0; j < x->ny; ++j)
+    for (int i = 0; i < x->nx; ++i) {
+      size_t k = (size_t)j * x->nx + i;
+      double m = INFINITY;
+      int f;
+      if (flags_in) f = flags_in[k] != 0;
+      else if (x->c->indicator == ORC_IND_ALL) f = 1;
+      else f = indicator_cell(x, work, i, j, &m);
+      if (flags_out) flags_out[k] = (uint8_t)f;
+      if (margin_out) margin_out[k] = m;
+      if (f && x->c->limiter == ORC_LIM_CSWENO) limit_cell(x, work, i, j, U);
+    }
+  return ORC_OK;
+}
+
+int orc_limit(const orc_config *c, double *U, uint8_t *flags_out, double *margin_out, const uint8_t *flags_in) {
+  orc_ctx x;
+  int rc = make_ctx(c, &x);
+  if (rc) return rc;
+  size_t n = (size_t)x.nv * x.nm * x.ny * x.nx;
+  double *work = (double *)malloc(n * sizeof(double));
+  if (!work) return ORC_ERR_ARG;
+  rc = limit_state(&x, U, work, flags_out, margin_out, flags_in);
+  free(work);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time step: CFL rule on cell means (the paper states none).                */
+/* ------------------------------------------------------------------------ */
+
+int orc_max_speed(const orc_config *c, const double *U, double *sx, double *sy) {
+  orc_ctx x;
+  int rc = make_ctx(c, &x);
+  if (rc) return rc;
+  double k0 = cell_mean_factor(&x), mx = 0.0, my = 0.0;
+  int bad = 0;
+  for (int j = 0; j < x.ny; ++j)
+    for (int i = 0; i < x.nx; ++i) {
+      double u[ORC_MAXV];
+      for (int v = 0; v < x.nv; ++v) u[v] = U[at(&x, v, 0, j, i)] * k0;
+      mx = fmax(mx, spectral_radius(&x, 0, u, &bad));
+      if (c->dim == 2) my = fmax(my, spectral_radius(&x, 1, u, &bad));
+    }
+  *sx = mx;
+  *sy = my;
+  return bad ? ORC_ERR_NONPHYSICAL : ORC_OK;
+}
+
+int orc_cfl_dt(const orc_config *c, const double *U, double *dt) {
+  double sx, sy;
+  int rc = orc_max_speed(c, U, &sx, &sy);
+  if (rc) return rc;
+  double hx = (c->x1 - c->x0) / c->nx;
+  if (c->dim == 1) {
+    *dt = sx > 0.0 ? c->cfl * hx / sx : INFINITY;
+  } else {
+    double hy = (c->y1 - c->y0) / c->ny;
+    double den = sx / hx + sy / hy;
+    *dt = den > 0.0 ? c->cfl / den : INFINITY;
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Third-order TVD (SSP) Runge-Kutta with the limiter after every stage.     */
+/* ------------------------------------------------------------------------ */
+
+int orc_step(const orc_config *c, double *U, double dt) {
+  orc_ctx x;
+  int rc = make_ctx(c, &x);
+  if (rc) return rc;
+  size_t n = (size_t)x.nv * x.nm * x.ny * x.nx;
+  double *U1 = (double *)malloc(n * sizeof(double)), *U2 = (double *)malloc(n * sizeof(double));
+  double *L = (double *)malloc(n * sizeof(double)), *W = (double *)malloc(n * sizeof(double));
+  if (!U1 || !U2 || !L || !W) {
+    free(U1); free(U2); free(L); free(W);
+    return ORC_ERR_ARG;
+  }
+  int bad = 0;
+  int lim = c->limiter == ORC_LIM_CSWENO;
+  /* stage 1: u1 = u + dt L(u) */
+  if (orc_residual(c, U, L)) bad = 1;
+  for (size_t k = 0; k < n; ++k) U1[k] = U[k] + dt * L[k];
+  if (lim) limit_state(&x, U1, W, NULL, NULL, NULL);
+  /* stage 2: u2 = 3/4 u + 1/4 (u1 + dt L(u1)) */
+  if (orc_residual(c, U1, L)) bad = 1;
+  for (size_t k = 0; k < n; ++k) U2[k] = 0.75 * U[k] + 0.25 * (U1[k] + dt * L[k]);
+  if (lim) limit_state(&x, U2, W, NULL, NULL, NULL);
+  /* stage 3: u = 1/3 u + 2/3 (u2 + dt L(u2)) */
+  if (orc_residual(c, U2, L)) bad = 1;
+  for (size_t k = 0; k < n; ++k) U[k] = U[k] / 3.0 + 2.0 * (U2[k] + dt * L[k]) / 3.0;
+  if (lim) limit_state(&x, U, W, NULL, NULL, NULL);
+  free(U1); free(U2); free(L); free(W);
+  return bad ? ORC_ERR_NONPHYSICAL : ORC_OK;
+}
+
+/* Advance to t_end (or max_steps).  dt_fixed > 0 uses that step, otherwise
+ * the CFL rule; the last step is clipped so that t lands on t_end. */
+int orc_run(const orc_config *c, double *U, double *t, double t_end, double dt_fixed, int32_t max_steps,
+            int32_t *steps, double *dt_log, int32_t dt_log_len) {
+  int s = 0, rc = ORC_OK;
+  while (*t < t_end && s < max_steps) {
+    double dt = dt_fixed;
+    if (!(dt_fixed > 0.0)) {
+      rc = orc_cfl_dt(c, U, &dt);
+      if (rc) break;
+    }
+    int last = 0;
+    if (*t + dt >= t_end) {
+      dt = t_end - *t;
+      last = 1;
+    }
+    rc = orc_step(c, U, dt);
+    if (dt_log && s < dt_log_len) dt_log[s] = dt;
+    ++s;
+    *t = last ? t_end : *t + dt;
+    if (rc) break;
+  }
+  *steps = s;
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Initial data: L2 projection of point values onto the modal basis.        */
+/* pv layout: [v][qy][qx][j][i] at the nodes returned by orc_proj_nodes.     */
+/* ------------------------------------------------------------------------ */
+
+int orc_proj_nodes(int order, double *r, double *w, int32_t *nq) {
+  const orc_tables *T = tables(order);
+  if (!T) return ORC_ERR_ARG;
+  *nq = T->npq;
+  for (int k = 0; k < T->npq; ++k) {
+    if (r) r[k] = T->rpq[k];
+    if (w) w[k] = T->wpq[k];
+  }
+  return ORC_OK;
+}
+
+int orc_project(const orc_config *c, const double *pv, double *U) {
+  orc_ctx x;
+  int rc = make_ctx(c, &x);
+  if (rc) return rc;
+  const orc_tables *T = x.T;
+  int nq = T->npq, nqy = c->dim == 2 ? nq : 1, np = x.np;
+  size_t plane = (size_t)x.nx * x.ny;
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < x.ny; ++j)
+    for (int i = 0; i < x.nx; ++i)
+      for (int v = 0; v < x.nv; ++v)
+        for (int q = 0; q < x.nm; ++q) {
+          int m = q % np, n = q / np;
+          double s = 0.0;
+          for (int b = 0; b < nqy; ++b)
+            for (int a = 0; a < nq; ++a) {
+              double val = pv[(((size_t)v * nqy + b) * nq + a) * plane + (size_t)j * x.nx + i];
+              double wgt = T->wpq[a] * T->bpq[m][a];
+              if (c->dim == 2) wgt *= T->wpq[b] * T->bpq[n][b];
+              s += wgt * val;
+            }
+          U[at(&x, v, q, j, i)] = s;
+        }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Introspection for the pin tests.                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Reconstruction rule, linear weights, the rows T_i[k] giving p_i(x_G) from
+ * the stencil means, and the smoothness quadratic forms B_i (beta_i = a^T B_i a
+ * over the cells of S_i), evaluated through the oracle's own routines. */
+int orc_weno_tables(int order, int32_t *ng, double *rg, double *wg, double *gam, double *rows, double *bmat,
+                    int32_t *split, double *gam_resid) {
+  const orc_tables *T = tables(order);
+  if (!T) return ORC_ERR_ARG;
+  int N = order, ns = 2 * N + 1;
+  *ng = T->ng;
+  *gam_resid = T->gam_resid;
+  for (int G = 0; G < T->ng; ++G) {
+    rg[G] = T->rg[G];
+    wg[G] = T->wg[G];
+    split[G] = T->split[G];
+    for (int i = 0; i <= N; ++i) {
+      gam[G * (N + 1) + i] = T->gam[G][i];
+      for (int k = 0; k < ns; ++k) {
+        double a[ORC_MAXS] = {0}, c[ORC_MAXP];
+        a[k] = 1.0;
+        double v = 0.0;
+        if (k >= i && k <= i + N) {
+          small_poly(T, i, a, c);
+          for (int d = 0; d <= N; ++d) v += c[d] * pow(0.5 * T->rg[G], d);
+        }
+        rows[(G * (N + 1) + i) * ns + k] = v;
+      }
+    }
+  }
+  /* polarisation of the quadratic form: B[k][l] = (b(e_k+e_l) - b(e_k) - b(e_l))/2 */
+  for (int i = 0; i <= N; ++i)
+    for (int k = 0; k <= N; ++k)
+      for (int l = 0; l <= N; ++l) {
+        double a[ORC_MAXS] = {0}, c[ORC_MAXP];
+        a[i + k] += 1.0;
+        a[i + l] += 1.0;
+        small_poly(T, i, a, c);
+        double bkl = smoothness(N, c);
+        double bk, bl;
+        memset(a, 0, sizeof(a));
+        a[i + k] = 1.0;
+        small_poly(T, i, a, c);
+        bk = smoothness(N, c);
+        memset(a, 0, sizeof(a));
+        a[i + l] = 1.0;
+        small_poly(T, i, a, c);
+        bl = smoothness(N, c);
+        double v = (k == l) ? bk : 0.5 * (bkl - bk - bl);
+        bmat[(i * (N + 1) + k) * (N + 1) + l] = v;
+      }
+  return ORC_OK;
+}
+
+/* One WENO reconstruction through the oracle's own routine (pin tests). */
+int orc_weno_eval(int order, int G, const double *a, double eps, int negw_mode, double *out) {
+  const orc_tables *T = tables(order);
+  if (!T || G < 0 || G >= T->ng) return ORC_ERR_ARG;
+  *out = orc_weno_point(T, G, a, eps, negw_mode);
+  return ORC_OK;
+}
+
+int orc_subcell_means(int order, double *sub) {
+  const orc_tables *T = tables(order);
+  if (!T) return ORC_ERR_ARG;
+  for (int k = 0; k < order; ++k)
+    for (int n = 0; n <= order; ++n) sub[k * (order + 1) + n] = T->sub[k][n];
+  return ORC_OK;
+}
+
+int orc_quadrature(int kind, int n, double *x, double *w) {
+  if (n < 2 || n > 12) return ORC_ERR_ARG;
+  if (kind == 0) gauss_rule(n, x, w);
+  else gauss_lobatto_rule(n, x, w);
+  return ORC_OK;
+}
+
+int orc_basis(int n, double r, double *val, double *der) {
+  *val = psi(n, r);
+  *der = dpsi(n, r);
+  return ORC_OK;
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
