@@ -362,10 +362,18 @@ static double smoothness(int N, const double *c) {
   return beta;
 }
 
-static double orc_weno_point(const orc_tables *T, int G, const double *a, double eps, int negw_mode) {
+static double orc_weno_point(const orc_tables *T, int G, const double *a_in, double eps, int negw_mode) {
   int N = T->N;
   double xi = 0.5 * T->rg[G];
   double p[ORC_MAXP], beta[ORC_MAXP];
+  /* The reconstruction is taken on the means relative to the troubled cell's
+   * mean a0: the derivatives in beta do not see the shift, and since the
+   * normalised weights sum to one, u_G = a0 + (reconstruction of a - a0).
+   * This is the same definition, without the cancellation of O(1) means in
+   * the smoothness quadratic forms. */
+  const double a0 = a_in[N];
+  double a[ORC_MAXS];
+  for (int k = 0; k < 2 * N + 1; ++k) a[k] = a_in[k] - a0;
   for (int i = 0; i <= N; ++i) {
     double c[ORC_MAXP];
     small_poly(T, i, a, c);
@@ -383,7 +391,7 @@ static double orc_weno_point(const orc_tables *T, int G, const double *a, double
       wsum += wb;
       usum += wb * p[i];
     }
-    return usum / wsum;
+    return a0 + usum / wsum;
   }
   /* A point with a negative linear weight (P3 only): the paper is silent.
    * Reading taken: split the linear weights into a positive and a negative
@@ -408,7 +416,7 @@ static double orc_weno_point(const orc_tables *T, int G, const double *a, double
     wms += wm;
     ums += wm * p[i];
   }
-  return sp * (ups / wps) - sm * (ums / wms);
+  return a0 + (sp * (ups / wps) - sm * (ums / wms));
 }
 
 /* ------------------------------------------------------------------------ */
