@@ -1,0 +1,162 @@
+/*
+ * dg.h -- C-ABI of libdg.so: the explicit SSP-RK3 Runge-Kutta discontinuous
+ * Galerkin step on uniform Cartesian meshes with the compact subcell WENO
+ * (CSWENO) limiter of Kochi & Ramakrishna, "A compact subcell WENO limiting
+ * strategy using immediate neighbors for Runge-Kutta Discontinuous Galerkin
+ * Methods" (arXiv 1904.11147), running in HIP kernels on gfx950 (MI355X).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Problem (Section 2, first equation and its 2D form in Section 4):
+ *   u_t + f(u)_x (+ g(u)_y) = 0 on [x0,x1] (x [y0,y1]) split into nx (x ny)
+ *   equal cells; Burgers f = g = u^2/2, or the ideal-gas Euler equations with
+ *   conserved variables (rho, rho u, E) in 1D and (rho, rho u, rho v, E) in 2D
+ *   (Examples 7 and 3 of Section 4).
+ * Basis (Section 2, orthonormalised Legendre polynomials and the affine map):
+ *   psi_n(r) = sqrt((2n+1)/2) P_n(r) on r in [-1,1]; in 2D the tensor product
+ *   psi_m(r) psi_n(s) with m, n <= N (Q^N).  A cell mean is U_0 / sqrt(2) in 1D
+ *   and U_00 / 2 in 2D.
+ * State layout ("state" arguments): FP64, structure of arrays
+ *   state[v][q][j][i], i fastest, v < nv (1 Burgers, 3 Euler 1D, 4 Euler 2D),
+ *   q = m + (N+1) n < (N+1)^dim (m the x-degree), j < ny (1 in 1D), i < nx.
+ * Pointers: every pointer named "state", "out", "point_values", "flags",
+ *   "margin" or "flags_override" is DEVICE memory on the device that was
+ *   current when dg_init ran; every other pointer is HOST memory.  The caller
+ *   owns all memory, including the workspace given to dg_init; the library
+ *   allocates no device memory.  Device buffers are only borrowed for the
+ *   duration of a call.
+ * Streams: every call enqueues its work on the stream given to dg_init and
+ *   returns after that stream has finished it, unless stated otherwise.
+ * Errors: every call returns DG_OK (0) or a negative DG_ERR_* code; no
+ *   exception crosses the ABI.  DG_ERR_NONPHYSICAL means a kernel met a
+ *   non-positive density or pressure, or a NaN, since the previous check; the
+ *   results of that call are still written.  dg_strerror names a code.
+ * Threads: a dg_problem may be used by one host thread at a time; distinct
+ *   problems are independent.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DG_ABI_VERSION 1
+
+enum {
+  DG_OK = 0,
+  DG_ERR_INVALID_ARG = -1,
+  DG_ERR_UNSUPPORTED = -2,
+  DG_ERR_WORKSPACE = -3,
+  DG_ERR_HIP = -4,
+  DG_ERR_NONPHYSICAL = -5
+};
+
+enum { DG_EQ_BURGERS = 0, DG_EQ_EULER = 1 };
+enum { DG_BC_PERIODIC = 0, DG_BC_TRANSMISSIVE = 1 };
+enum { DG_LIM_NONE = 0, DG_LIM_CSWENO = 1 };
+enum { DG_IND_TVB = 0, DG_IND_ALL = 1 };
+enum { DG_NEGW_SPLIT = 0, DG_NEGW_RAW = 1 };
+
+typedef struct dg_config {
+  int32_t abi_version; /* DG_ABI_VERSION */
+  int32_t dim;         /* 1 or 2 */
+  int32_t equation;    /* DG_EQ_BURGERS or DG_EQ_EULER */
+  int32_t order;       /* N in 1..3: P^N in 1D, Q^N in 2D */
+  int32_t nx, ny;      /* cells per direction; ny must be 1 in 1D */
+  int32_t bc[4];       /* west, east, south, north: DG_BC_PERIODIC or DG_BC_TRANSMISSIVE
+                          (transmissive = even reflection of the adjacent cell;
+                          periodic sides must come in pairs) */
+  int32_t limiter;     /* DG_LIM_NONE or DG_LIM_CSWENO */
+  int32_t indicator;   /* DG_IND_TVB (TVB-modified minmod) or DG_IND_ALL (every cell) */
+  int32_t negw_mode;   /* P3 points with a negative linear weight: DG_NEGW_SPLIT
+                          (positive/negative split, theta = 3) or DG_NEGW_RAW */
+  int32_t reserved;    /* must be 0 */
+  double gamma;        /* ratio of specific heats (Euler), 1.4 */
+  double x0, x1, y0, y1;
+  double tvb_M;        /* TVB constant M; threshold M h^2 per direction */
+  double weno_eps;     /* epsilon of the nonlinear weights (Section 3, Step 5), 1e-6 */
+  double cfl;          /* CFL number used when dg_step is given dt <= 0 */
+} dg_config;
+
+typedef struct dg_problem dg_problem;
+
+/* Size in bytes of the device workspace dg_init needs for this configuration
+ * (two stage buffers of the state's size plus indicator arrays).  Returns
+ * DG_ERR_INVALID_ARG / DG_ERR_UNSUPPORTED for a bad configuration.  Host only:
+ * touches no device. */
+int dg_workspace_bytes(const dg_config *cfg, size_t *bytes);
+
+/* Creates a problem.  cfg is copied.  workspace: device memory of at least
+ * dg_workspace_bytes bytes, 256-byte aligned, kept by the caller until
+ * dg_destroy.  stream: a hipStream_t (NULL = the null stream).  Uploads the
+ * method's coefficient tables (Section 3, Steps 1-3) to the current device. */
+int dg_init(const dg_config *cfg, void *workspace, size_t workspace_bytes, void *stream, dg_problem **out);
+
+/* Frees the host-side handle (and any captured graph).  NULL is accepted. */
+int dg_destroy(dg_problem *p);
+
+/* Nodes and weights of the rule dg_project integrates with, on the reference
+ * cell [-1,1]: two panels [-1,0] and [0,1], each with an (N+2)-point Gauss
+ * rule, so a jump at a cell face or centre is integrated piecewise.  r_nodes
+ * and weights receive *nq values each (at most 10); either may be NULL. */
+int dg_proj_nodes(const dg_problem *p, double *r_nodes, double *weights, int32_t *nq);
+
+/* L2 projection of initial data onto the modal basis (Section 2, modal form),
+ * for the cell rows j0 .. j0+nrows-1 (1D: j0 = 0, nrows = 1).
+ * point_values: device, [nv][nq][nq][nrows][nx] in 2D ([nv][nq][1][nx] in 1D),
+ * the value at the physical point of reference coordinates
+ * (r_nodes[a], r_nodes[b]) of cell (i, j0+jr) stored at [v][b][a][jr][i].
+ * Writes those rows of state.  Does not limit: call dg_limit afterwards. */
+int dg_project(dg_problem *p, const double *point_values, int32_t j0, int32_t nrows, double *state);
+
+/* Spatial operator L(U) of the semi-discrete scheme (Section 2, eq.
+ * weakFormScheme, modal form with a local Lax-Friedrichs flux evaluated
+ * pointwise at the (N+1)-point Gauss nodes of each face, and the volume term
+ * by (N+1)^dim-point Gauss quadrature).  out has the layout of state and must
+ * not alias it. */
+int dg_residual(dg_problem *p, const double *state, double *out);
+
+/* One application of the limiter (Section 3): troubled-cell indicator, then
+ * CSWENO reconstruction of every troubled cell (compact subcell stencil,
+ * WENO values at the Step-1 points, projection of moments 1..N; the cell mean
+ * is kept bit for bit).  Jacobi semantics: every decision and reconstruction
+ * reads state as it was on entry.  In place on state.
+ * flags (device uint8[ny][nx]) and margin (device double[ny][nx]) receive the
+ * indicator and, for DG_IND_TVB, a lower bound on the change of the tested
+ * quantities that would alter the decision; either may be NULL.
+ * flags_override (device uint8[ny][nx], non-zero = troubled) replaces the
+ * indicator when not NULL.  n_troubled (host) receives the count; may be NULL. */
+int dg_limit(dg_problem *p, double *state, uint8_t *flags, double *margin, const uint8_t *flags_override,
+             int32_t *n_troubled);
+
+/* Time step of the CFL rule on cell means: 1D dt = cfl h / S, 2D
+ * dt = cfl / (S_x/h_x + S_y/h_y), S the largest spectral radius of the mean
+ * states (|u| for Burgers, |u_n| + c for Euler).  *dt is a host double;
+ * infinity when S = 0. */
+int dg_cfl_dt(dg_problem *p, const double *state, double *dt);
+
+/* Advances state from *t towards t_end by third-order TVD Runge-Kutta steps
+ * with the limiter after every stage (Section 3, last paragraph), at most
+ * max_steps steps.  dt > 0: fixed step; dt <= 0: the CFL rule of dg_cfl_dt,
+ * recomputed each step on the device.  The last step is clipped so that t
+ * lands on t_end.  *t (host) is updated; *steps_taken (host, may be NULL)
+ * receives the number of steps.  The step sequence is captured once in a HIP
+ * graph per state pointer and replayed. */
+int dg_step(dg_problem *p, double *state, double *t, double t_end, double dt, int32_t max_steps,
+            int32_t *steps_taken);
+
+/* Status word of the problem: DG_OK or DG_ERR_NONPHYSICAL (sticky until read;
+ * reading clears it).  Synchronises the stream. */
+int dg_status(dg_problem *p);
+
+/* Static string naming a status code. */
+const char *dg_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DG_H */

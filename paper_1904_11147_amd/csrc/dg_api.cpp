@@ -1,0 +1,384 @@
+// C-ABI of libdg.so (declared in include/dg.h): configuration checks,
+// workspace layout, the SSP-RK3 step sequence and its HIP-graph replay.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <mutex>
+#include <new>
+
+#include "dg_internal.h"
+
+using dg::DevScalars;
+using dg::LaunchCtx;
+
+struct dg_problem {
+  dg_config cfg;
+  LaunchCtx ctx;
+  size_t ws_bytes;
+  size_t state_elems;
+  int device;
+  hipStream_t user_stream;
+  hipStream_t capture_stream;
+  hipGraphExec_t graph;
+  const double *graph_state;
+  int graph_cfl;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t scalars, bufA, bufB, flags, margin, list, total;
+};
+
+int num_vars(const dg_config *c) { return c->equation == DG_EQ_BURGERS ? 1 : c->dim + 2; }
+int num_modes(const dg_config *c) { return c->dim == 1 ? c->order + 1 : (c->order + 1) * (c->order + 1); }
+
+int validate(const dg_config *c) {
+  if (!c) return DG_ERR_INVALID_ARG;
+  if (c->abi_version != DG_ABI_VERSION || c->reserved != 0) return DG_ERR_INVALID_ARG;
+  if (c->dim != 1 && c->dim != 2) return DG_ERR_UNSUPPORTED;
+  if (c->equation != DG_EQ_BURGERS && c->equation != DG_EQ_EULER) return DG_ERR_UNSUPPORTED;
+  if (c->order < 1 || c->order > dg::kMaxN) return DG_ERR_UNSUPPORTED;
+  if (c->nx < 1 || c->ny < 1 || (c->dim == 1 && c->ny != 1)) return DG_ERR_INVALID_ARG;
+  for (int k = 0; k < 4; ++k)
+    if (c->bc[k] != DG_BC_PERIODIC && c->bc[k] != DG_BC_TRANSMISSIVE) return DG_ERR_INVALID_ARG;
+  if ((c->bc[0] == DG_BC_PERIODIC) != (c->bc[1] == DG_BC_PERIODIC)) return DG_ERR_INVALID_ARG;
+  if (c->dim == 2 && (c->bc[2] == DG_BC_PERIODIC) != (c->bc[3] == DG_BC_PERIODIC)) return DG_ERR_INVALID_ARG;
+  if (c->limiter != DG_LIM_NONE && c->limiter != DG_LIM_CSWENO) return DG_ERR_INVALID_ARG;
+  if (c->indicator != DG_IND_TVB && c->indicator != DG_IND_ALL) return DG_ERR_UNSUPPORTED;
+  if (c->negw_mode != DG_NEGW_SPLIT && c->negw_mode != DG_NEGW_RAW) return DG_ERR_INVALID_ARG;
+  if (!(c->x1 > c->x0) || (c->dim == 2 && !(c->y1 > c->y0))) return DG_ERR_INVALID_ARG;
+  if (c->equation == DG_EQ_EULER && !(c->gamma > 1.0)) return DG_ERR_INVALID_ARG;
+  if (!(c->tvb_M >= 0.0) || !(c->weno_eps > 0.0) || !(c->cfl > 0.0)) return DG_ERR_INVALID_ARG;
+  const long long cells = (long long)c->nx * c->ny;
+  if (cells > (1ll << 31) - 1) return DG_ERR_UNSUPPORTED;  // cell index stored as int32
+  return DG_OK;
+}
+
+Layout layout(const dg_config *c) {
+  Layout L;
+  const size_t cells = (size_t)c->nx * c->ny;
+  const size_t state = cells * num_vars(c) * num_modes(c) * sizeof(double);
+  size_t off = 0;
+  L.scalars = off;
+  off += align_up(sizeof(DevScalars));
+  L.bufA = off;
+  off += align_up(state);
+  L.bufB = off;
+  off += align_up(state);
+  L.flags = off;
+  off += align_up(cells);
+  L.margin = off;
+  off += align_up(cells * sizeof(double));
+  L.list = off;
+  off += align_up(cells * sizeof(int32_t));
+  L.total = off;
+  return L;
+}
+
+bool g_tables_ready[64];
+std::mutex g_tables_mu;
+
+int ensure_tables(int device) {
+  std::lock_guard<std::mutex> lk(g_tables_mu);
+  if (device < 0 || device >= 64) return DG_ERR_HIP;
+  if (g_tables_ready[device]) return DG_OK;
+  dg::OrderTables tabs[dg::kMaxN + 1];
+  std::memset(tabs, 0, sizeof(tabs));
+  for (int N = 1; N <= dg::kMaxN; ++N) {
+    int rc = dg::build_order_tables(N, &tabs[N]);
+    if (rc) return rc;
+  }
+  int rc = dg::upload_tables(tabs);
+  if (rc) return rc;
+  g_tables_ready[device] = true;
+  return DG_OK;
+}
+
+int hip_ok(hipError_t e) { return e == hipSuccess ? DG_OK : DG_ERR_HIP; }
+
+int sync_status(dg_problem *p, DevScalars *host) {
+  DevScalars tmp;
+  DevScalars *h = host ? host : &tmp;
+  if (hipMemcpyAsync(h, p->ctx.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, p->user_stream) != hipSuccess)
+    return DG_ERR_HIP;
+  if (hipStreamSynchronize(p->user_stream) != hipSuccess) return DG_ERR_HIP;
+  return h->status ? DG_ERR_NONPHYSICAL : DG_OK;
+}
+
+// One SSP-RK3 step with the limiter after every stage (enqueue only).
+int enqueue_step(dg_problem *p, double *state, bool cfl_mode) {
+  LaunchCtx &c = p->ctx;
+  const bool lim = p->cfg.limiter == DG_LIM_CSWENO;
+  int rc = dg::launch_dt_finalize(c);
+  if (!rc) rc = dg::launch_stage(c, 1, state, nullptr, c.bufA, false);
+  if (!rc && lim) rc = dg::launch_limit(c, c.bufA, c.bufB, 0, c.flags, nullptr, nullptr);
+  if (!rc) rc = dg::launch_stage(c, 2, c.bufA, state, c.bufB, false);
+  if (!rc && lim) rc = dg::launch_limit(c, c.bufB, c.bufA, 1, c.flags, nullptr, nullptr);
+  if (!rc) rc = dg::launch_stage(c, 3, c.bufB, state, state, cfl_mode);
+  if (!rc && lim) rc = dg::launch_limit(c, state, c.bufA, 2, c.flags, nullptr, nullptr);
+  return rc;
+}
+
+int build_graph(dg_problem *p, double *state, bool cfl_mode) {
+  if (p->graph) {
+    (void)hipGraphExecDestroy(p->graph);
+    p->graph = nullptr;
+  }
+  if (!p->capture_stream && hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess)
+    return DG_ERR_HIP;
+  void *saved = p->ctx.stream;
+  p->ctx.stream = p->capture_stream;
+  if (hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    p->ctx.stream = saved;
+    return DG_ERR_HIP;
+  }
+  int rc = enqueue_step(p, state, cfl_mode);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(p->capture_stream, &g);
+  p->ctx.stream = saved;
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return DG_ERR_HIP;
+  e = hipGraphInstantiate(&p->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    p->graph = nullptr;
+    return DG_ERR_HIP;
+  }
+  p->graph_state = state;
+  p->graph_cfl = cfl_mode ? 1 : 0;
+  return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dg_workspace_bytes(const dg_config *cfg, size_t *bytes) {
+  if (!bytes) return DG_ERR_INVALID_ARG;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  *bytes = layout(cfg).total;
+  return DG_OK;
+}
+
+int dg_init(const dg_config *cfg, void *workspace, size_t workspace_bytes, void *stream, dg_problem **out) {
+  if (!out) return DG_ERR_INVALID_ARG;
+  *out = nullptr;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  Layout L = layout(cfg);
+  if (!workspace || workspace_bytes < L.total || ((uintptr_t)workspace % kAlign) != 0) return DG_ERR_WORKSPACE;
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return DG_ERR_HIP;
+  rc = ensure_tables(device);
+  if (rc) return rc;
+  dg_problem *p = new (std::nothrow) dg_problem();
+  if (!p) return DG_ERR_INVALID_ARG;
+  p->cfg = *cfg;
+  p->device = device;
+  p->user_stream = (hipStream_t)stream;
+  p->ws_bytes = workspace_bytes;
+  p->state_elems = (size_t)cfg->nx * cfg->ny * num_vars(cfg) * num_modes(cfg);
+  char *ws = (char *)workspace;
+  LaunchCtx &c = p->ctx;
+  c.dim = cfg->dim;
+  c.eq = cfg->equation;
+  c.N = cfg->order;
+  c.nv = num_vars(cfg);
+  c.nm = num_modes(cfg);
+  c.geo.nx = cfg->nx;
+  c.geo.ny = cfg->ny;
+  for (int k = 0; k < 4; ++k) c.geo.bc[k] = cfg->bc[k];
+  if (cfg->dim == 1) {  // the y-direction of a 1D problem is a single periodic row
+    c.geo.bc[2] = c.geo.bc[3] = DG_BC_PERIODIC;
+  }
+  c.geo.hx = (cfg->x1 - cfg->x0) / cfg->nx;
+  c.geo.hy = cfg->dim == 2 ? (cfg->y1 - cfg->y0) / cfg->ny : 1.0;
+  c.geo.rhx = 2.0 / c.geo.hx;
+  c.geo.rhy = 2.0 / c.geo.hy;
+  c.geo.gamma = cfg->gamma;
+  c.geo.tvb_Mx = cfg->tvb_M * c.geo.hx * c.geo.hx;
+  c.geo.tvb_My = cfg->tvb_M * c.geo.hy * c.geo.hy;
+  c.geo.eps = cfg->weno_eps;
+  c.geo.negw_raw = cfg->negw_mode == DG_NEGW_RAW ? 1 : 0;
+  c.stream = stream;
+  c.sc = (DevScalars *)(ws + L.scalars);
+  c.bufA = (double *)(ws + L.bufA);
+  c.bufB = (double *)(ws + L.bufB);
+  c.flags = (uint8_t *)(ws + L.flags);
+  c.margin = (double *)(ws + L.margin);
+  c.list = (int32_t *)(ws + L.list);
+  c.cfl = cfg->cfl;
+  c.limiter = cfg->limiter;
+  c.indicator = cfg->indicator;
+  c.grid_cap = 2048;
+  if (hipMemsetAsync(c.sc, 0, sizeof(DevScalars), p->user_stream) != hipSuccess ||
+      hipStreamSynchronize(p->user_stream) != hipSuccess) {
+    delete p;
+    return DG_ERR_HIP;
+  }
+  *out = p;
+  return DG_OK;
+}
+
+int dg_destroy(dg_problem *p) {
+  if (!p) return DG_OK;
+  if (p->graph) (void)hipGraphExecDestroy(p->graph);
+  if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+  delete p;
+  return DG_OK;
+}
+
+int dg_proj_nodes(const dg_problem *p, double *r_nodes, double *weights, int32_t *nq) {
+  if (!p || !nq) return DG_ERR_INVALID_ARG;
+  dg::OrderTables t;
+  int rc = dg::build_order_tables(p->cfg.order, &t);
+  if (rc) return rc;
+  *nq = t.npq;
+  for (int k = 0; k < t.npq; ++k) {
+    if (r_nodes) r_nodes[k] = t.rpq[k];
+    if (weights) weights[k] = t.wpq[k];
+  }
+  return DG_OK;
+}
+
+int dg_project(dg_problem *p, const double *point_values, int32_t j0, int32_t nrows, double *state) {
+  if (!p || !point_values || !state || nrows < 1 || j0 < 0 || j0 + nrows > p->cfg.ny) return DG_ERR_INVALID_ARG;
+  int rc = dg::launch_project(p->ctx, point_values, j0, nrows, state);
+  if (rc) return rc;
+  return hip_ok(hipStreamSynchronize(p->user_stream));
+}
+
+int dg_residual(dg_problem *p, const double *state, double *out) {
+  if (!p || !state || !out || state == out) return DG_ERR_INVALID_ARG;
+  int rc = dg::launch_residual(p->ctx, state, out);
+  if (rc) return rc;
+  return sync_status(p, nullptr);
+}
+
+int dg_limit(dg_problem *p, double *state, uint8_t *flags, double *margin, const uint8_t *flags_override,
+             int32_t *n_troubled) {
+  if (!p || !state) return DG_ERR_INVALID_ARG;
+  int rc = dg::launch_reset_counts(p->ctx);
+  if (rc) return rc;
+  const LaunchCtx &c = p->ctx;  // with DG_LIM_NONE only the indicator runs
+  rc = dg::launch_limit(c, state, c.bufA, 3, flags, margin, flags_override);
+  if (rc) return rc;
+  DevScalars h;
+  rc = sync_status(p, &h);
+  if (n_troubled) *n_troubled = h.count[3];
+  return rc;
+}
+
+int dg_cfl_dt(dg_problem *p, const double *state, double *dt) {
+  if (!p || !state || !dt) return DG_ERR_INVALID_ARG;
+  int rc = dg::launch_speed(p->ctx, state);
+  if (rc) return rc;
+  DevScalars h;
+  rc = sync_status(p, &h);
+  double sx, sy;
+  std::memcpy(&sx, &h.smax[0], sizeof(double));
+  std::memcpy(&sy, &h.smax[1], sizeof(double));
+  const double inf = std::numeric_limits<double>::infinity();
+  if (p->cfg.dim == 1) {
+    *dt = sx > 0.0 ? p->cfg.cfl * p->ctx.geo.hx / sx : inf;
+  } else {
+    double den = sx / p->ctx.geo.hx + sy / p->ctx.geo.hy;
+    *dt = den > 0.0 ? p->cfg.cfl / den : inf;
+  }
+  return rc;
+}
+
+int dg_step(dg_problem *p, double *state, double *t, double t_end, double dt, int32_t max_steps,
+            int32_t *steps_taken) {
+  if (!p || !state || !t || max_steps < 0) return DG_ERR_INVALID_ARG;
+  if (steps_taken) *steps_taken = 0;
+  if (max_steps == 0 || !(*t < t_end)) return DG_OK;
+  const bool cfl_mode = !(dt > 0.0);
+  // device scalars for this call
+  DevScalars h;
+  int rc = sync_status(p, &h);
+  if (rc == DG_ERR_HIP) return rc;
+  h.t = *t;
+  h.t_end = t_end;
+  h.dt_fixed = cfl_mode ? 0.0 : dt;
+  h.dt = 0.0;
+  h.steps = 0;
+  h.max_steps = max_steps;
+  h.done = 0;
+  h.smax[0] = h.smax[1] = 0ull;
+  for (int k = 0; k < 4; ++k) h.count[k] = 0;
+  if (hipMemcpyAsync(p->ctx.sc, &h, sizeof(DevScalars), hipMemcpyHostToDevice, p->user_stream) != hipSuccess ||
+      hipStreamSynchronize(p->user_stream) != hipSuccess)
+    return DG_ERR_HIP;
+  // the first step's speed; later steps take it from the stage-3 kernel
+  if (cfl_mode && (rc = dg::launch_speed(p->ctx, state)) != DG_OK) return rc;
+  if (!p->graph || p->graph_state != state || p->graph_cfl != (cfl_mode ? 1 : 0)) {
+    rc = build_graph(p, state, cfl_mode);
+    if (rc) return rc;
+  }
+  long remaining = max_steps;
+  long chunk = 8;
+  if (!cfl_mode) {
+    double n = std::ceil((t_end - *t) / dt) + 1.0;
+    if (n < (double)remaining) remaining = (long)n;
+    chunk = remaining;
+  }
+  long launched = 0;
+  while (launched < remaining) {
+    long k = chunk < remaining - launched ? chunk : remaining - launched;
+    for (long s = 0; s < k; ++s)
+      if (hipGraphLaunch(p->graph, p->user_stream) != hipSuccess) return DG_ERR_HIP;
+    launched += k;
+    rc = sync_status(p, &h);
+    if (rc == DG_ERR_HIP) return rc;
+    if (h.done) break;
+    if (chunk < 256) chunk *= 2;
+  }
+  if (!h.done) {
+    // one more finalize pass decides whether t_end or max_steps was reached
+    rc = sync_status(p, &h);
+    if (rc == DG_ERR_HIP) return rc;
+  }
+  *t = h.t;
+  if (steps_taken) *steps_taken = h.steps;
+  return h.status ? DG_ERR_NONPHYSICAL : DG_OK;
+}
+
+int dg_status(dg_problem *p) {
+  if (!p) return DG_ERR_INVALID_ARG;
+  DevScalars h;
+  int rc = sync_status(p, &h);
+  if (rc == DG_ERR_HIP) return rc;
+  if (h.status) {
+    int32_t zero = 0;
+    if (hipMemcpyAsync(&p->ctx.sc->status, &zero, sizeof(zero), hipMemcpyHostToDevice, p->user_stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(p->user_stream) != hipSuccess)
+      return DG_ERR_HIP;
+  }
+  return rc;
+}
+
+const char *dg_strerror(int code) {
+  switch (code) {
+    case DG_OK: return "ok";
+    case DG_ERR_INVALID_ARG: return "invalid argument";
+    case DG_ERR_UNSUPPORTED: return "unsupported configuration";
+    case DG_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case DG_ERR_HIP: return "HIP runtime error";
+    case DG_ERR_NONPHYSICAL: return "non-physical state (density or pressure <= 0, or NaN)";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Internal declarations shared by the host side of libdg (tables, C-ABI) and
+// the HIP kernel translation unit.  Not part of the public ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/dg.h"
+
+namespace dg {
+
+constexpr int kMaxN = 3;
+constexpr int kMaxP = kMaxN + 1;  // N+1
+constexpr int kMaxG = 4;          // reconstruction points per direction
+constexpr int kMaxPQ = 10;        // projection nodes per direction
+
+// Coefficients of one order N, in double, as the kernels read them.
+struct OrderTables {
+  int32_t N, ng, npq, pad;
+  double wq[kMaxP];           // (N+1)-point Gauss weights on [-1,1]
+  double bq[kMaxP][kMaxP];    // psi_n(r_q)            [n][q]
+  double dbq[kMaxP][kMaxP];   // psi_n'(r_q)           [n][q]
+  double bm[kMaxP], bp[kMaxP], b0[kMaxP];  // psi_n(-1), psi_n(+1), psi_n(0)
+  double wg[kMaxG];           // reconstruction-rule weights (sum 2)
+  double bg[kMaxP][kMaxG];    // psi_n(r_G)            [n][G]
+  double T[kMaxG][kMaxP][kMaxP];  // p_i(x_G) = sum_k T[G][i][k] a[i+k]
+  double gam[kMaxG][kMaxP];       // linear weights
+  int32_t split[kMaxG];           // point has a negative linear weight
+  double gpn[kMaxG][kMaxP], gmn[kMaxG][kMaxP];  // split groups, normalised
+  double sp[kMaxG], sm[kMaxG];                  // split group sums
+  double B[kMaxP][kMaxP][kMaxP];  // beta_i = sum_kl B[i][k][l] a[i+k] a[i+l]
+  double sub[kMaxP][kMaxP];       // mean of psi_n over subcell k of [-1,1]  [k][n]
+  double rpq[kMaxPQ], wpq[kMaxPQ];
+  double bpq[kMaxP][kMaxPQ];      // psi_n at the projection nodes
+};
+
+// Builds the tables of order N (1..3) on the host.  Returns 0 or a DG_ERR code.
+int build_order_tables(int N, OrderTables *out);
+
+// Uploads tables of all orders to the current device (kernel TU).
+int upload_tables(const OrderTables *tabs /* [kMaxN+1], index N */);
+
+// Device scalars at the head of the workspace.
+struct DevScalars {
+  unsigned long long smax[2];  // max spectral radius (bits of a positive double), x and y
+  double dt;
+  double t;
+  double t_end;
+  double dt_fixed;
+  int32_t steps;
+  int32_t max_steps;
+  int32_t done;
+  int32_t status;
+  int32_t count[4];  // troubled-cell counts: stage 1..3, standalone limiter
+  int32_t pad[6];
+};
+
+struct Geometry {
+  int32_t nx, ny;
+  int32_t bc[4];
+  double hx, hy;     // cell widths
+  double rhx, rhy;   // 2/hx, 2/hy
+  double gamma;
+  double tvb_Mx, tvb_My;  // M hx^2, M hy^2
+  double eps;
+  int32_t negw_raw;
+  int32_t pad;
+};
+
+struct Kernels;  // launch helpers live in the kernel TU
+
+// Work of one call, described to the kernel TU.
+struct LaunchCtx {
+  int dim, eq, N, nv, nm;
+  Geometry geo;
+  void *stream;
+  DevScalars *sc;        // device
+  double *bufA, *bufB;   // device, state-sized
+  uint8_t *flags;        // device [cells]
+  double *margin;        // device [cells]
+  int32_t *list;         // device [cells]
+  double cfl;
+  int limiter, indicator;
+  int grid_cap;          // blocks for list-driven kernels
+};
+
+// Kernel-TU entry points (host functions, enqueue only).
+int launch_residual(const LaunchCtx &c, const double *u, double *out);
+int launch_stage(const LaunchCtx &c, int stage, const double *u, const double *un, double *out, bool want_speed);
+int launch_limit(const LaunchCtx &c, double *u, double *side, int count_slot, uint8_t *flags, double *margin,
+                 const uint8_t *flags_override);
+int launch_speed(const LaunchCtx &c, const double *u);
+int launch_dt_finalize(const LaunchCtx &c);
+int launch_reset_counts(const LaunchCtx &c);
+int launch_project(const LaunchCtx &c, const double *pv, int j0, int nrows, double *u);
+
+}  // namespace dg

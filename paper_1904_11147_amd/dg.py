@@ -1,0 +1,273 @@
+"""ctypes binding of libdg.so (include/dg.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of the library.  PyTorch provides device memory (the state, the workspace,
+flag and margin buffers) and the stream; the library never allocates.
+
+Raises ``DGLibraryMissing`` when libdg.so is not built -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdg.so")
+
+DG_ABI_VERSION = 1
+DG_OK, DG_ERR_INVALID_ARG, DG_ERR_UNSUPPORTED, DG_ERR_WORKSPACE, DG_ERR_HIP, DG_ERR_NONPHYSICAL = 0, -1, -2, -3, -4, -5
+BURGERS, EULER = 0, 1
+PERIODIC, TRANSMISSIVE = 0, 1
+LIM_NONE, LIM_CSWENO = 0, 1
+IND_TVB, IND_ALL = 0, 1
+NEGW_SPLIT, NEGW_RAW = 0, 1
+
+# every symbol include/dg.h declares
+EXPORTS = ("dg_workspace_bytes", "dg_init", "dg_destroy", "dg_proj_nodes", "dg_project", "dg_residual",
+           "dg_limit", "dg_cfl_dt", "dg_step", "dg_status", "dg_strerror")
+
+
+class DGLibraryMissing(ImportError):
+    pass
+
+
+class DGError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("dim", ctypes.c_int32),
+        ("equation", ctypes.c_int32),
+        ("order", ctypes.c_int32),
+        ("nx", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("bc", ctypes.c_int32 * 4),
+        ("limiter", ctypes.c_int32),
+        ("indicator", ctypes.c_int32),
+        ("negw_mode", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("gamma", ctypes.c_double),
+        ("x0", ctypes.c_double),
+        ("x1", ctypes.c_double),
+        ("y0", ctypes.c_double),
+        ("y1", ctypes.c_double),
+        ("tvb_M", ctypes.c_double),
+        ("weno_eps", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise DGLibraryMissing(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                                   "python paper_1904_11147_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        P, vp = ctypes.POINTER, ctypes.c_void_p
+        i32, d = ctypes.c_int32, ctypes.c_double
+        sigs = {
+            "dg_workspace_bytes": [P(Config), P(ctypes.c_size_t)],
+            "dg_init": [P(Config), vp, ctypes.c_size_t, vp, P(vp)],
+            "dg_destroy": [vp],
+            "dg_proj_nodes": [vp, P(d), P(d), P(i32)],
+            "dg_project": [vp, vp, i32, i32, vp],
+            "dg_residual": [vp, vp, vp],
+            "dg_limit": [vp, vp, vp, vp, vp, P(i32)],
+            "dg_cfl_dt": [vp, vp, P(d)],
+            "dg_step": [vp, vp, P(d), d, d, i32, P(i32)],
+            "dg_status": [vp],
+        }
+        for name, args in sigs.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.dg_strerror.argtypes = [ctypes.c_int]
+        L.dg_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(code):
+    try:
+        return lib().dg_strerror(int(code)).decode()
+    except DGLibraryMissing:
+        return str(code)
+
+
+def make_config(dim=1, equation=BURGERS, order=2, nx=16, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
+                bc=(PERIODIC,) * 4, gamma=1.4, limiter=LIM_CSWENO, indicator=IND_TVB, negw_mode=NEGW_SPLIT,
+                tvb_M=1.0, weno_eps=1e-6, cfl=0.1):
+    c = Config()
+    c.abi_version = DG_ABI_VERSION
+    c.dim, c.equation, c.order = dim, equation, order
+    c.nx, c.ny = nx, (1 if dim == 1 else ny)
+    for k in range(4):
+        c.bc[k] = bc[k]
+    c.limiter, c.indicator, c.negw_mode, c.reserved = limiter, indicator, negw_mode, 0
+    c.gamma, c.x0, c.x1, c.y0, c.y1 = gamma, x0, x1, y0, y1
+    c.tvb_M, c.weno_eps, c.cfl = tvb_M, weno_eps, cfl
+    return c
+
+
+def workspace_bytes(cfg: Config) -> int:
+    n = ctypes.c_size_t()
+    rc = lib().dg_workspace_bytes(ctypes.byref(cfg), ctypes.byref(n))
+    if rc:
+        raise DGError(rc, "dg_workspace_bytes")
+    return n.value
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Problem:
+    """One discretised problem bound to a CUDA/HIP device and stream."""
+
+    def __init__(self, device="cuda", stream=None, **cfg):
+        self.cfg = make_config(**cfg)
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
+        self.dim, self.order = self.cfg.dim, self.cfg.order
+        self.nx, self.ny = self.cfg.nx, self.cfg.ny
+        self.nv = 1 if self.cfg.equation == BURGERS else self.dim + 2
+        self.nm = (self.order + 1) ** self.dim
+        nbytes = workspace_bytes(self.cfg)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            handle = ctypes.c_void_p()
+            rc = lib().dg_init(ctypes.byref(self.cfg), ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle))
+        if rc:
+            raise DGError(rc, "dg_init")
+        self._h = handle
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- shapes -----------------------------------------------------------
+    @property
+    def shape(self):
+        return (self.nv, self.nm, self.ny, self.nx)
+
+    def empty_state(self):
+        return torch.empty(self.shape, dtype=torch.float64, device=self.device)
+
+    def _check_state(self, s):
+        if s.dtype != torch.float64 or tuple(s.shape) != self.shape or not s.is_contiguous() or s.device != self.device:
+            raise ValueError(f"state must be a contiguous float64 {self.shape} tensor on {self.device}")
+
+    def _rc(self, rc, what, allow_nonphysical=False):
+        if rc == DG_ERR_NONPHYSICAL and allow_nonphysical:
+            return rc
+        if rc:
+            raise DGError(rc, what)
+        return rc
+
+    # -- calls --------------------------------------------------------------
+    def proj_nodes(self):
+        r = (ctypes.c_double * 16)()
+        w = (ctypes.c_double * 16)()
+        nq = ctypes.c_int32()
+        self._rc(lib().dg_proj_nodes(self._h, r, w, ctypes.byref(nq)), "dg_proj_nodes")
+        return [r[k] for k in range(nq.value)], [w[k] for k in range(nq.value)]
+
+    def project(self, point_values, state=None, j0=0):
+        """point_values: device float64 [nv][nq][nq][rows][nx] (1D [nv][nq][1][nx])."""
+        state = self.empty_state() if state is None else state
+        self._check_state(state)
+        pv = point_values.contiguous()
+        if pv.dtype != torch.float64 or pv.device != self.device:
+            raise ValueError("point_values must be float64 on the problem's device")
+        nrows = pv.shape[-2] if self.dim == 2 else 1
+        with torch.cuda.stream(self.stream):
+            self._rc(lib().dg_project(self._h, _ptr(pv), int(j0), int(nrows), _ptr(state)), "dg_project")
+        return state
+
+    def residual(self, state, out=None):
+        self._check_state(state)
+        out = torch.empty_like(state) if out is None else out
+        self._rc(lib().dg_residual(self._h, _ptr(state), _ptr(out)), "dg_residual", True)
+        return out
+
+    def limit(self, state, flags_override=None, want_margin=True, allow_nonphysical=True):
+        """In place.  Returns (flags uint8 [ny,nx], margin float64 [ny,nx] or None, n_troubled)."""
+        self._check_state(state)
+        flags = torch.empty((self.ny, self.nx), dtype=torch.uint8, device=self.device)
+        margin = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device) if want_margin else None
+        ovr = None
+        if flags_override is not None:
+            ovr = flags_override.to(device=self.device, dtype=torch.uint8).contiguous()
+        n = ctypes.c_int32()
+        rc = lib().dg_limit(self._h, _ptr(state), _ptr(flags), _ptr(margin), _ptr(ovr), ctypes.byref(n))
+        self._rc(rc, "dg_limit", allow_nonphysical)
+        return flags, margin, n.value
+
+    def cfl_dt(self, state):
+        self._check_state(state)
+        dt = ctypes.c_double()
+        self._rc(lib().dg_cfl_dt(self._h, _ptr(state), ctypes.byref(dt)), "dg_cfl_dt", True)
+        return dt.value
+
+    def step(self, state, t, t_end, dt=0.0, max_steps=2**31 - 1, allow_nonphysical=False):
+        """Advance in place; returns (t, steps)."""
+        self._check_state(state)
+        tt = ctypes.c_double(t)
+        steps = ctypes.c_int32()
+        rc = lib().dg_step(self._h, _ptr(state), ctypes.byref(tt), float(t_end), float(dt), int(max_steps),
+                           ctypes.byref(steps))
+        self._rc(rc, "dg_step", allow_nonphysical)
+        return tt.value, steps.value
+
+    def status(self):
+        return lib().dg_status(self._h)
+
+
+def problem_from_workload(wl, device="cuda", **over):
+    kw = dict(dim=wl.dim, equation=wl.equation, order=wl.order, nx=wl.nx, ny=wl.ny, x0=wl.x0, x1=wl.x1,
+              y0=wl.y0, y1=wl.y1, bc=tuple(wl.bc), gamma=wl.gamma, cfl=wl.cfl)
+    kw.update(over)
+    return Problem(device=device, **kw)
+
+
+def initial_state(prob, wl, limit=True, rows_per_chunk=None):
+    """Project the workload's initial data (evaluated at this library's nodes)
+    and apply the limiter once."""
+    r, _ = prob.proj_nodes()
+    state = prob.empty_state()
+    if prob.dim == 1:
+        pv = torch.from_numpy(wl.point_values(r)).to(prob.device)
+        prob.project(pv, state)
+    else:
+        nq = len(r)
+        per_row = prob.nv * nq * nq * prob.nx * 8
+        rows = rows_per_chunk or max(1, min(prob.ny, (1 << 30) // per_row))
+        for j0 in range(0, prob.ny, rows):
+            nr = min(rows, prob.ny - j0)
+            pv = torch.from_numpy(wl.point_values(r, j0, nr)).to(prob.device)
+            prob.project(pv, state, j0=j0)
+            del pv
+    if limit:
+        prob.limit(state, want_margin=False)
+    return state

@@ -1,0 +1,74 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/dg.h declares, and its host-only calls validate configurations
+(no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dg_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def dg():
+    from paper_1904_11147_amd import dg as D
+    if not os.path.exists(D.LIB_PATH):
+        from paper_1904_11147_amd import build
+        build.build()
+    D.lib()
+    return D
+
+
+def test_exports_every_declared_symbol(dg):
+    names = _declared()
+    assert "dg_step" in names and "dg_limit" in names and "dg_init" in names
+    L = dg.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(dg.EXPORTS)
+
+
+def test_strerror(dg):
+    assert dg.strerror(0) == "ok"
+    assert "non-physical" in dg.strerror(-5)
+    assert dg.strerror(12345) == "unknown error"
+
+
+def test_workspace_bytes_and_validation(dg):
+    c = dg.make_config(dim=2, equation=dg.EULER, order=2, nx=2048, ny=2048, bc=(1, 1, 1, 1))
+    n = dg.workspace_bytes(c)
+    state = 2048 * 2048 * 9 * 4 * 8
+    assert n >= 2 * state and n < 2 * state + 2048 * 2048 * 16
+    bad = [dict(dim=3), dict(order=4), dict(order=0), dict(nx=0), dict(dim=1, ny=5),
+           dict(bc=(0, 1, 0, 0)), dict(limiter=7), dict(indicator=9), dict(negw_mode=5),
+           dict(x0=1.0, x1=0.0), dict(weno_eps=0.0), dict(cfl=-1.0), dict(equation=3)]
+    for kw in bad:
+        base = dict(dim=1, equation=0, order=2, nx=16)
+        base.update(kw)
+        if base["dim"] == 1 and "ny" in kw:
+            c = dg.make_config(**base)
+            c.ny = kw["ny"]
+        else:
+            c = dg.make_config(**base)
+        with pytest.raises(dg.DGError):
+            dg.workspace_bytes(c)
+    c = dg.make_config()
+    c.abi_version = 99
+    with pytest.raises(dg.DGError):
+        dg.workspace_bytes(c)
+
+
+def test_init_rejects_small_workspace_without_touching_device(dg):
+    c = dg.make_config(dim=1, nx=8)
+    h = ctypes.c_void_p()
+    rc = dg.lib().dg_init(ctypes.byref(c), None, 0, None, ctypes.byref(h))
+    assert rc == dg.DG_ERR_WORKSPACE
+    rc = dg.lib().dg_init(ctypes.byref(c), ctypes.c_void_p(4096 + 8), 1 << 30, None, ctypes.byref(h))
+    assert rc == dg.DG_ERR_WORKSPACE  # misaligned
