@@ -156,6 +156,17 @@ int dg_status(dg_problem *p);
 /* Static string naming a status code. */
 const char *dg_strerror(int code);
 
+/* Profiling (measurement only; not part of the method).  While enabled,
+ * dg_step launches its kernels one by one instead of replaying the graph and
+ * brackets every launch with HIP events on the problem's stream.
+ * dg_profile_read returns, per kind, the summed event time in milliseconds
+ * (ms[DG_PROF_KINDS], host) and the number of launches (launches[], host),
+ * plus the number of troubled cells flagged by all limiter passes
+ * (*troubled, host; may be NULL); reset != 0 clears the accumulators. */
+enum { DG_PROF_STAGE1 = 0, DG_PROF_STAGE23 = 1, DG_PROF_LIMITER = 2, DG_PROF_DT = 3, DG_PROF_KINDS = 4 };
+int dg_profile_enable(dg_problem *p, int enable);
+int dg_profile_read(dg_problem *p, double *ms, int64_t *launches, int64_t *troubled, int reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,9 +13,21 @@
 using dg::DevScalars;
 using dg::LaunchCtx;
 
+// Event-bracketed kernel timing for dg_profile_*.
+struct Profiler {
+  static constexpr int kEvents = 512;
+  bool enabled = false;
+  hipEvent_t ev[kEvents] = {};
+  int kind[kEvents / 2] = {};
+  int used = 0;  // events recorded since the last harvest
+  double ms[DG_PROF_KINDS] = {};
+  int64_t n[DG_PROF_KINDS] = {};
+};
+
 struct dg_problem {
   dg_config cfg;
   LaunchCtx ctx;
+  Profiler prof;
   size_t ws_bytes;
   size_t state_elems;
   int device;
@@ -111,17 +123,48 @@ int sync_status(dg_problem *p, DevScalars *host) {
   return h->status ? DG_ERR_NONPHYSICAL : DG_OK;
 }
 
+// Brackets one launch (or a group of launches) with events when profiling.
+struct Timed {
+  dg_problem *p;
+  int slot;
+  Timed(dg_problem *p_, int kind) : p(p_), slot(-1) {
+    Profiler &f = p->prof;
+    if (!f.enabled || f.used + 2 > Profiler::kEvents) return;
+    slot = f.used;
+    f.kind[slot / 2] = kind;
+    f.used += 2;
+    (void)hipEventRecord(f.ev[slot], (hipStream_t)p->ctx.stream);
+  }
+  ~Timed() {
+    if (slot >= 0) (void)hipEventRecord(p->prof.ev[slot + 1], (hipStream_t)p->ctx.stream);
+  }
+};
+
+// Adds the recorded intervals to the accumulators (stream must be idle).
+void harvest(dg_problem *p) {
+  Profiler &f = p->prof;
+  for (int k = 0; k + 1 < f.used; k += 2) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, f.ev[k], f.ev[k + 1]) == hipSuccess) {
+      f.ms[f.kind[k / 2]] += t;
+      f.n[f.kind[k / 2]] += 1;
+    }
+  }
+  f.used = 0;
+}
+
 // One SSP-RK3 step with the limiter after every stage (enqueue only).
 int enqueue_step(dg_problem *p, double *state, bool cfl_mode) {
   LaunchCtx &c = p->ctx;
   const bool lim = p->cfg.limiter == DG_LIM_CSWENO;
-  int rc = dg::launch_dt_finalize(c);
-  if (!rc) rc = dg::launch_stage(c, 1, state, nullptr, c.bufA, false);
-  if (!rc && lim) rc = dg::launch_limit(c, c.bufA, c.bufB, 0, c.flags, nullptr, nullptr);
-  if (!rc) rc = dg::launch_stage(c, 2, c.bufA, state, c.bufB, false);
-  if (!rc && lim) rc = dg::launch_limit(c, c.bufB, c.bufA, 1, c.flags, nullptr, nullptr);
-  if (!rc) rc = dg::launch_stage(c, 3, c.bufB, state, state, cfl_mode);
-  if (!rc && lim) rc = dg::launch_limit(c, state, c.bufA, 2, c.flags, nullptr, nullptr);
+  int rc;
+  { Timed t(p, DG_PROF_DT); rc = dg::launch_dt_finalize(c); }
+  if (!rc) { Timed t(p, DG_PROF_STAGE1); rc = dg::launch_stage(c, 1, state, nullptr, c.bufA, false); }
+  if (!rc && lim) { Timed t(p, DG_PROF_LIMITER); rc = dg::launch_limit(c, c.bufA, c.bufB, 0, c.flags, nullptr, nullptr); }
+  if (!rc) { Timed t(p, DG_PROF_STAGE23); rc = dg::launch_stage(c, 2, c.bufA, state, c.bufB, false); }
+  if (!rc && lim) { Timed t(p, DG_PROF_LIMITER); rc = dg::launch_limit(c, c.bufB, c.bufA, 1, c.flags, nullptr, nullptr); }
+  if (!rc) { Timed t(p, DG_PROF_STAGE23); rc = dg::launch_stage(c, 3, c.bufB, state, state, cfl_mode); }
+  if (!rc && lim) { Timed t(p, DG_PROF_LIMITER); rc = dg::launch_limit(c, state, c.bufA, 2, c.flags, nullptr, nullptr); }
   return rc;
 }
 
@@ -232,6 +275,8 @@ int dg_init(const dg_config *cfg, void *workspace, size_t workspace_bytes, void 
 
 int dg_destroy(dg_problem *p) {
   if (!p) return DG_OK;
+  for (int k = 0; k < Profiler::kEvents; ++k)
+    if (p->prof.ev[k]) (void)hipEventDestroy(p->prof.ev[k]);
   if (p->graph) (void)hipGraphExecDestroy(p->graph);
   if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
   delete p;
@@ -322,7 +367,8 @@ int dg_step(dg_problem *p, double *state, double *t, double t_end, double dt, in
     return DG_ERR_HIP;
   // the first step's speed; later steps take it from the stage-3 kernel
   if (cfl_mode && (rc = dg::launch_speed(p->ctx, state)) != DG_OK) return rc;
-  if (!p->graph || p->graph_state != state || p->graph_cfl != (cfl_mode ? 1 : 0)) {
+  const bool prof = p->prof.enabled;
+  if (!prof && (!p->graph || p->graph_state != state || p->graph_cfl != (cfl_mode ? 1 : 0))) {
     rc = build_graph(p, state, cfl_mode);
     if (rc) return rc;
   }
@@ -336,11 +382,19 @@ int dg_step(dg_problem *p, double *state, double *t, double t_end, double dt, in
   long launched = 0;
   while (launched < remaining) {
     long k = chunk < remaining - launched ? chunk : remaining - launched;
-    for (long s = 0; s < k; ++s)
-      if (hipGraphLaunch(p->graph, p->user_stream) != hipSuccess) return DG_ERR_HIP;
+    if (prof && k > 16) k = 16;  // bounded by the event pool
+    for (long s = 0; s < k; ++s) {
+      if (prof) {
+        rc = enqueue_step(p, state, cfl_mode);
+        if (rc) return rc;
+      } else if (hipGraphLaunch(p->graph, p->user_stream) != hipSuccess) {
+        return DG_ERR_HIP;
+      }
+    }
     launched += k;
     rc = sync_status(p, &h);
     if (rc == DG_ERR_HIP) return rc;
+    if (prof) harvest(p);
     if (h.done) break;
     if (chunk < 256) chunk *= 2;
   }
@@ -367,6 +421,42 @@ int dg_status(dg_problem *p) {
       return DG_ERR_HIP;
   }
   return rc;
+}
+
+int dg_profile_enable(dg_problem *p, int enable) {
+  if (!p) return DG_ERR_INVALID_ARG;
+  if (enable && !p->prof.ev[0]) {
+    for (int k = 0; k < Profiler::kEvents; ++k)
+      if (hipEventCreate(&p->prof.ev[k]) != hipSuccess) return DG_ERR_HIP;
+  }
+  p->prof.enabled = enable != 0;
+  p->prof.used = 0;
+  return DG_OK;
+}
+
+int dg_profile_read(dg_problem *p, double *ms, int64_t *launches, int64_t *troubled, int reset) {
+  if (!p) return DG_ERR_INVALID_ARG;
+  DevScalars h;
+  int rc = sync_status(p, &h);
+  if (rc == DG_ERR_HIP) return rc;
+  harvest(p);
+  for (int k = 0; k < DG_PROF_KINDS; ++k) {
+    if (ms) ms[k] = p->prof.ms[k];
+    if (launches) launches[k] = p->prof.n[k];
+  }
+  if (troubled) *troubled = (int64_t)h.troubled_total;
+  if (reset) {
+    for (int k = 0; k < DG_PROF_KINDS; ++k) {
+      p->prof.ms[k] = 0.0;
+      p->prof.n[k] = 0;
+    }
+    unsigned long long zero = 0;
+    if (hipMemcpyAsync(&p->ctx.sc->troubled_total, &zero, sizeof(zero), hipMemcpyHostToDevice, p->user_stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(p->user_stream) != hipSuccess)
+      return DG_ERR_HIP;
+  }
+  return DG_OK;
 }
 
 const char *dg_strerror(int code) {

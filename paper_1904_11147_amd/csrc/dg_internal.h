@@ -52,7 +52,8 @@ struct DevScalars {
   int32_t done;
   int32_t status;
   int32_t count[4];  // troubled-cell counts: stage 1..3, standalone limiter
-  int32_t pad[6];
+  unsigned long long troubled_total;  // all troubled cells flagged since the last reset
+  int32_t pad[4];
 };
 
 struct Geometry {

@@ -612,7 +612,10 @@ __global__ __launch_bounds__(kBlock) void k_indicator(LimitArgs a) {
     const int lane = __lane_id();
     const int leader = __ffsll((long long)ballot) - 1;
     int base = 0;
-    if (lane == leader) base = atomicAdd(a.count, __popcll(ballot));
+    if (lane == leader) {
+      base = atomicAdd(a.count, __popcll(ballot));
+      atomicAdd(&a.sc->troubled_total, (unsigned long long)__popcll(ballot));
+    }
     base = __shfl(base, leader);
     if (flag) a.list[base + __popcll(ballot & ((1ull << lane) - 1ull))] = (int32_t)cell;
   }

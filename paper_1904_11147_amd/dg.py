@@ -27,7 +27,8 @@ NEGW_SPLIT, NEGW_RAW = 0, 1
 
 # every symbol include/dg.h declares
 EXPORTS = ("dg_workspace_bytes", "dg_init", "dg_destroy", "dg_proj_nodes", "dg_project", "dg_residual",
-           "dg_limit", "dg_cfl_dt", "dg_step", "dg_status", "dg_strerror")
+           "dg_limit", "dg_cfl_dt", "dg_step", "dg_status", "dg_strerror", "dg_profile_enable", "dg_profile_read")
+PROF_KINDS = ("stage1", "stage23", "limiter", "dt")
 
 
 class DGLibraryMissing(ImportError):
@@ -87,6 +88,8 @@ def lib():
             "dg_cfl_dt": [vp, vp, P(d)],
             "dg_step": [vp, vp, P(d), d, d, i32, P(i32)],
             "dg_status": [vp],
+            "dg_profile_enable": [vp, ctypes.c_int],
+            "dg_profile_read": [vp, P(d), P(ctypes.c_int64), P(ctypes.c_int64), ctypes.c_int],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -242,6 +245,17 @@ class Problem:
 
     def status(self):
         return lib().dg_status(self._h)
+
+    def profile(self, enable=True):
+        self._rc(lib().dg_profile_enable(self._h, 1 if enable else 0), "dg_profile_enable")
+
+    def profile_read(self, reset=False):
+        """{kind: (ms, launches)} and the troubled-cell total since the last reset."""
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_int64 * 4)()
+        tr = ctypes.c_int64()
+        self._rc(lib().dg_profile_read(self._h, ms, n, ctypes.byref(tr), 1 if reset else 0), "dg_profile_read")
+        return {k: (ms[i], n[i]) for i, k in enumerate(PROF_KINDS)}, tr.value
 
 
 def problem_from_workload(wl, device="cuda", **over):
