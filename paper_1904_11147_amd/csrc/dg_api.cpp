@@ -264,6 +264,7 @@ int dg_init(const dg_config *cfg, void *workspace, size_t workspace_bytes, void 
   c.limiter = cfg->limiter;
   c.indicator = cfg->indicator;
   c.grid_cap = 2048;
+  c.use_march = 1;
   if (hipMemsetAsync(c.sc, 0, sizeof(DevScalars), p->user_stream) != hipSuccess ||
       hipStreamSynchronize(p->user_stream) != hipSuccess) {
     delete p;

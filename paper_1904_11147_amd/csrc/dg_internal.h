@@ -83,6 +83,7 @@ struct LaunchCtx {
   double cfl;
   int limiter, indicator;
   int grid_cap;          // blocks for list-driven kernels
+  int use_march;         // 2D: marching stage kernel where registers allow
 };
 
 // Kernel-TU entry points (host functions, enqueue only).

@@ -80,7 +80,7 @@ template <> struct Phys<1, 2> {
   static constexpr int NV = 4;
   template <int DIR>
   __device__ static inline void flux(const double *u, double *f, double g, bool &bad) {
-    double rho = u[0], vx = u[1] / rho, vy = u[2] / rho;
+    double rho = u[0], ir = 1.0 / rho, vx = u[1] * ir, vy = u[2] * ir;
     double p = (g - 1.0) * (u[3] - 0.5 * rho * (vx * vx + vy * vy));
     bad |= !(rho > 0.0 && p > 0.0);
     double vn = DIR == 0 ? vx : vy;
@@ -91,10 +91,10 @@ template <> struct Phys<1, 2> {
   }
   template <int DIR>
   __device__ static inline double speed(const double *u, double g, bool &bad) {
-    double rho = u[0], vx = u[1] / rho, vy = u[2] / rho;
+    double rho = u[0], ir = 1.0 / rho, vx = u[1] * ir, vy = u[2] * ir;
     double p = (g - 1.0) * (u[3] - 0.5 * rho * (vx * vx + vy * vy));
     bad |= !(rho > 0.0 && p > 0.0);
-    return fabs(DIR == 0 ? vx : vy) + sqrt(g * p / rho);
+    return fabs(DIR == 0 ? vx : vy) + sqrt(g * p * ir);
   }
 };
 
@@ -431,6 +431,643 @@ __global__ __launch_bounds__(kBlock) void k_stage_2d(StageArgs a) {
       spy = fmax(spy, __shfl_xor(spy, o));
     }
     if (__lane_id() == 0) {
+      atomicMax(&a.sc->smax[0], (unsigned long long)__double_as_longlong(spx));
+      atomicMax(&a.sc->smax[1], (unsigned long long)__double_as_longlong(spy));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Residual + SSP-RK3 stage in 2D, marching form.  One 64-lane wavefront owns a
+// strip of 62 columns (lanes 1..62; lanes 0 and 63 are the strip's x-halo)
+// and walks up a chunk of rows.  Each lane loads its cell's modes once per
+// row (coalesced, 512 B per mode plane); the east trace of the western
+// neighbour and the western face flux of the eastern neighbour move between
+// lanes by shuffles, so every x-face flux is computed once; the flux on the
+// south face of a row is the north-face flux of the row below, carried in
+// registers, so rows are not re-read except one halo row per chunk.
+// ---------------------------------------------------------------------------
+constexpr int kStrip = 62;
+
+// Trace of the cell polynomial on the face x = +-1 (SIDE = +1 / -1) at the N+1
+// edge Gauss points s_e:  sum_n (sum_m U_mn psi_m(+-1)) psi_n(s_e).
+template <int N, int NV, int SIDE>
+__device__ inline void trace_x(const OrderTables &T, const double (&U)[NV][(N + 1) * (N + 1)], double (&out)[NV][N + 1]) {
+  constexpr int NP = N + 1;
+  const double *b = SIDE > 0 ? T.bp : T.bm;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double c[NP];
+#pragma unroll
+    for (int n = 0; n < NP; ++n) {
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < NP; ++m) s += U[v][m + NP * n] * b[m];
+      c[n] = s;
+    }
+#pragma unroll
+    for (int e = 0; e < NP; ++e) {
+      double s = 0.0;
+#pragma unroll
+      for (int n = 0; n < NP; ++n) s += c[n] * T.bq[n][e];
+      out[v][e] = s;
+    }
+  }
+}
+
+// Trace on the face y = +-1 at the edge Gauss points r_e.
+template <int N, int NV, int SIDE>
+__device__ inline void trace_y(const OrderTables &T, const double (&U)[NV][(N + 1) * (N + 1)], double (&out)[NV][N + 1]) {
+  constexpr int NP = N + 1;
+  const double *b = SIDE > 0 ? T.bp : T.bm;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double c[NP];
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+      double s = 0.0;
+#pragma unroll
+      for (int n = 0; n < NP; ++n) s += U[v][m + NP * n] * b[n];
+      c[m] = s;
+    }
+#pragma unroll
+    for (int e = 0; e < NP; ++e) {
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < NP; ++m) s += c[m] * T.bq[m][e];
+      out[v][e] = s;
+    }
+  }
+}
+
+// LLF fluxes at the N+1 points of a face from the lower/left traces a and the
+// upper/right traces b.
+template <int EQ, int N, int NV, int DIR>
+__device__ inline void face_flux(const double (&a)[NV][N + 1], const double (&b)[NV][N + 1], double (&F)[NV][N + 1],
+                                 double g, bool &bad) {
+#pragma unroll
+  for (int e = 0; e < N + 1; ++e) {
+    double ua[NV], ub[NV], f[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      ua[v] = a[v][e];
+      ub[v] = b[v][e];
+    }
+    llf<EQ, 2, DIR>(ua, ub, f, g, bad);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v][e] = f[v];
+  }
+}
+
+// Lift of a face flux into the residual: L -= sgn * scale * psi_normal(+-1) *
+// sum_e w_e F_e psi_tangential(e)  (DIR 0: x-face, normal degree m).
+template <int N, int NV, int DIR, int SIDE>
+__device__ inline void lift(const OrderTables &T, const double (&F)[NV][N + 1], double scale,
+                            double (&L)[NV][(N + 1) * (N + 1)]) {
+  constexpr int NP = N + 1;
+  const double *b = SIDE > 0 ? T.bp : T.bm;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double phi[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int e = 0; e < NP; ++e) s += T.wq[e] * F[v][e] * T.bq[k][e];
+      phi[k] = s * scale;
+    }
+#pragma unroll
+    for (int l = 0; l < NP; ++l)
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        const int q = DIR == 0 ? (l + NP * k) : (k + NP * l);
+        if (SIDE > 0) L[v][q] -= b[l] * phi[k];
+        else L[v][q] += b[l] * phi[k];
+      }
+  }
+}
+
+// South trace (y = -1) of the cell of row j+1 at the edge points, streamed one
+// variable at a time so that no full cell state stays live.
+template <int N, int NV>
+__device__ inline void south_trace_streamed(const OrderTables &T, const double *__restrict__ u, long plane,
+                                            const CellIdx &c, double (&ts)[NV][N + 1]) {
+  constexpr int NP = N + 1, NM = NP * NP;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double m9[NM];
+#pragma unroll
+    for (int q = 0; q < NM; ++q) {
+      const int m = q % NP, n = q / NP;
+      const double s = u[(long)(v * NM + q) * plane + c.idx];
+      m9[q] = ((c.fx && (m & 1)) != (c.fy && (n & 1))) ? -s : s;
+    }
+#pragma unroll
+    for (int e = 0; e < NP; ++e) {
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        double cm = 0.0;
+#pragma unroll
+        for (int n = 0; n < NP; ++n) cm += m9[m + NP * n] * T.bm[n];
+        acc += cm * T.bq[m][e];
+      }
+      ts[v][e] = acc;
+    }
+  }
+}
+
+template <int N, int EQ, int STAGE>
+__global__ __launch_bounds__(64) void k_stage_2d_march(StageArgs a, int rows_per_block) {
+  constexpr int NP = N + 1, NM = NP * NP, NV = Phys<EQ, 2>::NV;
+  using P = Phys<EQ, 2>;
+  const OrderTables &T = c_tab[N];
+  const Geometry &g = a.geo;
+  if (STAGE != 0 && a.sc->done) return;
+  const int lane = threadIdx.x;
+  int col = blockIdx.x * kStrip + lane - 1;
+  if (col > g.nx) col = g.nx;  // lanes past the east ghost column duplicate it
+  const bool owner = lane >= 1 && lane <= kStrip && col < g.nx;
+  const int j0 = blockIdx.y * rows_per_block;
+  const int j1 = min(j0 + rows_per_block, g.ny);
+  const long plane = (long)g.nx * g.ny;
+  const double dt = STAGE == 0 ? 0.0 : a.sc->dt;
+  bool bad = false;
+  double spx = 0.0, spy = 0.0;
+
+  // flux on the south face of row j0 from the halo row below
+  double FS[NV][NP];
+  {
+    double Ub[NV][NM], tn[NV][NP], ts[NV][NP];
+    load_cell<NP, NM, NV, 2>(a.u, plane, map_cell(g, col, j0 - 1), Ub);
+    trace_y<N, NV, +1>(T, Ub, tn);
+    south_trace_streamed<N, NV>(T, a.u, plane, map_cell(g, col, j0), ts);
+    face_flux<EQ, N, NV, 1>(tn, ts, FS, g.gamma, bad);
+  }
+  for (int j = j0; j < j1; ++j) {
+    // Re-derive the table reference every row: the empty asm makes the
+    // pointer opaque, so table values are re-read from the scalar cache
+    // instead of being hoisted out of the loop into registers.
+    const OrderTables *Tp = &c_tab[N];
+    asm volatile("" : "+s"(Tp));
+    const OrderTables &T = *Tp;
+    const CellIdx me = map_cell(g, col, j);
+    double L[NV][NM];
+    double tn[NV][NP];
+    {
+      double U[NV][NM];
+      load_cell<NP, NM, NV, 2>(a.u, plane, me, U);
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int q = 0; q < NM; ++q) L[v][q] = 0.0;
+      // x-faces first: this lane's west face uses the east trace of lane-1
+      {
+        double te[NV][NP], tl[NV][NP];
+        trace_x<N, NV, +1>(T, U, te);
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int e = 0; e < NP; ++e) tl[v][e] = __shfl_up(te[v][e], 1);
+        double tw[NV][NP], FW[NV][NP];
+        trace_x<N, NV, -1>(T, U, tw);
+        face_flux<EQ, N, NV, 0>(tl, tw, FW, g.gamma, bad);
+        lift<N, NV, 0, -1>(T, FW, g.rhx, L);
+        double FE[NV][NP];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int e = 0; e < NP; ++e) FE[v][e] = __shfl_down(FW[v][e], 1);
+        lift<N, NV, 0, +1>(T, FE, g.rhx, L);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      // volume term, one quadrature row qy at a time (not unrolled: keeps
+      // one row of point values and fluxes live)
+#pragma unroll 1
+      for (int qy = 0; qy < NP; ++qy) {
+        double Fx[NV][NP], Gy[NV][NP];
+#pragma unroll
+        for (int qx = 0; qx < NP; ++qx) {
+          double uq[NV], f[NV], gg[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int n = 0; n < NP; ++n) {
+              double t = 0.0;
+#pragma unroll
+              for (int m = 0; m < NP; ++m) t += U[v][m + NP * n] * T.bq[m][qx];
+              s += t * T.bq[n][qy];
+            }
+            uq[v] = s;
+          }
+          P::template flux<0>(uq, f, g.gamma, bad);
+          P::template flux<1>(uq, gg, g.gamma, bad);
+          const double w = T.wq[qx] * T.wq[qy];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            Fx[v][qx] = w * g.rhx * f[v];
+            Gy[v][qx] = w * g.rhy * gg[v];
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int m = 0; m < NP; ++m) {
+            double sa = 0.0, sb = 0.0;
+#pragma unroll
+            for (int qx = 0; qx < NP; ++qx) {
+              sa += Fx[v][qx] * T.dbq[m][qx];
+              sb += Gy[v][qx] * T.bq[m][qx];
+            }
+#pragma unroll
+            for (int n = 0; n < NP; ++n) L[v][m + NP * n] += sa * T.bq[n][qy] + sb * T.dbq[n][qy];
+          }
+      }
+      trace_y<N, NV, +1>(T, U, tn);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // y-faces: south flux carried from the row below; north flux from this
+    // row's north trace and the next row's south trace
+    {
+      double ts[NV][NP], FN[NV][NP];
+      south_trace_streamed<N, NV>(T, a.u, plane, map_cell(g, col, j + 1), ts);
+      face_flux<EQ, N, NV, 1>(tn, ts, FN, g.gamma, bad);
+      lift<N, NV, 1, -1>(T, FS, g.rhy, L);
+      lift<N, NV, 1, +1>(T, FN, g.rhy, L);
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < NP; ++e) FS[v][e] = FN[v][e];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (owner) {
+      const long cell = (long)j * g.nx + col;
+      double mean[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < NM; ++q) {
+          const long k = (long)(v * NM + q) * plane + cell;
+          double r;
+          if (STAGE == 0) r = L[v][q];
+          else if (STAGE == 1) r = a.u[k] + dt * L[v][q];
+          else if (STAGE == 2) r = 0.75 * a.un[k] + 0.25 * (a.u[k] + dt * L[v][q]);
+          else r = a.un[k] / 3.0 + 2.0 * (a.u[k] + dt * L[v][q]) / 3.0;
+          a.out[k] = r;
+          if (q == 0) mean[v] = r * (T.b0[0] * T.b0[0]);
+        }
+      }
+      if (STAGE == 3 && a.want_speed) {
+        spx = fmax(spx, P::template speed<0>(mean, g.gamma, bad));
+        spy = fmax(spy, P::template speed<1>(mean, g.gamma, bad));
+      }
+    }
+  }
+  if (bad) atomicOr(&a.sc->status, 1);
+  if (STAGE == 3 && a.want_speed) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      spx = fmax(spx, __shfl_xor(spx, o));
+      spy = fmax(spy, __shfl_xor(spy, o));
+    }
+    if (lane == 0) {
+      atomicMax(&a.sc->smax[0], (unsigned long long)__double_as_longlong(spx));
+      atomicMax(&a.sc->smax[1], (unsigned long long)__double_as_longlong(spy));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2D Euler stage kernel with two lanes per cell.  Lane 2s+h of a wavefront
+// owns conserved variables 2h and 2h+1 of the cell in slot s, i.e.
+// (rho, rho u) for h = 0 and (rho v, E) for h = 1, and the matching modes of
+// the residual, which halves the per-lane state.  Every linear step (traces,
+// quadrature values, contractions, lifts) works on the lane's own two
+// variables; at each flux point the two lanes swap their point values
+// (shfl_xor 1), both form the primitive variables, and each evaluates only
+// its own flux components.  The wavefront marches up a chunk of rows over a
+// strip of 30 columns (slots 1..30; slots 0 and 31 are the x-halo).
+// ---------------------------------------------------------------------------
+constexpr int kPairStrip = 30;
+
+struct EulerPrim {
+  double ir, vx, vy, p;
+};
+
+// 1/x from the hardware estimate refined by two Newton steps (about 1 ulp for
+// normal x; the density is checked separately).
+__device__ inline double fast_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// sqrt(a) for a > 0 from the reciprocal square-root estimate and Newton
+// (Goldschmidt) refinement, about 1 ulp; a <= 0 or NaN gives NaN.
+__device__ inline double fast_sqrt(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  double gq = a * y, h = 0.5 * y;
+  double r = fma(-gq, h, 0.5);
+  gq = fma(gq, r, gq);
+  h = fma(h, r, h);
+  r = fma(-gq, h, 0.5);
+  gq = fma(gq, r, gq);
+  h = fma(h, r, h);
+  const double d = fma(-gq, gq, a);
+  gq = fma(d, h, gq);
+  return a > 0.0 ? gq : (a == 0.0 ? 0.0 : __builtin_nan(""));
+}
+
+// Full state (rho, mx, my, E) from the lane's pair (a0, a1) and its partner's.
+__device__ inline EulerPrim euler_prim(double a0, double a1, double b0, double b1, bool h1, double g, bool &bad) {
+  const double rho = h1 ? b0 : a0, mx = h1 ? b1 : a1, my = h1 ? a0 : b0, E = h1 ? a1 : b1;
+  EulerPrim s;
+  s.ir = fast_rcp(rho);
+  s.vx = mx * s.ir;
+  s.vy = my * s.ir;
+  s.p = (g - 1.0) * (E - 0.5 * rho * (s.vx * s.vx + s.vy * s.vy));
+  bad |= !(rho > 0.0 && s.p > 0.0);
+  return s;
+}
+
+// Own flux components in direction DIR: f = w vx + (0, p, 0, p vx),
+// g = w vy + (0, 0, p, p vy), for the lane's variables 2h, 2h+1.
+template <int DIR>
+__device__ inline void euler_flux_pair(const EulerPrim &s, double a0, double a1, bool h1, double &f0, double &f1) {
+  const double vn = DIR == 0 ? s.vx : s.vy;
+  if (DIR == 0) {
+    f0 = a0 * vn;
+    f1 = a1 * vn + (h1 ? s.p * vn : s.p);
+  } else {
+    f0 = a0 * vn + (h1 ? s.p : 0.0);
+    f1 = a1 * vn + (h1 ? s.p * vn : 0.0);
+  }
+}
+
+template <int DIR>
+__device__ inline double euler_speed(const EulerPrim &s, double rho, double g) {
+  return fabs(DIR == 0 ? s.vx : s.vy) + fast_sqrt(g * s.p * s.ir);
+}
+
+// LLF flux at one face point for the lane's two variables: left/lower state
+// (l0, l1) and right/upper (r0, r1) are the lane's own components.
+template <int DIR>
+__device__ inline void llf_pair(double l0, double l1, double r0, double r1, bool h1, double g, double &F0, double &F1,
+                                bool &bad) {
+  const double pl0 = __shfl_xor(l0, 1), pl1 = __shfl_xor(l1, 1);
+  const double pr0 = __shfl_xor(r0, 1), pr1 = __shfl_xor(r1, 1);
+  const EulerPrim sl = euler_prim(l0, l1, pl0, pl1, h1, g, bad);
+  const EulerPrim sr = euler_prim(r0, r1, pr0, pr1, h1, g, bad);
+  const double al = fmax(euler_speed<DIR>(sl, 0.0, g), euler_speed<DIR>(sr, 0.0, g));
+  double fl0, fl1, fr0, fr1;
+  euler_flux_pair<DIR>(sl, l0, l1, h1, fl0, fl1);
+  euler_flux_pair<DIR>(sr, r0, r1, h1, fr0, fr1);
+  F0 = 0.5 * (fl0 + fr0) - 0.5 * al * (r0 - l0);
+  F1 = 0.5 * (fl1 + fr1) - 0.5 * al * (r1 - l1);
+}
+
+template <int N, int STAGE>
+__global__ __launch_bounds__(64, 2) void k_stage_2d_euler_pair(StageArgs a, int rows_per_block) {
+  constexpr int NP = N + 1, NM = NP * NP;
+  // the current row's modes of this lane's two variables, [k*NM+q][lane]
+  __shared__ double row[2 * NM * 64];
+  const OrderTables &T = c_tab[N];
+  const Geometry &g = a.geo;
+  if (STAGE != 0 && a.sc->done) return;
+  const int lane = threadIdx.x, slot = lane >> 1, half = lane & 1;
+  const bool h1 = half != 0;
+  int col = blockIdx.x * kPairStrip + slot - 1;
+  if (col > g.nx) col = g.nx;
+  const bool owner = slot >= 1 && slot <= kPairStrip && col < g.nx;
+  const int j0 = blockIdx.y * rows_per_block;
+  const int j1 = min(j0 + rows_per_block, g.ny);
+  const long plane = (long)g.nx * g.ny;
+  const double dt = STAGE == 0 ? 0.0 : a.sc->dt;
+  const int v0 = 2 * half;  // first owned variable
+  bool bad = false;
+  double spx = 0.0, spy = 0.0;
+
+  // lane's two variables start at plane (2 half) * NM; offsets fit 32 bits
+  const double *ubase = a.u + (size_t)v0 * NM * plane;
+  auto load2 = [&](const CellIdx &c, double (&U)[2][NM]) {
+    const unsigned idx = (unsigned)c.idx;
+    const unsigned long long sx = c.fx ? 0x8000000000000000ull : 0ull, sy = c.fy ? 0x8000000000000000ull : 0ull;
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int q = 0; q < NM; ++q) {
+        const int m = q % NP, n = q / NP;
+        const double *pl = ubase + (size_t)(k * NM + q) * plane;
+        double s = pl[idx];
+        if ((m & 1) || (n & 1)) {
+          const unsigned long long msk = ((m & 1) ? sx : 0ull) ^ ((n & 1) ? sy : 0ull);
+          s = __longlong_as_double(__double_as_longlong(s) ^ (long long)msk);
+        }
+        U[k][q] = s;
+      }
+  };
+  auto rd = [&](int k, int q) -> double { return row[(k * NM + q) * 64 + lane]; };
+  // trace of the two own variables on a face (dirf 0: x-face, 1: y-face)
+  // from modes given by a getter
+  auto trace2 = [&](auto get, const double *b, int dirf, double (&out)[2][NP]) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      double c[NP];
+#pragma unroll
+      for (int t = 0; t < NP; ++t) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < NP; ++l) s += get(k, dirf == 0 ? (l + NP * t) : (t + NP * l)) * b[l];
+        c[t] = s;
+      }
+#pragma unroll
+      for (int e = 0; e < NP; ++e) {
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < NP; ++t) s += c[t] * T.bq[t][e];
+        out[k][e] = s;
+      }
+    }
+  };
+  auto lift2 = [&](const double (&F)[2][NP], const double *b, int dirf, int side, double scale, double (&L)[2][NM]) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      double phi[NP];
+#pragma unroll
+      for (int t = 0; t < NP; ++t) {
+        double s = 0.0;
+#pragma unroll
+        for (int e = 0; e < NP; ++e) s += T.wq[e] * F[k][e] * T.bq[t][e];
+        phi[t] = s * scale;
+      }
+#pragma unroll
+      for (int l = 0; l < NP; ++l)
+#pragma unroll
+        for (int t = 0; t < NP; ++t) {
+          const int q = dirf == 0 ? (l + NP * t) : (t + NP * l);
+          if (side > 0) L[k][q] -= b[l] * phi[t];
+          else L[k][q] += b[l] * phi[t];
+        }
+    }
+  };
+
+  // south-face flux of row j0 from the halo row below; row j0 into LDS
+  double FS[2][NP];
+  {
+    double P[2][NM], tn[2][NP], ts[2][NP];
+    load2(map_cell(g, col, j0 - 1), P);
+    trace2([&](int k, int q) { return P[k][q]; }, T.bp, 1, tn);
+    load2(map_cell(g, col, j0), P);
+    trace2([&](int k, int q) { return P[k][q]; }, T.bm, 1, ts);
+#pragma unroll
+    for (int e = 0; e < NP; ++e) llf_pair<1>(tn[0][e], tn[1][e], ts[0][e], ts[1][e], h1, g.gamma, FS[0][e], FS[1][e], bad);
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int q = 0; q < NM; ++q) row[(k * NM + q) * 64 + lane] = P[k][q];
+  }
+  for (int j = j0; j < j1; ++j) {
+    // next row in flight while this row is computed
+    double P[2][NM];
+    load2(map_cell(g, col, j + 1), P);
+    const long cellj = (long)j * g.nx + col;
+    double L[2][NM];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int q = 0; q < NM; ++q) L[k][q] = 0.0;
+    // x-faces: west face from slot-1's east trace; east flux from slot+1
+    {
+      double te[2][NP], tw[2][NP], FW[2][NP], FE[2][NP];
+      trace2(rd, T.bp, 0, te);
+      trace2(rd, T.bm, 0, tw);
+#pragma unroll
+      for (int e = 0; e < NP; ++e) {
+        const double l0 = __shfl_up(te[0][e], 2), l1 = __shfl_up(te[1][e], 2);
+        llf_pair<0>(l0, l1, tw[0][e], tw[1][e], h1, g.gamma, FW[0][e], FW[1][e], bad);
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int e = 0; e < NP; ++e) FE[k][e] = __shfl_down(FW[k][e], 2);
+      lift2(FW, T.bm, 0, -1, g.rhx, L);
+      lift2(FE, T.bp, 0, +1, g.rhx, L);
+    }
+    // volume term
+#pragma unroll 1
+    for (int qy = 0; qy < NP; ++qy) {
+      double Fx[2][NP], Gy[2][NP];
+#pragma unroll
+      for (int qx = 0; qx < NP; ++qx) {
+        double uq[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          double s = 0.0;
+#pragma unroll
+          for (int n = 0; n < NP; ++n) {
+            double t = 0.0;
+#pragma unroll
+            for (int m = 0; m < NP; ++m) t += rd(k, m + NP * n) * T.bq[m][qx];
+            s += t * T.bq[n][qy];
+          }
+          uq[k] = s;
+        }
+        const double b0 = __shfl_xor(uq[0], 1), b1 = __shfl_xor(uq[1], 1);
+        const EulerPrim st = euler_prim(uq[0], uq[1], b0, b1, h1, g.gamma, bad);
+        double f0, f1, g0, g1;
+        euler_flux_pair<0>(st, uq[0], uq[1], h1, f0, f1);
+        euler_flux_pair<1>(st, uq[0], uq[1], h1, g0, g1);
+        const double w = T.wq[qx] * T.wq[qy];
+        Fx[0][qx] = w * g.rhx * f0;
+        Fx[1][qx] = w * g.rhx * f1;
+        Gy[0][qx] = w * g.rhy * g0;
+        Gy[1][qx] = w * g.rhy * g1;
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+          double sa = 0.0, sb = 0.0;
+#pragma unroll
+          for (int qx = 0; qx < NP; ++qx) {
+            sa += Fx[k][qx] * T.dbq[m][qx];
+            sb += Gy[k][qx] * T.bq[m][qx];
+          }
+#pragma unroll
+          for (int n = 0; n < NP; ++n) L[k][m + NP * n] += sa * T.bq[n][qy] + sb * T.dbq[n][qy];
+        }
+    }
+    // this row's u^n in flight during the y-face work
+    double Un[2][NM];
+    if (STAGE >= 2) {
+      __builtin_amdgcn_sched_barrier(0);
+      const double *nbase = a.un + (size_t)v0 * NM * plane;
+      const unsigned idx = (unsigned)(owner ? cellj : 0);
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int q = 0; q < NM; ++q) Un[k][q] = nbase[(size_t)(k * NM + q) * plane + idx];
+    }
+    // y-faces: carried south flux, north flux from the next row's south trace
+    {
+      double tn[2][NP], ts[2][NP], FN[2][NP];
+      trace2(rd, T.bp, 1, tn);
+      trace2([&](int k, int q) { return P[k][q]; }, T.bm, 1, ts);
+#pragma unroll
+      for (int e = 0; e < NP; ++e) llf_pair<1>(tn[0][e], tn[1][e], ts[0][e], ts[1][e], h1, g.gamma, FN[0][e], FN[1][e], bad);
+      lift2(FS, T.bm, 1, -1, g.rhy, L);
+      lift2(FN, T.bp, 1, +1, g.rhy, L);
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int e = 0; e < NP; ++e) FS[k][e] = FN[k][e];
+    }
+    // RK stage combination (u^(s) of this row from LDS)
+    double m0 = 0.0, m1 = 0.0;
+    {
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int q = 0; q < NM; ++q) {
+          const long kk = (long)((v0 + k) * NM + q) * plane + cellj;
+          double r = 0.0;
+          if (owner) {
+            const double uo = rd(k, q);
+            if (STAGE == 0) r = L[k][q];
+            else if (STAGE == 1) r = uo + dt * L[k][q];
+            else if (STAGE == 2) r = 0.75 * Un[k][q] + 0.25 * (uo + dt * L[k][q]);
+            else r = Un[k][q] / 3.0 + 2.0 * (uo + dt * L[k][q]) / 3.0;
+            a.out[kk] = r;
+          }
+          if (q == 0) (k == 0 ? m0 : m1) = r * (T.b0[0] * T.b0[0]);
+        }
+    }
+    if (STAGE == 3 && a.want_speed) {
+      const double p0 = __shfl_xor(m0, 1), p1 = __shfl_xor(m1, 1);
+      if (owner) {
+        const EulerPrim s = euler_prim(m0, m1, p0, p1, h1, g.gamma, bad);
+        spx = fmax(spx, euler_speed<0>(s, 0.0, g.gamma));
+        spy = fmax(spy, euler_speed<1>(s, 0.0, g.gamma));
+      }
+    }
+    // the next row becomes the current one (each lane touches only its own slots)
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int q = 0; q < NM; ++q) row[(k * NM + q) * 64 + lane] = P[k][q];
+  }
+  if (bad) atomicOr(&a.sc->status, 1);
+  if (STAGE == 3 && a.want_speed) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      spx = fmax(spx, __shfl_xor(spx, o));
+      spy = fmax(spy, __shfl_xor(spy, o));
+    }
+    if (lane == 0) {
       atomicMax(&a.sc->smax[0], (unsigned long long)__double_as_longlong(spx));
       atomicMax(&a.sc->smax[1], (unsigned long long)__double_as_longlong(spy));
     }
@@ -891,8 +1528,29 @@ dim3 cell_grid(const LaunchCtx &c, dim3 &block) {
   return dim3((c.geo.nx + 63) / 64, (c.geo.ny + block.y - 1) / block.y, 1);
 }
 
+// Rows per marching wavefront: enough waves to fill 256 CUs several times.
+int march_rows(const LaunchCtx &c, int strip = kStrip) {
+  const long strips = (c.geo.nx + strip - 1) / strip;
+  int rows = 32;
+  while (rows > 4 && strips * ((c.geo.ny + rows - 1) / rows) < 8192) rows /= 2;
+  return rows;
+}
+
 template <int D, int E, int NN, int STAGE>
 void stage_launch(const LaunchCtx &c, const StageArgs &a) {
+  constexpr bool march = D == 2 && E == 0;
+  if (D == 2 && E == 1 && c.use_march) {
+    const int rows = march_rows(c, kPairStrip);
+    dim3 grid((c.geo.nx + kPairStrip - 1) / kPairStrip, (c.geo.ny + rows - 1) / rows, 1);
+    hipLaunchKernelGGL((k_stage_2d_euler_pair<NN, STAGE>), grid, dim3(64), 0, S(c), a, rows);
+    return;
+  }
+  if (D == 2 && march && c.use_march) {
+    const int rows = march_rows(c);
+    dim3 grid((c.geo.nx + kStrip - 1) / kStrip, (c.geo.ny + rows - 1) / rows, 1);
+    hipLaunchKernelGGL((k_stage_2d_march<NN, E, STAGE>), grid, dim3(64), 0, S(c), a, rows);
+    return;
+  }
   dim3 block, grid = cell_grid(c, block);
   if (D == 1) hipLaunchKernelGGL((k_stage_1d<NN, E, STAGE>), grid, block, 0, S(c), a);
   else hipLaunchKernelGGL((k_stage_2d<NN, E, STAGE>), grid, block, 0, S(c), a);
