@@ -58,7 +58,7 @@ enum {
 enum { DG_EQ_BURGERS = 0, DG_EQ_EULER = 1 };
 enum { DG_BC_PERIODIC = 0, DG_BC_TRANSMISSIVE = 1 };
 enum { DG_LIM_NONE = 0, DG_LIM_CSWENO = 1 };
-enum { DG_IND_TVB = 0, DG_IND_ALL = 1 };
+enum { DG_IND_TVB = 0, DG_IND_ALL = 1, DG_IND_LEARNED = 2 };
 enum { DG_NEGW_SPLIT = 0, DG_NEGW_RAW = 1 };
 
 typedef struct dg_config {
@@ -71,7 +71,9 @@ typedef struct dg_config {
                           (transmissive = even reflection of the adjacent cell;
                           periodic sides must come in pairs) */
   int32_t limiter;     /* DG_LIM_NONE or DG_LIM_CSWENO */
-  int32_t indicator;   /* DG_IND_TVB (TVB-modified minmod) or DG_IND_ALL (every cell) */
+  int32_t indicator;   /* DG_IND_TVB (TVB-modified minmod), DG_IND_ALL (every cell), or
+                          DG_IND_LEARNED (2D only: the MLP of dg_set_learned with the TVB
+                          decision in its uncertain band) */
   int32_t negw_mode;   /* P3 points with a negative linear weight: DG_NEGW_SPLIT
                           (positive/negative split, theta = 3) or DG_NEGW_RAW */
   int32_t reserved;    /* must be 0 */
@@ -166,6 +168,53 @@ const char *dg_strerror(int code);
 enum { DG_PROF_STAGE1 = 0, DG_PROF_STAGE23 = 1, DG_PROF_LIMITER = 2, DG_PROF_DT = 3, DG_PROF_KINDS = 4 };
 int dg_profile_enable(dg_problem *p, int enable);
 int dg_profile_read(dg_problem *p, double *ms, int64_t *launches, int64_t *troubled, int reset);
+
+/* ---- Learned troubled-cell indicator (not in the paper: its indicator is
+ * KXRCF, Sec. 3; the workload asks for a small MLP trained on the flags and
+ * limited/unlimited pairs of the plain method, with TVB as the fallback).
+ *
+ * Features of a cell, per conserved variable v, in the order of the cells
+ * C, W, E, S, N and their (N+1)^2 modes: the five mode-0 entries minus the
+ * centre's mode 0, all divided by max(max |entry|, M hx^2).  F = 5 (N+1)^2 nv
+ * features (180 for 2D Euler Q2), zero-padded to KP = 16 ceil(F/16) in the
+ * bf16 layout.  Network: 64 ReLU units, 64 ReLU units, one sigmoid output;
+ * bf16 weights, fp32 biases and accumulation (BF16 MFMA).
+ * Master parameters (fp32, host or device order W1 [64][F] | W2 [64][64] |
+ * w3 [64] | b1 [64] | b2 [64] | b3); bf16 weight buffer W1 [64][KP] |
+ * W2 [64][64] | W2^T [64][64] | w3 [64].  All buffers below are DEVICE memory
+ * owned by the caller; "stream" is a hipStream_t. */
+
+/* Sizes for F features: padded width, master and bf16 element counts (host). */
+int dg_mlp_layout(int32_t features, int32_t *padded, int64_t *n_master, int64_t *n_bf16);
+
+/* Features of every cell of a 2D state: f32 [cells][F] and/or bf16 [cells][KP]
+ * (either may be NULL). */
+int dg_mlp_features(dg_problem *p, const double *state, float *f32, uint16_t *bf16);
+
+/* prob[i] = sigmoid(network(x[i])) for n rows of x (bf16 [n][KP]). */
+int dg_mlp_forward(const uint16_t *x, int32_t n, int32_t features, const uint16_t *w_bf16, const float *master,
+                   float *prob, void *stream);
+
+/* Adds to grad (fp32, master order, zeroed by the caller or by dg_mlp_adam)
+ * the gradient of the mean weighted binary cross-entropy
+ * (1/n) sum_i wgt[i] (log(1 + e^z_i) - y[i] z_i) and adds that loss to *loss
+ * (device float).  dh1: bf16 scratch of n*64 elements. */
+int dg_mlp_gradient(const uint16_t *x, const float *y, const float *wgt, int32_t n, int32_t features,
+                    const uint16_t *w_bf16, const float *master, float *grad, uint16_t *dh1, float *loss,
+                    void *stream);
+
+/* One Adam step (beta 0.9, 0.999, eps 1e-8, bias-corrected with step >= 1) on
+ * master from grad, then grad := 0 and the bf16 buffer refreshed; step = 0
+ * only refreshes the bf16 buffer from master. */
+int dg_mlp_adam(float *master, float *adam_m, float *adam_v, float *grad, uint16_t *w_bf16, int32_t features,
+                float lr, int32_t step, void *stream);
+
+/* Weights for DG_IND_LEARNED on this problem (kept as pointers until
+ * replaced): a cell is troubled when p > band_hi, untroubled when p < band_lo,
+ * and decided by TVB in between.  prob (device float [cells], may be NULL)
+ * receives p at every indicator pass. */
+int dg_set_learned(dg_problem *p, const uint16_t *w_bf16, const float *master, double band_lo, double band_hi,
+                   float *prob);
 
 #ifdef __cplusplus
 }

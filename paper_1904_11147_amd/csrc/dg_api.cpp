@@ -62,7 +62,9 @@ int validate(const dg_config *c) {
   if ((c->bc[0] == DG_BC_PERIODIC) != (c->bc[1] == DG_BC_PERIODIC)) return DG_ERR_INVALID_ARG;
   if (c->dim == 2 && (c->bc[2] == DG_BC_PERIODIC) != (c->bc[3] == DG_BC_PERIODIC)) return DG_ERR_INVALID_ARG;
   if (c->limiter != DG_LIM_NONE && c->limiter != DG_LIM_CSWENO) return DG_ERR_INVALID_ARG;
-  if (c->indicator != DG_IND_TVB && c->indicator != DG_IND_ALL) return DG_ERR_UNSUPPORTED;
+  if (c->indicator != DG_IND_TVB && c->indicator != DG_IND_ALL && c->indicator != DG_IND_LEARNED)
+    return DG_ERR_UNSUPPORTED;
+  if (c->indicator == DG_IND_LEARNED && c->dim != 2) return DG_ERR_UNSUPPORTED;
   if (c->negw_mode != DG_NEGW_SPLIT && c->negw_mode != DG_NEGW_RAW) return DG_ERR_INVALID_ARG;
   if (!(c->x1 > c->x0) || (c->dim == 2 && !(c->y1 > c->y0))) return DG_ERR_INVALID_ARG;
   if (c->equation == DG_EQ_EULER && !(c->gamma > 1.0)) return DG_ERR_INVALID_ARG;
@@ -265,6 +267,11 @@ int dg_init(const dg_config *cfg, void *workspace, size_t workspace_bytes, void 
   c.indicator = cfg->indicator;
   c.grid_cap = 2048;
   c.use_march = 1;
+  c.mlp_w = nullptr;
+  c.mlp_m = nullptr;
+  c.mlp_prob = nullptr;
+  c.band_lo = 0.2;
+  c.band_hi = 0.8;
   if (hipMemsetAsync(c.sc, 0, sizeof(DevScalars), p->user_stream) != hipSuccess ||
       hipStreamSynchronize(p->user_stream) != hipSuccess) {
     delete p;
@@ -314,6 +321,7 @@ int dg_residual(dg_problem *p, const double *state, double *out) {
 int dg_limit(dg_problem *p, double *state, uint8_t *flags, double *margin, const uint8_t *flags_override,
              int32_t *n_troubled) {
   if (!p || !state) return DG_ERR_INVALID_ARG;
+  if (p->cfg.indicator == DG_IND_LEARNED && !p->ctx.mlp_w && !flags_override) return DG_ERR_INVALID_ARG;
   int rc = dg::launch_reset_counts(p->ctx);
   if (rc) return rc;
   const LaunchCtx &c = p->ctx;  // with DG_LIM_NONE only the indicator runs
@@ -347,6 +355,7 @@ int dg_cfl_dt(dg_problem *p, const double *state, double *dt) {
 int dg_step(dg_problem *p, double *state, double *t, double t_end, double dt, int32_t max_steps,
             int32_t *steps_taken) {
   if (!p || !state || !t || max_steps < 0) return DG_ERR_INVALID_ARG;
+  if (p->cfg.indicator == DG_IND_LEARNED && !p->ctx.mlp_w) return DG_ERR_INVALID_ARG;
   if (steps_taken) *steps_taken = 0;
   if (max_steps == 0 || !(*t < t_end)) return DG_OK;
   const bool cfl_mode = !(dt > 0.0);
@@ -456,6 +465,67 @@ int dg_profile_read(dg_problem *p, double *ms, int64_t *launches, int64_t *troub
             hipSuccess ||
         hipStreamSynchronize(p->user_stream) != hipSuccess)
       return DG_ERR_HIP;
+  }
+  return DG_OK;
+}
+
+int dg_mlp_layout(int32_t features, int32_t *padded, int64_t *n_master, int64_t *n_bf16) {
+  int kp;
+  long nm, nb;
+  int rc = dg::mlp_layout(features, &kp, &nm, &nb);
+  if (rc) return rc;
+  if (padded) *padded = kp;
+  if (n_master) *n_master = nm;
+  if (n_bf16) *n_bf16 = nb;
+  return DG_OK;
+}
+
+int dg_mlp_features(dg_problem *p, const double *state, float *f32, uint16_t *bf16) {
+  if (!p || !state || (!f32 && !bf16) || p->cfg.dim != 2) return DG_ERR_INVALID_ARG;
+  const int F = 5 * p->ctx.nm * p->ctx.nv;
+  int kp;
+  int rc = dg::mlp_layout(F, &kp, nullptr, nullptr);
+  if (!rc) rc = dg::launch_mlp_features(p->ctx, state, f32, bf16, kp);
+  if (rc) return rc;
+  return hip_ok(hipStreamSynchronize(p->user_stream));
+}
+
+int dg_mlp_forward(const uint16_t *x, int32_t n, int32_t features, const uint16_t *w_bf16, const float *master,
+                   float *prob, void *stream) {
+  if (!x || !w_bf16 || !master || !prob || n < 0) return DG_ERR_INVALID_ARG;
+  int rc = dg::launch_mlp_forward(x, n, features, w_bf16, master, prob, stream);
+  if (rc) return rc;
+  return hip_ok(hipStreamSynchronize((hipStream_t)stream));
+}
+
+int dg_mlp_gradient(const uint16_t *x, const float *y, const float *wgt, int32_t n, int32_t features,
+                    const uint16_t *w_bf16, const float *master, float *grad, uint16_t *dh1, float *loss,
+                    void *stream) {
+  if (!x || !y || !wgt || !w_bf16 || !master || !grad || !dh1 || !loss || n < 0) return DG_ERR_INVALID_ARG;
+  int rc = dg::launch_mlp_gradient(x, y, wgt, n, features, w_bf16, master, grad, dh1, loss, stream);
+  if (rc) return rc;
+  return hip_ok(hipStreamSynchronize((hipStream_t)stream));
+}
+
+int dg_mlp_adam(float *master, float *adam_m, float *adam_v, float *grad, uint16_t *w_bf16, int32_t features,
+                float lr, int32_t step, void *stream) {
+  if (!master || !w_bf16 || step < 0 || (step > 0 && (!adam_m || !adam_v || !grad))) return DG_ERR_INVALID_ARG;
+  int rc = dg::launch_mlp_adam(master, adam_m, adam_v, grad, w_bf16, features, lr, step, stream);
+  if (rc) return rc;
+  return hip_ok(hipStreamSynchronize((hipStream_t)stream));
+}
+
+int dg_set_learned(dg_problem *p, const uint16_t *w_bf16, const float *master, double band_lo, double band_hi,
+                   float *prob) {
+  if (!p || !w_bf16 || !master || !(band_lo <= band_hi) || p->cfg.dim != 2) return DG_ERR_INVALID_ARG;
+  p->ctx.mlp_w = w_bf16;
+  p->ctx.mlp_m = master;
+  p->ctx.band_lo = band_lo;
+  p->ctx.band_hi = band_hi;
+  p->ctx.mlp_prob = prob;
+  if (p->graph) {  // the captured step holds the old arguments
+    (void)hipGraphExecDestroy(p->graph);
+    p->graph = nullptr;
   }
   return DG_OK;
 }

@@ -84,6 +84,10 @@ struct LaunchCtx {
   int limiter, indicator;
   int grid_cap;          // blocks for list-driven kernels
   int use_march;         // 2D: marching stage kernel where registers allow
+  const uint16_t *mlp_w; // learned indicator: bf16 weights (caller-owned)
+  const float *mlp_m;    // fp32 master parameters (biases read from here)
+  float *mlp_prob;       // optional per-cell probability output
+  double band_lo, band_hi;
 };
 
 // Kernel-TU entry points (host functions, enqueue only).
@@ -95,5 +99,11 @@ int launch_speed(const LaunchCtx &c, const double *u);
 int launch_dt_finalize(const LaunchCtx &c);
 int launch_reset_counts(const LaunchCtx &c);
 int launch_project(const LaunchCtx &c, const double *pv, int j0, int nrows, double *u);
+int launch_mlp_features(const LaunchCtx &c, const double *u, float *f32, uint16_t *bf, int KP);
+int mlp_layout(int F, int *KP, long *nmaster, long *nbf16);
+int launch_mlp_forward(const uint16_t *x, int n, int F, const uint16_t *W, const float *M, float *p, void *stream);
+int launch_mlp_gradient(const uint16_t *x, const float *y, const float *w, int n, int F, const uint16_t *W,
+                        const float *M, float *G, uint16_t *dh1, float *loss, void *stream);
+int launch_mlp_adam(float *M, float *m1, float *m2, float *G, uint16_t *W, int F, float lr, int step, void *stream);
 
 }  // namespace dg

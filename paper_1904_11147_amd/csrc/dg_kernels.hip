@@ -1185,65 +1185,56 @@ struct LimitArgs {
   int check_done;
 };
 
+// TVB-modified minmod decision of cell (i, j) from the state u; mg receives
+// the decision margin.
 template <int N, int EQ, int DIM>
-__global__ __launch_bounds__(kBlock) void k_indicator(LimitArgs a) {
+__device__ inline bool tvb_cell(const double *__restrict__ u, const Geometry &g, int i, int j, double &mg) {
   constexpr int NP = N + 1, NM = DIM == 1 ? NP : NP * NP, NV = Phys<EQ, DIM>::NV;
   const OrderTables &T = c_tab[N];
-  const Geometry &g = a.geo;
-  if (a.check_done && a.sc->done) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = DIM == 1 ? 0 : blockIdx.y * blockDim.y + threadIdx.y;
   const long plane = (long)g.nx * g.ny;
-  const bool active = i < g.nx && j < g.ny;
-  const long cell = (long)j * g.nx + i;
+  const double k0 = DIM == 1 ? T.b0[0] : T.b0[0] * T.b0[0];
   bool flag = false;
-  double mg = INFINITY;
-  if (active) {
-    if (a.ovr) {
-      flag = a.ovr[cell] != 0;
-    } else if (a.mode == DG_IND_ALL) {
-      flag = true;
-    } else {
-      const double k0 = DIM == 1 ? T.b0[0] : T.b0[0] * T.b0[0];
-      double C[NV][NM];
-      load_cell<NP, NM, NV, DIM>(a.u, plane, map_cell(g, i, j), C);
+  double C[NV][NM];
+  load_cell<NP, NM, NV, DIM>(u, plane, map_cell(g, i, j), C);
 #pragma unroll
-      for (int dir = 0; dir < DIM; ++dir) {
-        const double Mh2 = dir == 0 ? g.tvb_Mx : g.tvb_My;
-        const CellIdx cp = map_cell(g, i + (dir == 0), j + (dir == 1));
-        const CellIdx cm = map_cell(g, i - (dir == 0), j - (dir == 1));
+  for (int dir = 0; dir < DIM; ++dir) {
+    const double Mh2 = dir == 0 ? g.tvb_Mx : g.tvb_My;
+    const CellIdx cp = map_cell(g, i + (dir == 0), j + (dir == 1));
+    const CellIdx cm = map_cell(g, i - (dir == 0), j - (dir == 1));
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          double mean = C[v][0] * k0;
-          double mp = a.u[(long)(v * NM) * plane + cp.idx] * k0;
-          double mm = a.u[(long)(v * NM) * plane + cm.idx] * k0;
-          double up = 0.0, um = 0.0;
+    for (int v = 0; v < NV; ++v) {
+      double mean = C[v][0] * k0;
+      double mp = u[(long)(v * NM) * plane + cp.idx] * k0;
+      double mm = u[(long)(v * NM) * plane + cm.idx] * k0;
+      double up = 0.0, um = 0.0;
 #pragma unroll
-          for (int q = 0; q < NM; ++q) {
-            int m = q % NP, n = q / NP;
-            double bu, bd;
-            if (DIM == 1) {
-              bu = T.bp[m];
-              bd = T.bm[m];
-            } else if (dir == 0) {
-              bu = T.bp[m] * T.b0[n];
-              bd = T.bm[m] * T.b0[n];
-            } else {
-              bu = T.b0[m] * T.bp[n];
-              bd = T.b0[m] * T.bm[n];
-            }
-            up += C[v][q] * bu;
-            um += C[v][q] * bd;
-          }
-          double dp = mp - mean, dm = mean - mm;
-          flag |= tvb_test(up - mean, dp, dm, Mh2, mg);
-          flag |= tvb_test(mean - um, dp, dm, Mh2, mg);
+      for (int q = 0; q < NM; ++q) {
+        int m = q % NP, n = q / NP;
+        double bu, bd;
+        if (DIM == 1) {
+          bu = T.bp[m];
+          bd = T.bm[m];
+        } else if (dir == 0) {
+          bu = T.bp[m] * T.b0[n];
+          bd = T.bm[m] * T.b0[n];
+        } else {
+          bu = T.b0[m] * T.bp[n];
+          bd = T.b0[m] * T.bm[n];
         }
+        up += C[v][q] * bu;
+        um += C[v][q] * bd;
       }
+      double dp = mp - mean, dm = mean - mm;
+      flag |= tvb_test(up - mean, dp, dm, Mh2, mg);
+      flag |= tvb_test(mean - um, dp, dm, Mh2, mg);
     }
-    if (a.flags) a.flags[cell] = flag ? 1 : 0;
-    if (a.margin) a.margin[cell] = mg;
   }
+  return flag;
+}
+
+// Appends the flagged cells of a wavefront to the troubled list (one atomic
+// per wavefront).
+__device__ inline void append_troubled(const LimitArgs &a, bool flag, long cell) {
   unsigned long long ballot = __ballot(flag);
   if (ballot) {
     const int lane = __lane_id();
@@ -1256,6 +1247,30 @@ __global__ __launch_bounds__(kBlock) void k_indicator(LimitArgs a) {
     base = __shfl(base, leader);
     if (flag) a.list[base + __popcll(ballot & ((1ull << lane) - 1ull))] = (int32_t)cell;
   }
+}
+
+template <int N, int EQ, int DIM>
+__global__ __launch_bounds__(kBlock) void k_indicator(LimitArgs a) {
+  const Geometry &g = a.geo;
+  if (a.check_done && a.sc->done) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = DIM == 1 ? 0 : blockIdx.y * blockDim.y + threadIdx.y;
+  const bool active = i < g.nx && j < g.ny;
+  const long cell = (long)j * g.nx + i;
+  bool flag = false;
+  double mg = INFINITY;
+  if (active) {
+    if (a.ovr) {
+      flag = a.ovr[cell] != 0;
+    } else if (a.mode == DG_IND_ALL) {
+      flag = true;
+    } else {
+      flag = tvb_cell<N, EQ, DIM>(a.u, g, i, j, mg);
+    }
+    if (a.flags) a.flags[cell] = flag ? 1 : 0;
+    if (a.margin) a.margin[cell] = mg;
+  }
+  append_troubled(a, flag, cell);
 }
 
 // ---------------------------------------------------------------------------
@@ -1460,6 +1475,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(LimitArgs a, double *dst) {
   }
 }
 
+#include "dg_mlp.hpp"
+
 // ---------------------------------------------------------------------------
 // L2 projection of point values (rows j0..j0+nrows-1).
 // ---------------------------------------------------------------------------
@@ -1594,7 +1611,13 @@ int launch_limit(const LaunchCtx &c, double *u, double *side, int count_slot, ui
     constexpr int NM = d == 1 ? n + 1 : (n + 1) * (n + 1);
     constexpr int NV = Phys<e, d>::NV;
     dim3 block, grid = cell_grid(c, block);
-    hipLaunchKernelGGL((k_indicator<n, e, d>), grid, block, 0, S(c), a);
+    if (d == 2 && c.indicator == DG_IND_LEARNED && !flags_override) {
+      LearnedArgs L{c.mlp_w, c.mlp_m, MlpLayout{5 * NM * NV, (5 * NM * NV + 15) / 16 * 16}, (float)c.band_lo,
+                    (float)c.band_hi, c.mlp_prob};
+      hipLaunchKernelGGL((k_indicator_learned<n, e>), dim3((c.geo.nx + 63) / 64, c.geo.ny), dim3(64), 0, S(c), a, L);
+    } else {
+      hipLaunchKernelGGL((k_indicator<n, e, d>), grid, block, 0, S(c), a);
+    }
     if (c.limiter == DG_LIM_CSWENO) {
       hipLaunchKernelGGL((k_csweno<n, e, d>), dim3(c.grid_cap), dim3(kBlock), 0, S(c), a);
       hipLaunchKernelGGL((k_scatter<NM, NV>), dim3(c.grid_cap), dim3(kBlock), 0, S(c), a, u);
@@ -1629,6 +1652,75 @@ int launch_project(const LaunchCtx &c, const double *pv, int j0, int nrows, doub
     hipLaunchKernelGGL((k_project<decltype(NN)::value, decltype(D)::value>), grid, dim3(kBlock), 0, S(c), pv, u,
                        c.geo, c.nv, j0, nrows);
   });
+}
+
+
+int launch_mlp_features(const LaunchCtx &c, const double *u, float *f32, uint16_t *bf, int KP) {
+  const long cells = (long)c.geo.nx * c.geo.ny;
+  dim3 grid((unsigned)((cells + kBlock - 1) / kBlock));
+  if (c.dim != 2) return DG_ERR_UNSUPPORTED;
+  return dispatch(c, [&](auto D, auto E, auto NN) {
+    constexpr int e = decltype(E)::value, n = decltype(NN)::value;
+    hipLaunchKernelGGL((k_mlp_features<n, Phys<e, 2>::NV>), grid, dim3(kBlock), 0, S(c), u, c.geo, f32, bf, KP);
+  });
+}
+
+template <typename F>
+int kp_dispatch(int KP, F &&f) {
+  switch (KP) {
+    case 32: f(std::integral_constant<int, 32>{}); break;
+    case 48: f(std::integral_constant<int, 48>{}); break;
+    case 80: f(std::integral_constant<int, 80>{}); break;
+    case 192: f(std::integral_constant<int, 192>{}); break;
+    case 320: f(std::integral_constant<int, 320>{}); break;
+    default: return DG_ERR_UNSUPPORTED;
+  }
+  return check_launch();
+}
+
+int mlp_layout(int F, int *KP, long *nmaster, long *nbf16) {
+  if (F < 1) return DG_ERR_INVALID_ARG;
+  MlpLayout lay{F, (F + 15) / 16 * 16};
+  if (KP) *KP = lay.KP;
+  if (nmaster) *nmaster = lay.nmaster();
+  if (nbf16) *nbf16 = lay.nbf16();
+  return DG_OK;
+}
+
+int launch_mlp_forward(const uint16_t *x, int n, int F, const uint16_t *W, const float *M, float *p, void *stream) {
+  MlpLayout lay{F, (F + 15) / 16 * 16};
+  if (n <= 0) return DG_OK;
+  return kp_dispatch(lay.KP, [&](auto K) {
+    hipLaunchKernelGGL((k_mlp_forward<decltype(K)::value>), dim3((n + 15) / 16), dim3(64), 0, (hipStream_t)stream, x,
+                       n, W, M, lay, p);
+  });
+}
+
+int launch_mlp_gradient(const uint16_t *x, const float *y, const float *w, int n, int F, const uint16_t *W,
+                        const float *M, float *G, uint16_t *dh1, float *loss, void *stream) {
+  MlpLayout lay{F, (F + 15) / 16 * 16};
+  if (n <= 0) return DG_OK;
+  const int ntiles = (n + 15) / 16;
+  const int blocks = ntiles < 4096 ? ntiles : 4096;
+  int rc = kp_dispatch(lay.KP, [&](auto K) {
+    hipLaunchKernelGGL((k_mlp_train_tiles<decltype(K)::value>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, x, y,
+                       w, n, W, M, lay, G, dh1, loss);
+  });
+  if (rc) return rc;
+  const int chunk = 1024;
+  dim3 grid((lay.KP + 63) / 64, (n + chunk - 1) / chunk);
+  return kp_dispatch(lay.KP, [&](auto K) {
+    hipLaunchKernelGGL((k_mlp_wgrad1<decltype(K)::value>), grid, dim3(64), 0, (hipStream_t)stream, x, dh1, n, lay, G,
+                       chunk);
+  });
+}
+
+int launch_mlp_adam(float *M, float *m1, float *m2, float *G, uint16_t *W, int F, float lr, int step, void *stream) {
+  MlpLayout lay{F, (F + 15) / 16 * 16};
+  const long n = lay.nmaster();
+  hipLaunchKernelGGL(k_mlp_adam, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, (hipStream_t)stream, M,
+                     m1, m2, G, W, lay, lr, step);
+  return check_launch();
 }
 
 }  // namespace dg

@@ -1,0 +1,453 @@
+// Learned troubled-cell indicator: features, MLP forward/backward with BF16
+// MFMA (FP32 accumulate), Adam, and the indicator kernel of the limiter.
+// Included into dg_kernels.hip (inside its anonymous namespace), so it shares
+// the coefficient tables, the boundary handling and the TVB decision.
+//
+// Network: x (F features, padded to KP, bf16) -> h1 = relu(W1 x + b1) (64)
+// -> h2 = relu(W2 h1 + b2) (64) -> z = w3 . h2 + b3 -> p = sigmoid(z).
+// Weights bf16, biases and accumulation fp32.
+//
+// MFMA v_mfma_f32_16x16x16_bf16 register layout (wave64, lane l, r = l % 16,
+// g = l / 16):  A (16 x 16, rows x k):   lane holds A[r][4g .. 4g+3]
+//               B (16 x 16, k x cols):   lane holds B[4g .. 4g+3][r]
+//               D (16 x 16, rows x cols): lane holds D[4g + i][r], i = 0..3.
+
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kHidden = 64;
+
+__device__ inline uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ inline f32x4_t mfma16(bf16x4_t a, bf16x4_t b, f32x4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ inline bf16x4_t pack4(float a, float b, float c, float d) {
+  bf16x4_t v;
+  v[0] = (short)f2bf(a);
+  v[1] = (short)f2bf(b);
+  v[2] = (short)f2bf(c);
+  v[3] = (short)f2bf(d);
+  return v;
+}
+
+__device__ inline bf16x4_t load4(const uint16_t *p) { return *reinterpret_cast<const bf16x4_t *>(p); }
+
+// Offsets into the bf16 weight buffer: W1 [64][KP] | W2 [64][64] | W2T [64][64] | w3 [64].
+struct MlpLayout {
+  int F, KP;
+  __host__ __device__ long w1() const { return 0; }
+  __host__ __device__ long w2() const { return (long)kHidden * KP; }
+  __host__ __device__ long w2t() const { return w2() + kHidden * kHidden; }
+  __host__ __device__ long w3() const { return w2t() + kHidden * kHidden; }
+  __host__ __device__ long nbf16() const { return w3() + kHidden; }
+  // master fp32: W1 [64][F] | W2 [64][64] | w3 [64] | b1 [64] | b2 [64] | b3
+  __host__ __device__ long mW2() const { return (long)kHidden * F; }
+  __host__ __device__ long mw3() const { return mW2() + kHidden * kHidden; }
+  __host__ __device__ long mb1() const { return mw3() + kHidden; }
+  __host__ __device__ long mb2() const { return mb1() + kHidden; }
+  __host__ __device__ long mb3() const { return mb2() + kHidden; }
+  __host__ __device__ long nmaster() const { return mb3() + 1; }
+};
+
+// One 16-sample tile through the network.  loadA(kb) returns the lane's A
+// fragment of the input rows (row r, features 16 kb + 4g ..).  lds is a
+// 16 x 64 bf16 scratch.  Outputs in D layout: h1, h2 (post-ReLU, fp32) and
+// z for samples 4g + i (the same in all 16 lanes of group g).
+template <int KP, typename LoadA>
+__device__ inline void mlp_tile_forward(LoadA loadA, const uint16_t *__restrict__ W, const float *__restrict__ M,
+                                        const MlpLayout &lay, uint16_t *lds, f32x4_t (&h1)[4], f32x4_t (&h2)[4],
+                                        float (&z)[4]) {
+  const int lane = __lane_id(), r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) h1[nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kb = 0; kb < KP / 16; ++kb) {
+    const bf16x4_t a = loadA(kb);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+      h1[nt] = mfma16(a, load4(W + lay.w1() + (long)(16 * nt + r) * KP + 16 * kb + 4 * g), h1[nt]);
+  }
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const float b = M[lay.mb1() + 16 * nt + r];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      h1[nt][i] = fmaxf(h1[nt][i] + b, 0.f);
+      lds[(4 * g + i) * kHidden + 16 * nt + r] = f2bf(h1[nt][i]);
+    }
+  }
+  __syncthreads();  // one wavefront per block: orders the LDS tile
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) h2[nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    const bf16x4_t a = load4(lds + r * kHidden + 16 * kb + 4 * g);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+      h2[nt] = mfma16(a, load4(W + lay.w2() + (16 * nt + r) * kHidden + 16 * kb + 4 * g), h2[nt]);
+  }
+  __syncthreads();  // the scratch tile may be rewritten by the caller next
+  float part[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const float b = M[lay.mb2() + 16 * nt + r];
+    const float w3 = bf2f(W[lay.w3() + 16 * nt + r]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      h2[nt][i] = fmaxf(h2[nt][i] + b, 0.f);
+      part[i] += bf2f(f2bf(h2[nt][i])) * w3;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float s = part[i];
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+    z[i] = s + M[lay.mb3()];
+  }
+}
+
+// Features of cell (i, j) for variable v written as bf16 into dst[0..5*NM)
+// (and fp32 into dst32 when given): cells C, W, E, S, N in that order, each
+// with its modes; mode-0 entries shifted by the centre's mode 0; all scaled
+// by max(max |entry|, M hx^2).
+template <int N, int NV>
+__device__ inline void cell_features(const double *__restrict__ u, const Geometry &g, int i, int j, int v,
+                                     uint16_t *dst, float *dst32) {
+  constexpr int NP = N + 1, NM = NP * NP;
+  const long plane = (long)g.nx * g.ny;
+  double f[5 * NM];
+  const int di[5] = {0, -1, 1, 0, 0}, dj[5] = {0, 0, 0, -1, 1};
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    const CellIdx ci = map_cell(g, i + di[c], j + dj[c]);
+#pragma unroll
+    for (int q = 0; q < NM; ++q) {
+      const int m = q % NP, n = q / NP;
+      const double s = u[(long)(v * NM + q) * plane + ci.idx];
+      f[c * NM + q] = ((ci.fx && (m & 1)) != (ci.fy && (n & 1))) ? -s : s;
+    }
+  }
+  const double c0 = f[0];
+  double mx = g.tvb_Mx;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) f[c * NM] -= c0;
+#pragma unroll
+  for (int k = 0; k < 5 * NM; ++k) mx = fmax(mx, fabs(f[k]));
+  const double inv = 1.0 / mx;
+#pragma unroll
+  for (int k = 0; k < 5 * NM; ++k) {
+    const float x = (float)(f[k] * inv);
+    if (dst) dst[k] = f2bf(x);
+    if (dst32) dst32[k] = x;
+  }
+}
+
+template <int N, int NV>
+__global__ __launch_bounds__(kBlock) void k_mlp_features(const double *__restrict__ u, Geometry g, float *f32,
+                                                         uint16_t *bf, int KP) {
+  constexpr int NM = (N + 1) * (N + 1), F = 5 * NM * NV;
+  const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= (long)g.nx * g.ny) return;
+  const int i = (int)(cell % g.nx), j = (int)(cell / g.nx);
+#pragma unroll 1
+  for (int v = 0; v < NV; ++v)
+    cell_features<N, NV>(u, g, i, j, v, bf ? bf + cell * KP + v * 5 * NM : nullptr,
+                         f32 ? f32 + cell * F + v * 5 * NM : nullptr);
+  if (bf)
+    for (int k = F; k < KP; ++k) bf[cell * KP + k] = 0;
+}
+
+// Inference: p for n samples (rows of x, KP bf16 each).  One wavefront per
+// 16-sample tile.
+template <int KP>
+__global__ __launch_bounds__(64) void k_mlp_forward(const uint16_t *__restrict__ x, int n, const uint16_t *W,
+                                                    const float *M, MlpLayout lay, float *p) {
+  __shared__ uint16_t lds[16 * kHidden];
+  const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
+  const long s0 = (long)blockIdx.x * 16;
+  auto loadA = [&](int kb) -> bf16x4_t {
+    const long row = s0 + r;
+    if (row >= n) return bf16x4_t{0, 0, 0, 0};
+    return load4(x + row * KP + 16 * kb + 4 * g);
+  };
+  f32x4_t h1[4], h2[4];
+  float z[4];
+  mlp_tile_forward<KP>(loadA, W, M, lay, lds, h1, h2, z);
+  if (r == 0)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const long s = s0 + 4 * g + i;
+      if (s < n) p[s] = 1.f / (1.f + __expf(-z[i]));
+    }
+}
+
+// Training, part 1: forward and backward of each 16-sample tile; dW2, b2,
+// w3, b3, b1 gradients accumulated per wavefront and added atomically; dh1
+// (bf16, [n][64]) stored for the dW1 kernel; loss summed atomically.
+template <int KP>
+__global__ __launch_bounds__(64) void k_mlp_train_tiles(const uint16_t *__restrict__ x, const float *__restrict__ y,
+                                                        const float *__restrict__ wgt, int n, const uint16_t *W,
+                                                        const float *M, MlpLayout lay, float *G, uint16_t *dh1_out,
+                                                        float *loss) {
+  __shared__ uint16_t lds[16 * kHidden];
+  const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
+  const int ntiles = (n + 15) / 16;
+  const float inv_n = 1.0f / (float)n;
+  f32x4_t gW2[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) gW2[a][b] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  float gb1[4] = {0.f, 0.f, 0.f, 0.f}, gb2[4] = {0.f, 0.f, 0.f, 0.f}, gw3[4] = {0.f, 0.f, 0.f, 0.f};
+  float gb3 = 0.f, lsum = 0.f;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const long s0 = (long)t * 16;
+    auto loadA = [&](int kb) -> bf16x4_t {
+      const long row = s0 + r;
+      if (row >= n) return bf16x4_t{0, 0, 0, 0};
+      return load4(x + row * KP + 16 * kb + 4 * g);
+    };
+    f32x4_t h1[4], h2[4];
+    float z[4];
+    mlp_tile_forward<KP>(loadA, W, M, lay, lds, h1, h2, z);
+    float dz[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const long s = s0 + 4 * g + i;
+      if (s < n) {
+        const float yy = y[s], ww = wgt[s];
+        const float pp = 1.f / (1.f + __expf(-z[i]));
+        dz[i] = ww * (pp - yy) * inv_n;
+        // log(1 + e^z) - y z, stable
+        const float sp = fmaxf(z[i], 0.f) + log1pf(__expf(-fabsf(z[i])));
+        if (r == 0) lsum += ww * (sp - yy * z[i]) * inv_n;
+      } else {
+        dz[i] = 0.f;
+      }
+    }
+    // layer 3 and dh2 (D layout), w3 gradient
+    f32x4_t dh2[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const float w3 = bf2f(W[lay.w3() + 16 * nt + r]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        gw3[nt] += dz[i] * bf2f(f2bf(h2[nt][i]));
+        dh2[nt][i] = h2[nt][i] > 0.f ? dz[i] * w3 : 0.f;
+        gb2[nt] += dh2[nt][i];
+      }
+    }
+    if (r == 0)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) gb3 += dz[i];
+    // dW2 += dh2^T h1: both operands are already in the D layout
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      const bf16x4_t a = pack4(dh2[mt][0], dh2[mt][1], dh2[mt][2], dh2[mt][3]);
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+        gW2[mt][nt] = mfma16(a, pack4(h1[nt][0], h1[nt][1], h1[nt][2], h1[nt][3]), gW2[mt][nt]);
+    }
+    // dh1 = (dh2 W2) . [h1 > 0]: dh2 to the A layout through LDS, W2^T rows for B
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) lds[(4 * g + i) * kHidden + 16 * nt + r] = f2bf(dh2[nt][i]);
+    __syncthreads();
+    f32x4_t dh1[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) dh1[nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      const bf16x4_t a = load4(lds + r * kHidden + 16 * kb + 4 * g);
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+        dh1[nt] = mfma16(a, load4(W + lay.w2t() + (16 * nt + r) * kHidden + 16 * kb + 4 * g), dh1[nt]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float d = h1[nt][i] > 0.f ? dh1[nt][i] : 0.f;
+        gb1[nt] += d;
+        const long s = s0 + 4 * g + i;
+        if (s < n) dh1_out[s * kHidden + 16 * nt + r] = f2bf(d);
+      }
+  }
+  // reduce over the four lane groups and add
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    float a1 = gb1[nt], a2 = gb2[nt], a3 = gw3[nt];
+    a1 += __shfl_xor(a1, 16);
+    a1 += __shfl_xor(a1, 32);
+    a2 += __shfl_xor(a2, 16);
+    a2 += __shfl_xor(a2, 32);
+    a3 += __shfl_xor(a3, 16);
+    a3 += __shfl_xor(a3, 32);
+    if (g == 0) {
+      atomicAdd(&G[lay.mb1() + 16 * nt + r], a1);
+      atomicAdd(&G[lay.mb2() + 16 * nt + r], a2);
+      atomicAdd(&G[lay.mw3() + 16 * nt + r], a3);
+    }
+  }
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) atomicAdd(&G[lay.mW2() + (16 * mt + 4 * g + i) * kHidden + 16 * nt + r], gW2[mt][nt][i]);
+  float b3 = gb3, ls = lsum;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    b3 += __shfl_xor(b3, o);
+    ls += __shfl_xor(ls, o);
+  }
+  if (lane == 0) {
+    atomicAdd(&G[lay.mb3()], b3);
+    atomicAdd(loss, ls);
+  }
+}
+
+// Training, part 2: dW1 += dh1^T x over a chunk of samples (split-K), one
+// wavefront per (chunk, 64-column group of the padded input).
+template <int KP>
+__global__ __launch_bounds__(64) void k_mlp_wgrad1(const uint16_t *__restrict__ x, const uint16_t *__restrict__ dh1,
+                                                   int n, MlpLayout lay, float *G, int chunk) {
+  const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
+  const int col0 = blockIdx.x * 64;
+  const long sA = (long)blockIdx.y * chunk, sB = min((long)n, sA + chunk);
+  f32x4_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  for (long s0 = sA; s0 < sB; s0 += 16) {
+    bf16x4_t A[4], B[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const long s = s0 + 4 * g + j;
+        A[mt][j] = (short)(s < sB ? dh1[s * kHidden + 16 * mt + r] : 0);
+      }
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int c = col0 + 16 * nt + r;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const long s = s0 + 4 * g + j;
+        B[nt][j] = (short)(s < sB && c < KP ? x[s * KP + c] : 0);
+      }
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma16(A[mt], B[nt], acc[mt][nt]);
+  }
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int c = col0 + 16 * nt + r;
+      if (c < lay.F)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) atomicAdd(&G[(long)(16 * mt + 4 * g + i) * lay.F + c], acc[mt][nt][i]);
+    }
+}
+
+// Adam on the fp32 master parameters; refreshes the bf16 copies and clears
+// the gradient.  step >= 1; step == 0 only copies master -> bf16.
+__global__ __launch_bounds__(kBlock) void k_mlp_adam(float *M, float *m1, float *m2, float *G, uint16_t *W,
+                                                     MlpLayout lay, float lr, int step) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= lay.nmaster()) return;
+  float w = M[k];
+  if (step > 0) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float gk = G[k];
+    const float a = b1 * m1[k] + (1.f - b1) * gk;
+    const float b = b2 * m2[k] + (1.f - b2) * gk * gk;
+    m1[k] = a;
+    m2[k] = b;
+    const float ah = a / (1.f - powf(b1, (float)step));
+    const float bh = b / (1.f - powf(b2, (float)step));
+    w -= lr * ah / (sqrtf(bh) + eps);
+    M[k] = w;
+    G[k] = 0.f;
+  }
+  if (k < lay.mW2()) {
+    const long o = k / lay.F, c = k % lay.F;
+    W[lay.w1() + o * lay.KP + c] = f2bf(w);
+  } else if (k < lay.mw3()) {
+    const long o = (k - lay.mW2()) / kHidden, c = (k - lay.mW2()) % kHidden;
+    W[lay.w2() + o * kHidden + c] = f2bf(w);
+    W[lay.w2t() + c * kHidden + o] = f2bf(w);
+  } else if (k < lay.mb1()) {
+    W[lay.w3() + (k - lay.mw3())] = f2bf(w);
+  }
+}
+
+// The limiter's learned indicator (2D): one wavefront per 64 consecutive cells
+// of a row.  Features -> LDS (bf16) -> four 16-cell tiles through the network;
+// p > band_hi flags, p < band_lo clears, otherwise the TVB decision.
+struct LearnedArgs {
+  const uint16_t *W;
+  const float *M;
+  MlpLayout lay;
+  float band_lo, band_hi;
+  float *prob;  // may be null: per-cell probability
+};
+
+template <int N, int EQ>
+__global__ __launch_bounds__(64) void k_indicator_learned(LimitArgs a, LearnedArgs L) {
+  constexpr int NM = (N + 1) * (N + 1), NV = Phys<EQ, 2>::NV, F = 5 * NM * NV, KP = (F + 15) / 16 * 16;
+  __shared__ uint16_t feat[64 * KP];
+  __shared__ uint16_t scratch[16 * kHidden];
+  __shared__ float zs[64];
+  const Geometry &g = a.geo;
+  if (a.check_done && a.sc->done) return;
+  const int lane = threadIdx.x;
+  const int i = blockIdx.x * 64 + lane, j = blockIdx.y;
+  const bool active = i < g.nx && j < g.ny;
+  const long cell = (long)j * g.nx + i;
+#pragma unroll 1
+  for (int v = 0; v < NV; ++v)
+    cell_features<N, NV>(a.u, g, active ? i : g.nx - 1, j, v, feat + lane * KP + v * 5 * NM, nullptr);
+  for (int k = F; k < KP; ++k) feat[lane * KP + k] = 0;
+  __syncthreads();
+  const int r = lane & 15, gq = lane >> 4;
+#pragma unroll 1
+  for (int t = 0; t < 4; ++t) {
+    auto loadA = [&](int kb) -> bf16x4_t { return load4(feat + (16 * t + r) * KP + 16 * kb + 4 * gq); };
+    f32x4_t h1[4], h2[4];
+    float z[4];
+    mlp_tile_forward<KP>(loadA, L.W, L.M, L.lay, scratch, h1, h2, z);
+    if (r == 0)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) zs[16 * t + 4 * gq + q] = z[q];
+  }
+  __syncthreads();
+  bool flag = false;
+  double mg = INFINITY;
+  if (active) {
+    const float p = 1.f / (1.f + __expf(-zs[lane]));
+    if (L.prob) L.prob[cell] = p;
+    if (a.ovr) flag = a.ovr[cell] != 0;
+    else if (p > L.band_hi) flag = true;
+    else if (p < L.band_lo) flag = false;
+    else flag = tvb_cell<N, EQ, 2>(a.u, g, i, j, mg);
+    if (a.flags) a.flags[cell] = flag ? 1 : 0;
+    if (a.margin) a.margin[cell] = mg;
+  }
+  append_troubled(a, flag, cell);
+}

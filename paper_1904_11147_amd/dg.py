@@ -22,12 +22,13 @@ DG_OK, DG_ERR_INVALID_ARG, DG_ERR_UNSUPPORTED, DG_ERR_WORKSPACE, DG_ERR_HIP, DG_
 BURGERS, EULER = 0, 1
 PERIODIC, TRANSMISSIVE = 0, 1
 LIM_NONE, LIM_CSWENO = 0, 1
-IND_TVB, IND_ALL = 0, 1
+IND_TVB, IND_ALL, IND_LEARNED = 0, 1, 2
 NEGW_SPLIT, NEGW_RAW = 0, 1
 
 # every symbol include/dg.h declares
 EXPORTS = ("dg_workspace_bytes", "dg_init", "dg_destroy", "dg_proj_nodes", "dg_project", "dg_residual",
-           "dg_limit", "dg_cfl_dt", "dg_step", "dg_status", "dg_strerror", "dg_profile_enable", "dg_profile_read")
+           "dg_limit", "dg_cfl_dt", "dg_step", "dg_status", "dg_strerror", "dg_profile_enable", "dg_profile_read",
+           "dg_mlp_layout", "dg_mlp_features", "dg_mlp_forward", "dg_mlp_gradient", "dg_mlp_adam", "dg_set_learned")
 PROF_KINDS = ("stage1", "stage23", "limiter", "dt")
 
 
@@ -90,6 +91,12 @@ def lib():
             "dg_status": [vp],
             "dg_profile_enable": [vp, ctypes.c_int],
             "dg_profile_read": [vp, P(d), P(ctypes.c_int64), P(ctypes.c_int64), ctypes.c_int],
+            "dg_mlp_layout": [i32, P(i32), P(ctypes.c_int64), P(ctypes.c_int64)],
+            "dg_mlp_features": [vp, vp, vp, vp],
+            "dg_mlp_forward": [vp, i32, i32, vp, vp, vp, vp],
+            "dg_mlp_gradient": [vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp],
+            "dg_mlp_adam": [vp, vp, vp, vp, vp, i32, ctypes.c_float, i32, vp],
+            "dg_set_learned": [vp, vp, vp, d, d, vp],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)

@@ -1,0 +1,197 @@
+"""Learned troubled-cell indicator: parameter buffers, training-data generation
+from plain runs, and the training loop.  Every arithmetic step runs in the
+library's kernels (features, BF16-MFMA forward/backward, Adam); torch holds the
+buffers and selects samples.
+
+Recipe (the workload's; the paper's own indicator is KXRCF):
+* data: plain FP64 runs (TVB M = 1 + CSWENO) of seeded 64 x 64 four-state
+  Riemann problems (Q2 Euler) to t = 0.25; every `every`-th step, the state
+  after one *unlimited* SSP-RK3 step from the current limited state is the
+  sample state.  Its features, its TVB flags (label) and the change the
+  limiter makes to each cell, w = 1 + |limited - unlimited|_1 / |unlimited|_1
+  (the sample weight), are recorded for every troubled cell and as many
+  random untroubled cells;
+* training: weighted binary cross-entropy, Adam (lr 1e-3), FP32 master
+  weights with BF16 copies;
+* inference: p > 0.8 troubled, p < 0.2 untroubled, TVB in between.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import dg
+from . import workloads as W
+
+HIDDEN = 64
+
+
+def layout(features):
+    kp = ctypes.c_int32()
+    nm = ctypes.c_int64()
+    nb = ctypes.c_int64()
+    rc = dg.lib().dg_mlp_layout(int(features), ctypes.byref(kp), ctypes.byref(nm), ctypes.byref(nb))
+    if rc:
+        raise dg.DGError(rc, "dg_mlp_layout")
+    return kp.value, nm.value, nb.value
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class MLP:
+    """Device buffers of one network with F input features."""
+
+    def __init__(self, features, device="cuda", seed=0, params=None):
+        self.F = int(features)
+        self.KP, nmaster, nbf16 = layout(self.F)
+        self.device = torch.device(device)
+        if params is None:
+            rng = np.random.default_rng(seed)
+            H = HIDDEN
+            params = np.concatenate([
+                rng.normal(size=H * self.F) * np.sqrt(2.0 / self.F),
+                rng.normal(size=H * H) * np.sqrt(2.0 / H),
+                rng.normal(size=H) * np.sqrt(1.0 / H),
+                np.zeros(2 * H + 1)])
+        params = np.asarray(params, dtype=np.float32)
+        assert params.size == nmaster
+        self.master = torch.from_numpy(params.copy()).to(self.device)
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        self.grad = torch.zeros_like(self.master)
+        self.w = torch.zeros(nbf16, dtype=torch.int16, device=self.device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        self.step_no = 0
+        self._dh1 = None
+        self.stream = torch.cuda.current_stream(self.device)
+        self._adam(0.0, 0)  # bf16 copies from the master weights
+
+    def _adam(self, lr, step):
+        rc = dg.lib().dg_mlp_adam(_p(self.master), _p(self.m), _p(self.v), _p(self.grad), _p(self.w), self.F,
+                                  ctypes.c_float(lr), int(step), ctypes.c_void_p(self.stream.cuda_stream))
+        if rc:
+            raise dg.DGError(rc, "dg_mlp_adam")
+
+    def forward(self, x_bf16):
+        n = x_bf16.shape[0]
+        p = torch.empty(n, dtype=torch.float32, device=self.device)
+        rc = dg.lib().dg_mlp_forward(_p(x_bf16), int(n), self.F, _p(self.w), _p(self.master), _p(p),
+                                     ctypes.c_void_p(self.stream.cuda_stream))
+        if rc:
+            raise dg.DGError(rc, "dg_mlp_forward")
+        return p
+
+    def gradient(self, x_bf16, y, wgt, accumulate=False):
+        """Adds the batch gradient to self.grad; returns the batch loss."""
+        n = x_bf16.shape[0]
+        if self._dh1 is None or self._dh1.numel() < n * HIDDEN:
+            self._dh1 = torch.empty(n * HIDDEN, dtype=torch.int16, device=self.device)
+        if not accumulate:
+            self.grad.zero_()
+        self.loss.zero_()
+        rc = dg.lib().dg_mlp_gradient(_p(x_bf16), _p(y), _p(wgt), int(n), self.F, _p(self.w), _p(self.master),
+                                      _p(self.grad), _p(self._dh1), _p(self.loss),
+                                      ctypes.c_void_p(self.stream.cuda_stream))
+        if rc:
+            raise dg.DGError(rc, "dg_mlp_gradient")
+        return float(self.loss.item())
+
+    def adam_step(self, lr=1e-3):
+        self.step_no += 1
+        self._adam(lr, self.step_no)
+
+    def params_numpy(self):
+        return self.master.detach().cpu().numpy().astype(np.float64)
+
+    def save(self, path):
+        np.savez(path, master=self.master.cpu().numpy(), F=self.F)
+
+    @classmethod
+    def load(cls, path, device="cuda"):
+        z = np.load(path, allow_pickle=False)
+        return cls(int(z["F"]), device=device, params=z["master"])
+
+
+def features(prob, state, bf16=True):
+    """Features of every cell of a 2D problem's state (kernel)."""
+    F = 5 * prob.nm * prob.nv
+    KP, _, _ = layout(F)
+    cells = prob.nx * prob.ny
+    if bf16:
+        out = torch.empty((cells, KP), dtype=torch.int16, device=prob.device)
+        rc = dg.lib().dg_mlp_features(prob._h, _p(state), None, _p(out))
+    else:
+        out = torch.empty((cells, F), dtype=torch.float32, device=prob.device)
+        rc = dg.lib().dg_mlp_features(prob._h, _p(state), _p(out), None)
+    if rc:
+        raise dg.DGError(rc, "dg_mlp_features")
+    return out
+
+
+def attach(prob, net, band=(0.2, 0.8), prob_out=None):
+    rc = dg.lib().dg_set_learned(prob._h, _p(net.w), _p(net.master), float(band[0]), float(band[1]),
+                                 _p(prob_out))
+    if rc:
+        raise dg.DGError(rc, "dg_set_learned")
+
+
+def generate_samples(seeds, n=64, order=2, t_end=0.25, every=10, device="cuda", max_steps=100000, gen_seed=0):
+    """Training samples from plain runs (see the module docstring).
+    Returns (x bf16 [S][KP], y float [S], w float [S])."""
+    g = torch.Generator(device="cpu").manual_seed(gen_seed)
+    xs, ys, ws = [], [], []
+    for seed in seeds:
+        wl = W.riemann2d(n=n, order=order, seed=seed, t_end=t_end)
+        plain = dg.problem_from_workload(wl, device=device)
+        free = dg.problem_from_workload(wl, device=device, limiter=dg.LIM_NONE)
+        state = dg.initial_state(plain, wl, limit=True)
+        t, k = 0.0, 0
+        while t < t_end and k < max_steps:
+            if k % every == 0:
+                u = state.clone()
+                dt = plain.cfl_dt(u)
+                free.step(u, 0.0, 1.0, dt=dt, max_steps=1, allow_nonphysical=True)
+                lim = u.clone()
+                flags, _, _ = plain.limit(lim, want_margin=False)
+                x = features(plain, u, bf16=True)
+                f = flags.reshape(-1).to(torch.float32)
+                num = (lim - u).abs().sum(dim=(0, 1)).reshape(-1)
+                den = u.abs().sum(dim=(0, 1)).reshape(-1).clamp_min(1e-300)
+                wgt = (1.0 + num / den).to(torch.float32)
+                tr = torch.nonzero(f > 0.5).reshape(-1)
+                un = torch.nonzero(f < 0.5).reshape(-1)
+                if un.numel() > 0 and tr.numel() > 0:
+                    pick = torch.randperm(un.numel(), generator=g)[: tr.numel()].to(un.device)
+                    idx = torch.cat([tr, un[pick]])
+                    xs.append(x[idx])
+                    ys.append(f[idx])
+                    ws.append(wgt[idx])
+            t, steps = plain.step(state, t, t_end, max_steps=1)
+            k += 1
+        plain.close()
+        free.close()
+    return torch.cat(xs), torch.cat(ys), torch.cat(ws)
+
+
+def train(net, x, y, w, epochs=3, batch=4096, lr=1e-3, seed=0, log=None):
+    """Mini-batch Adam over shuffled samples; returns the per-epoch mean loss."""
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    n = x.shape[0]
+    hist = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=gen).to(x.device)
+        tot, cnt = 0.0, 0
+        for s in range(0, n, batch):
+            idx = perm[s:s + batch]
+            loss = net.gradient(x[idx].contiguous(), y[idx].contiguous(), w[idx].contiguous())
+            net.adam_step(lr)
+            tot += loss * idx.numel()
+            cnt += idx.numel()
+        hist.append(tot / max(1, cnt))
+        if log:
+            log(f"epoch {ep}: loss {hist[-1]:.5f}")
+    return hist
