@@ -9,8 +9,8 @@ Recipe (the workload's; the paper's own indicator is KXRCF):
   after one *unlimited* SSP-RK3 step from the current limited state is the
   sample state.  Its features, its TVB flags (label) and the change the
   limiter makes to each cell, w = 1 + |limited - unlimited|_1 / |unlimited|_1
-  (the sample weight), are recorded for every troubled cell and as many
-  random untroubled cells;
+  (the sample weight), are recorded for equal numbers of random troubled and
+  untroubled cells (at most `cap` of each per sampled state);
 * training: weighted binary cross-entropy, Adam (lr 1e-3), FP32 master
   weights with BF16 copies;
 * inference: p > 0.8 troubled, p < 0.2 untroubled, TVB in between.
@@ -139,8 +139,14 @@ def attach(prob, net, band=(0.2, 0.8), prob_out=None):
         raise dg.DGError(rc, "dg_set_learned")
 
 
-def generate_samples(seeds, n=64, order=2, t_end=0.25, every=10, device="cuda", max_steps=100000, gen_seed=0):
-    """Training samples from plain runs (see the module docstring).
+SKIPPED = []  # (seed, time) of runs that met a non-physical state
+
+
+def generate_samples(seeds, n=64, order=2, t_end=0.25, every=10, device="cuda", max_steps=100000, gen_seed=0,
+                     cap=256):
+    """Training samples from plain runs (see the module docstring).  A run
+    that meets a non-physical state (no positivity limiter is applied) stops
+    there; its earlier samples are kept and the seed is recorded in SKIPPED.
     Returns (x bf16 [S][KP], y float [S], w float [S])."""
     g = torch.Generator(device="cpu").manual_seed(gen_seed)
     xs, ys, ws = [], [], []
@@ -149,29 +155,40 @@ def generate_samples(seeds, n=64, order=2, t_end=0.25, every=10, device="cuda", 
         plain = dg.problem_from_workload(wl, device=device)
         free = dg.problem_from_workload(wl, device=device, limiter=dg.LIM_NONE)
         state = dg.initial_state(plain, wl, limit=True)
+        u = torch.empty_like(state)  # fixed buffers: the captured step graphs stay valid
+        lim = torch.empty_like(state)
         t, k = 0.0, 0
         while t < t_end and k < max_steps:
-            if k % every == 0:
-                u = state.clone()
-                dt = plain.cfl_dt(u)
-                free.step(u, 0.0, 1.0, dt=dt, max_steps=1, allow_nonphysical=True)
-                lim = u.clone()
-                flags, _, _ = plain.limit(lim, want_margin=False)
-                x = features(plain, u, bf16=True)
-                f = flags.reshape(-1).to(torch.float32)
-                num = (lim - u).abs().sum(dim=(0, 1)).reshape(-1)
-                den = u.abs().sum(dim=(0, 1)).reshape(-1).clamp_min(1e-300)
-                wgt = (1.0 + num / den).to(torch.float32)
-                tr = torch.nonzero(f > 0.5).reshape(-1)
-                un = torch.nonzero(f < 0.5).reshape(-1)
-                if un.numel() > 0 and tr.numel() > 0:
-                    pick = torch.randperm(un.numel(), generator=g)[: tr.numel()].to(un.device)
-                    idx = torch.cat([tr, un[pick]])
-                    xs.append(x[idx])
-                    ys.append(f[idx])
-                    ws.append(wgt[idx])
-            t, steps = plain.step(state, t, t_end, max_steps=1)
-            k += 1
+            u.copy_(state)
+            dt = plain.cfl_dt(u)
+            free.step(u, 0.0, 1.0, dt=dt, max_steps=1, allow_nonphysical=True)
+            lim.copy_(u)
+            flags, _, _ = plain.limit(lim, want_margin=False)
+            x = features(plain, u, bf16=True)
+            f = flags.reshape(-1).to(torch.float32)
+            num = (lim - u).abs().sum(dim=(0, 1)).reshape(-1)
+            den = u.abs().sum(dim=(0, 1)).reshape(-1).clamp_min(1e-300)
+            wgt = (1.0 + num / den).to(torch.float32)
+            # finite samples only (bf16 exponent all ones = inf/nan)
+            ok = ((x & 0x7F80) != 0x7F80).all(dim=1) & torch.isfinite(wgt)
+            tr = torch.nonzero((f > 0.5) & ok).reshape(-1)
+            un = torch.nonzero((f < 0.5) & ok).reshape(-1)
+            m = min(tr.numel(), un.numel(), cap)
+            if m > 0:
+                pt = torch.randperm(tr.numel(), generator=g)[:m].to(tr.device)
+                pu = torch.randperm(un.numel(), generator=g)[:m].to(un.device)
+                idx = torch.cat([tr[pt], un[pu]])
+                xs.append(x[idx])
+                ys.append(f[idx])
+                ws.append(wgt[idx])
+            try:
+                t, steps = plain.step(state, t, t_end, max_steps=every)
+            except dg.DGError as e:
+                if e.code != dg.DG_ERR_NONPHYSICAL:
+                    raise
+                SKIPPED.append((seed, t))
+                break
+            k += steps
         plain.close()
         free.close()
     return torch.cat(xs), torch.cat(ys), torch.cat(ws)
@@ -195,3 +212,69 @@ def train(net, x, y, w, epochs=3, batch=4096, lr=1e-3, seed=0, log=None):
         if log:
             log(f"epoch {ep}: loss {hist[-1]:.5f}")
     return hist
+
+
+def _density_means(state, dim=2):
+    return (state[0, 0] / 2.0).double()
+
+
+def _average_down(fine_means, factor):
+    ny, nx = fine_means.shape
+    return fine_means.reshape(ny // factor, factor, nx // factor, factor).mean(dim=(1, 3))
+
+
+def evaluate(net, seeds, n=128, order=2, t_end=0.25, band=(0.2, 0.8), device="cuda", probe_every=50):
+    """Plain (TVB) vs learned runs of held-out problems: steps, troubled
+    fraction, flag disagreement with TVB on the plain trajectory, and the L1
+    error of the density means against the plain solution on the 2x-refined
+    mesh averaged down.  Returns a list of per-seed dicts."""
+    out = []
+    for seed in seeds:
+        wl = W.riemann2d(n=n, order=order, seed=seed, t_end=t_end)
+        res = {"seed": seed, "n": n}
+        finals = {}
+        for kind in ("plain", "learned"):
+            kw = {} if kind == "plain" else {"indicator": dg.IND_LEARNED}
+            prob = dg.problem_from_workload(wl, device=device, **kw)
+            if kind == "learned":
+                attach(prob, net, band)
+            state = dg.initial_state(prob, wl, limit=True)
+            prob.profile_read(reset=True)
+            torch.cuda.synchronize()
+            t, steps = prob.step(state, 0.0, t_end, allow_nonphysical=True)
+            res[kind + "_nonphysical"] = prob.status() != 0
+            _, troubled = prob.profile_read(reset=True)
+            res[kind + "_steps"] = steps
+            res[kind + "_troubled_fraction"] = troubled / max(1, 3 * wl.cells * steps)
+            finals[kind] = _density_means(state)
+            prob.close()
+        # disagreement of the two indicators along the plain trajectory
+        plain = dg.problem_from_workload(wl, device=device)
+        learn = dg.problem_from_workload(wl, device=device, indicator=dg.IND_LEARNED)
+        attach(learn, net, band)
+        state = dg.initial_state(plain, wl, limit=True)
+        t, dis, tot = 0.0, 0, 0
+        while t < t_end:
+            a = state.clone()
+            b = state.clone()
+            fa, _, _ = plain.limit(a, want_margin=False)
+            fb, _, _ = learn.limit(b, want_margin=False)
+            dis += int((fa != fb).sum().item())
+            tot += fa.numel()
+            t, _ = plain.step(state, t, t_end, max_steps=probe_every, allow_nonphysical=True)
+        res["flag_disagreement"] = dis / max(1, tot)
+        plain.close()
+        learn.close()
+        # reference: plain on the 2x-refined mesh, averaged down
+        wf = W.riemann2d(n=2 * n, order=order, seed=seed, t_end=t_end)
+        ref = dg.problem_from_workload(wf, device=device)
+        rs = dg.initial_state(ref, wf, limit=True)
+        ref.step(rs, 0.0, t_end, allow_nonphysical=True)
+        res["reference_nonphysical"] = ref.status() != 0
+        rmean = _average_down(_density_means(rs), 2)
+        ref.close()
+        for kind in ("plain", "learned"):
+            res[kind + "_L1"] = float((finals[kind] - rmean).abs().mean().item())
+        res["L1_learned_vs_plain"] = float((finals["learned"] - finals["plain"]).abs().mean().item())
+        out.append(res)
+    return out
