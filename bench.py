@@ -11,7 +11,6 @@ kernel profiling on (HIP events around every launch on the problem's stream),
 so the dominant kernel's average duration comes from the same region.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -22,12 +21,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-DOF updates/s, 2D Euler P2 (plain vs learned+batched) at equal L1"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1904_11147_amd", "csrc", "dg_kernels.hip")
+COPY_BYTES = 1 << 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage23_riemann2d_2048_q2.json")
-
-
-def kernel_hash():
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
 
 
 def traffic_for(bytes_alg):
@@ -37,16 +32,18 @@ def traffic_for(bytes_alg):
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256_16") != kernel_hash():
+    from paper_1904_11147_amd.profiling import kernel_source_hash
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(n_window=1024, seed=12345):
-    """The CPU oracle, as it stands, timed on one SSP-RK3 step of a
-    n_window^2 sub-block of the same problem (cells [512,1536)^2 of the
-    2048^2 mesh, i.e. [0.25,0.75]^2, which holds the quadrant corner), with
-    its own projection of the initial data."""
+def cpu_baseline(n_window=1024, seed=12345, min_seconds=10.0, max_steps=20):
+    """The CPU oracle, as it stands, timed on SSP-RK3 steps of a n_window^2
+    sub-block of the same problem (cells [512,1536)^2 of the 2048^2 mesh,
+    i.e. [0.25,0.75]^2, which holds the quadrant corner), with its own
+    projection of the initial data; steps are taken until at least
+    min_seconds have passed."""
     from oracle import oracle as O
     from paper_1904_11147_amd import workloads as W
     full = W.riemann2d(n=2048, order=2, seed=seed)
@@ -57,15 +54,17 @@ def cpu_baseline(n_window=1024, seed=12345):
                    bc=tuple(wl.bc), cfl=wl.cfl)
     r, _ = op.proj_nodes()
     U = op.limit(op.project(wl.point_values(r)))[0]
-    dt = op.cfl_dt(U)
+    steps = 0
     t0 = time.perf_counter()
-    op.step(U, dt)
+    while steps < max_steps and (steps == 0 or time.perf_counter() - t0 < min_seconds):
+        U = op.step(U, op.cfl_dt(U))
+        steps += 1
     el = time.perf_counter() - t0
     dofs = n_window * n_window * 36
-    return {"value": dofs / el, "unit": "cell-DOF updates/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"one SSP-RK3 step (3 residuals + 3 TVB/CSWENO passes) of the {n_window}x{n_window} "
-                      f"sub-block [0.25,0.75]^2 of the 2048^2 Q2 Euler Riemann problem, seed {seed}; "
-                      f"{el:.2f} s"}
+    return {"value": dofs * steps / el, "unit": "cell-DOF updates/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{steps} SSP-RK3 steps (each 3 residuals + 3 TVB/CSWENO passes, CFL dt) of the "
+                      f"{n_window}x{n_window} sub-block [0.25,0.75]^2 of the 2048^2 Q2 Euler Riemann problem, "
+                      f"seed {seed}; {el:.2f} s"}
 
 
 def main():
@@ -76,6 +75,9 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--seed", type=int, default=12345)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed region, run a plain 1 GiB device copy kernel three times "
+                         "(the known-size reference for rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -109,6 +111,14 @@ def main():
     torch.cuda.synchronize()
     el_graph = time.perf_counter() - g0
 
+    if args.copy_calibration:
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
     dofs = wl.dofs
     state_bytes = dofs * 8
     value = dofs * steps / el
@@ -139,7 +149,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_stage_2d<2,Euler,stage 2|3>",
+            "kernel": "k_stage_2d_euler_pair<2, stage 2|3>",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

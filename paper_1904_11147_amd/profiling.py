@@ -1,0 +1,126 @@
+"""Summaries of rocprofv3 output for the committed profiles.
+
+    python -m paper_1904_11147_amd.profiling stats  <kernel_stats.csv> --cmd "<command>" --out <summary.txt>
+    python -m paper_1904_11147_amd.profiling traffic --fetch <csv> --write <csv> --kernel <substring>
+            --copy-kernel <substring> --copy-bytes <B> --cmd "<command>" --out <traffic.json>
+
+`stats` shortens the kernel names of a `--kernel-trace --stats` CSV and keeps
+calls, total, average, min and max duration.  `traffic` turns two `--pmc`
+runs (FETCH_SIZE, then WRITE_SIZE, both in KiB per dispatch) into HBM bytes
+per launch of one kernel, each counter scaled by what it reads for a plain
+copy kernel that moves a known number of bytes (read once, written once).
+The result records the hash of the kernel source it was taken on, so that a
+reader can tell when the kernel has changed since.
+"""
+import argparse
+import csv
+import hashlib
+import json
+import os
+import re
+import statistics
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1904_11147_amd", "csrc", "dg_kernels.hip")
+
+
+def kernel_source_hash():
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def short_name(k):
+    k = k.replace("void ", "").replace("dg::(anonymous namespace)::", "").replace("(anonymous namespace)::", "")
+    k = re.sub(r"\(.*$", "", k)
+    return k[:110]
+
+
+def stats(path, cmd, out):
+    rows = list(csv.DictReader(open(path)))
+    lines = [f"# rocprofv3 kernel statistics", f"# command: {cmd}", "#",
+             f"{'kernel':<110} {'calls':>7} {'total_ms':>10} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
+    for r in rows:
+        lines.append(f"{short_name(r['Name']):<110} {int(r['Calls']):>7} {float(r['TotalDurationNs']) / 1e6:>10.3f} "
+                     f"{float(r['AverageNs']) / 1e3:>10.2f} {float(r['MinNs']) / 1e3:>10.2f} "
+                     f"{float(r['MaxNs']) / 1e3:>10.2f} {float(r['Percentage']):>6.2f}")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def _per_dispatch(path, counter):
+    """{kernel name: [value per dispatch]} of one counter (KiB per dispatch)."""
+    acc = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        key = (r["Kernel_Name"], r["Dispatch_Id"])
+        acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
+    res = {}
+    for (k, _), v in acc.items():
+        res.setdefault(k, []).append(v)
+    return res
+
+
+def _pick(d, pattern):
+    hits = [k for k in d if re.search(pattern, k)]
+    if not hits:
+        raise SystemExit(f"no kernel matching {pattern!r} among {sorted(map(short_name, d))}")
+    vals = [v for k in hits for v in d[k]]
+    return hits, vals
+
+
+def traffic(fetch, write, kernel, copy_kernel, copy_bytes, cmd, out):
+    f = _per_dispatch(fetch, "FETCH_SIZE")
+    w = _per_dispatch(write, "WRITE_SIZE")
+    _, cf = _pick(f, copy_kernel)
+    _, cw = _pick(w, copy_kernel)
+    kf_names, kf = _pick(f, kernel)
+    _, kw = _pick(w, kernel)
+    fetch_scale = copy_bytes / (statistics.median(cf) * 1024)
+    write_scale = copy_bytes / (statistics.median(cw) * 1024)
+    fetch_b = statistics.mean(kf) * 1024 * fetch_scale
+    write_b = statistics.mean(kw) * 1024 * write_scale
+    res = {
+        "kernel": short_name(kf_names[0]),
+        "kernel_source_sha256_16": kernel_source_hash(),
+        "dispatches": {"fetch": len(kf), "write": len(kw)},
+        "fetch_kib_per_launch_raw": statistics.mean(kf),
+        "write_kib_per_launch_raw": statistics.mean(kw),
+        "copy_kernel": short_name(_pick(f, copy_kernel)[0][0]),
+        "copy_bytes_each_way": copy_bytes,
+        "copy_fetch_kib_raw": statistics.median(cf),
+        "copy_write_kib_raw": statistics.median(cw),
+        "fetch_scale": fetch_scale,
+        "write_scale": write_scale,
+        "fetch_bytes_per_launch": fetch_b,
+        "write_bytes_per_launch": write_b,
+        "hbm_bytes_per_launch": fetch_b + write_b,
+        "command": cmd,
+    }
+    json.dump(res, open(out, "w"), indent=1)
+    print(json.dumps(res, indent=1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--cmd", required=True)
+    s.add_argument("--out", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--kernel", required=True, help="regular expression on the kernel name")
+    t.add_argument("--copy-kernel", required=True, help="regular expression on the kernel name")
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--cmd", required=True)
+    t.add_argument("--out", required=True)
+    a = ap.parse_args()
+    if a.what == "stats":
+        stats(a.csv, a.cmd, a.out)
+    else:
+        traffic(a.fetch, a.write, a.kernel, a.copy_kernel, a.copy_bytes, a.cmd, a.out)
+
+
+if __name__ == "__main__":
+    main()
