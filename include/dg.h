@@ -216,6 +216,68 @@ int dg_mlp_adam(float *master, float *adam_m, float *adam_v, float *grad, uint16
 int dg_set_learned(dg_problem *p, const uint16_t *w_bf16, const float *master, double band_lo, double band_hi,
                    float *prob);
 
+/* ------------------------------------------------------------------------
+ * Batched execution: n independent 2D Euler problems (any sizes, orders
+ * 1..3, boundary conditions and CFL numbers; one limiter and one indicator
+ * mode for all) advanced together, each with its own CFL time step
+ * (Section 2's scheme and Section 3's limiter applied to every instance as
+ * dg_step applies them to one).  A step of the batch is one SSP-RK3 step of
+ * every instance still short of its end time: per RK stage one persistent
+ * kernel per order walks a device-side queue of (instance, tile) work items,
+ * followed by the limiter pass of that stage; finished instances leave the
+ * queue on the device.  Each instance's results are identical, bit for bit,
+ * to dg_step on the same problem.
+ *
+ * Memory: the caller owns one device buffer `states` holding every
+ * instance's state (layout of dg_project, FP64) at element offsets
+ * offsets[i] (host int64 array, multiples of 32), and one workspace of
+ * dg_batch_workspace_bytes (256-byte aligned) that holds per-instance stage
+ * buffers (two state volumes each), scalars, descriptors, the work queues and
+ * the troubled-cell lists.  The library allocates nothing.
+ * ------------------------------------------------------------------------ */
+typedef struct dg_batch dg_batch;
+
+/* Workspace bytes for the n configurations cfgs[0..n-1] (n <= 4096; all 2D
+ * Euler; equal limiter and indicator; at most 2^31 - 1 cells in total). */
+int dg_batch_workspace_bytes(const dg_config *cfgs, int32_t n, size_t *bytes);
+
+/* Creates the batch on the current device and the given stream (NULL =
+ * default stream).  The workspace must stay valid until dg_batch_destroy. */
+int dg_batch_init(const dg_config *cfgs, int32_t n, void *workspace, size_t workspace_bytes, void *stream,
+                  dg_batch **out);
+
+int dg_batch_destroy(dg_batch *b);
+
+/* Times the stage kernel of every order present for each candidate tile
+ * height (rows marched per work item: 4, 8, 16, 32, 64; a tile is 30 columns
+ * wide) on the given states (a residual evaluation into the workspace; the
+ * states are not changed) and keeps the fastest per order for later
+ * dg_batch_step calls.  rows, tiles (host int32 [4], indexed by order: the
+ * tile height and the resulting tile count) and ms (host float [4], the best
+ * stage time) receive the choices and may be NULL.  Default height: 16. */
+int dg_batch_autotune(dg_batch *b, double *states, const int64_t *offsets, int32_t *rows, int32_t *tiles,
+                      float *ms);
+
+/* Sets the tile height of one order by hand. */
+int dg_batch_set_tiles(dg_batch *b, int32_t order, int32_t rows);
+
+/* Advances every instance i from t[i] (host double [n], updated) towards
+ * t_end[i] (host double [n]) by CFL time steps, at most max_steps steps each;
+ * steps (host int32 [n], may be NULL) receives the steps taken and status
+ * (host int32 [n], may be NULL) DG_OK or DG_ERR_NONPHYSICAL per instance (an
+ * instance that meets a non-physical state stops there).  troubled (host,
+ * may be NULL) receives the number of troubled cells flagged over all
+ * instances and limiter passes of the call.  Returns DG_ERR_NONPHYSICAL if
+ * any instance stopped that way. */
+int dg_batch_step(dg_batch *b, double *states, const int64_t *offsets, double *t, const double *t_end,
+                  int32_t max_steps, int32_t *steps, int32_t *status, int64_t *troubled);
+
+/* Weights of the learned indicator for the instances of one order (required
+ * for each order present when the batch uses DG_IND_LEARNED); as
+ * dg_set_learned. */
+int dg_batch_set_learned(dg_batch *b, int32_t order, const uint16_t *w_bf16, const float *master, double band_lo,
+                         double band_hi);
+
 #ifdef __cplusplus
 }
 #endif

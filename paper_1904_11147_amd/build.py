@@ -6,12 +6,12 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdg.so")
-SOURCES = ["dg_kernels.hip", "dg_tables.cpp", "dg_api.cpp"]
+SOURCES = ["dg_kernels.hip", "dg_tables.cpp", "dg_api.cpp", "dg_batch.cpp"]
 ARCH = os.environ.get("DG_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for all device code (see the design doc,
 # build notes); FP64 arithmetic is unaffected.
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=on"]
 
 
 def build(verbose=False):

@@ -38,19 +38,15 @@ struct dg_problem {
   int graph_cfl;
 };
 
-namespace {
-
-constexpr size_t kAlign = 256;
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-struct Layout {
-  size_t scalars, bufA, bufB, flags, margin, list, total;
-};
+// ---------------------------------------------------------------------------
+// Helpers shared with the batched API.
+// ---------------------------------------------------------------------------
+namespace dg {
 
 int num_vars(const dg_config *c) { return c->equation == DG_EQ_BURGERS ? 1 : c->dim + 2; }
 int num_modes(const dg_config *c) { return c->dim == 1 ? c->order + 1 : (c->order + 1) * (c->order + 1); }
 
-int validate(const dg_config *c) {
+int validate_config(const dg_config *c) {
   if (!c) return DG_ERR_INVALID_ARG;
   if (c->abi_version != DG_ABI_VERSION || c->reserved != 0) return DG_ERR_INVALID_ARG;
   if (c->dim != 1 && c->dim != 2) return DG_ERR_UNSUPPORTED;
@@ -74,6 +70,58 @@ int validate(const dg_config *c) {
   return DG_OK;
 }
 
+bool g_tables_ready[64];
+std::mutex g_tables_mu;
+
+int ensure_tables(int device) {
+  std::lock_guard<std::mutex> lk(g_tables_mu);
+  if (device < 0 || device >= 64) return DG_ERR_HIP;
+  if (g_tables_ready[device]) return DG_OK;
+  dg::OrderTables tabs[dg::kMaxN + 1];
+  std::memset(tabs, 0, sizeof(tabs));
+  for (int N = 1; N <= dg::kMaxN; ++N) {
+    int rc = dg::build_order_tables(N, &tabs[N]);
+    if (rc) return rc;
+  }
+  int rc = dg::upload_tables(tabs);
+  if (rc) return rc;
+  g_tables_ready[device] = true;
+  return DG_OK;
+}
+
+void fill_geometry(const dg_config *cfg, Geometry *g) {
+  g->nx = cfg->nx;
+  g->ny = cfg->ny;
+  for (int k = 0; k < 4; ++k) g->bc[k] = cfg->bc[k];
+  if (cfg->dim == 1) {  // the y-direction of a 1D problem is a single periodic row
+    g->bc[2] = g->bc[3] = DG_BC_PERIODIC;
+  }
+  g->hx = (cfg->x1 - cfg->x0) / cfg->nx;
+  g->hy = cfg->dim == 2 ? (cfg->y1 - cfg->y0) / cfg->ny : 1.0;
+  g->rhx = 2.0 / g->hx;
+  g->rhy = 2.0 / g->hy;
+  g->gamma = cfg->gamma;
+  g->tvb_Mx = cfg->tvb_M * g->hx * g->hx;
+  g->tvb_My = cfg->tvb_M * g->hy * g->hy;
+  g->eps = cfg->weno_eps;
+  g->negw_raw = cfg->negw_mode == DG_NEGW_RAW ? 1 : 0;
+  g->pad = 0;
+}
+
+}  // namespace dg
+
+using dg::num_modes;
+using dg::num_vars;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t scalars, bufA, bufB, flags, margin, list, total;
+};
+
 Layout layout(const dg_config *c) {
   Layout L;
   const size_t cells = (size_t)c->nx * c->ny;
@@ -93,25 +141,6 @@ Layout layout(const dg_config *c) {
   off += align_up(cells * sizeof(int32_t));
   L.total = off;
   return L;
-}
-
-bool g_tables_ready[64];
-std::mutex g_tables_mu;
-
-int ensure_tables(int device) {
-  std::lock_guard<std::mutex> lk(g_tables_mu);
-  if (device < 0 || device >= 64) return DG_ERR_HIP;
-  if (g_tables_ready[device]) return DG_OK;
-  dg::OrderTables tabs[dg::kMaxN + 1];
-  std::memset(tabs, 0, sizeof(tabs));
-  for (int N = 1; N <= dg::kMaxN; ++N) {
-    int rc = dg::build_order_tables(N, &tabs[N]);
-    if (rc) return rc;
-  }
-  int rc = dg::upload_tables(tabs);
-  if (rc) return rc;
-  g_tables_ready[device] = true;
-  return DG_OK;
 }
 
 int hip_ok(hipError_t e) { return e == hipSuccess ? DG_OK : DG_ERR_HIP; }
@@ -209,7 +238,7 @@ extern "C" {
 
 int dg_workspace_bytes(const dg_config *cfg, size_t *bytes) {
   if (!bytes) return DG_ERR_INVALID_ARG;
-  int rc = validate(cfg);
+  int rc = dg::validate_config(cfg);
   if (rc) return rc;
   *bytes = layout(cfg).total;
   return DG_OK;
@@ -218,13 +247,13 @@ int dg_workspace_bytes(const dg_config *cfg, size_t *bytes) {
 int dg_init(const dg_config *cfg, void *workspace, size_t workspace_bytes, void *stream, dg_problem **out) {
   if (!out) return DG_ERR_INVALID_ARG;
   *out = nullptr;
-  int rc = validate(cfg);
+  int rc = dg::validate_config(cfg);
   if (rc) return rc;
   Layout L = layout(cfg);
   if (!workspace || workspace_bytes < L.total || ((uintptr_t)workspace % kAlign) != 0) return DG_ERR_WORKSPACE;
   int device = 0;
   if (hipGetDevice(&device) != hipSuccess) return DG_ERR_HIP;
-  rc = ensure_tables(device);
+  rc = dg::ensure_tables(device);
   if (rc) return rc;
   dg_problem *p = new (std::nothrow) dg_problem();
   if (!p) return DG_ERR_INVALID_ARG;
@@ -238,23 +267,9 @@ int dg_init(const dg_config *cfg, void *workspace, size_t workspace_bytes, void 
   c.dim = cfg->dim;
   c.eq = cfg->equation;
   c.N = cfg->order;
-  c.nv = num_vars(cfg);
-  c.nm = num_modes(cfg);
-  c.geo.nx = cfg->nx;
-  c.geo.ny = cfg->ny;
-  for (int k = 0; k < 4; ++k) c.geo.bc[k] = cfg->bc[k];
-  if (cfg->dim == 1) {  // the y-direction of a 1D problem is a single periodic row
-    c.geo.bc[2] = c.geo.bc[3] = DG_BC_PERIODIC;
-  }
-  c.geo.hx = (cfg->x1 - cfg->x0) / cfg->nx;
-  c.geo.hy = cfg->dim == 2 ? (cfg->y1 - cfg->y0) / cfg->ny : 1.0;
-  c.geo.rhx = 2.0 / c.geo.hx;
-  c.geo.rhy = 2.0 / c.geo.hy;
-  c.geo.gamma = cfg->gamma;
-  c.geo.tvb_Mx = cfg->tvb_M * c.geo.hx * c.geo.hx;
-  c.geo.tvb_My = cfg->tvb_M * c.geo.hy * c.geo.hy;
-  c.geo.eps = cfg->weno_eps;
-  c.geo.negw_raw = cfg->negw_mode == DG_NEGW_RAW ? 1 : 0;
+  c.nv = dg::num_vars(cfg);
+  c.nm = dg::num_modes(cfg);
+  dg::fill_geometry(cfg, &c.geo);
   c.stream = stream;
   c.sc = (DevScalars *)(ws + L.scalars);
   c.bufA = (double *)(ws + L.bufA);

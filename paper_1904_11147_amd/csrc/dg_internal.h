@@ -90,6 +90,63 @@ struct LaunchCtx {
   double band_lo, band_hi;
 };
 
+// ---------------------------------------------------------------------------
+// Batched execution: many independent 2D Euler meshes of any size and order,
+// each with its own time step, advanced together.
+// ---------------------------------------------------------------------------
+constexpr int kBatchMax = 4096;  // instances per batch
+
+// One instance, in device memory.
+struct BatchInst {
+  Geometry geo;
+  double *u;           // state (caller-owned, inside the batch's states buffer)
+  double *A, *B;       // stage buffers (workspace)
+  DevScalars *sc;      // this instance's scalars (workspace)
+  int32_t order;       // N
+  int32_t rows;        // rows per stage-kernel tile
+  int32_t tiles_x, tiles_y;
+  int32_t segs;        // 64-cell row segments (indicator work items)
+  int32_t indicator;   // DG_IND_*
+  double cfl;
+};
+
+// Work queue of the instances of one order, rebuilt on the device after every
+// time-step decision.  Entries are the active instances in index order with
+// inclusive prefix sums of their stage tiles and indicator segments.
+struct BatchQueue {
+  int32_t n_active, total_tiles, total_segs, pad0;
+  int32_t count[4];  // troubled-list length of the limiter pass after stage 1, 2, 3
+  int32_t inst[kBatchMax];
+  int32_t tile_end[kBatchMax];
+  int32_t seg_end[kBatchMax];
+};
+
+struct BatchLearned {  // learned indicator of one order (null weights: not set)
+  const uint16_t *W;
+  const float *M;
+  float band_lo, band_hi;
+};
+
+// Work of one batched call, described to the kernel TU.
+struct BatchCtx {
+  int n;                 // instances
+  BatchInst *inst;       // device [n]
+  BatchQueue *queue;     // device [kMaxN + 1], indexed by order
+  int32_t *active;       // device: instances still advancing after the last decision
+  long long *list[kMaxN + 1];  // device, per order: troubled entries (instance << 32 | cell)
+  void *stream;
+  int limiter, indicator;  // one of each for the whole batch
+  int grid_cap;          // blocks of list-driven and indicator kernels
+  BatchLearned learned[kMaxN + 1];
+};
+
+// Host helpers of the C-ABI (dg_api.cpp).
+int validate_config(const dg_config *c);
+int ensure_tables(int device);
+void fill_geometry(const dg_config *cfg, Geometry *g);
+int num_vars(const dg_config *c);
+int num_modes(const dg_config *c);
+
 // Kernel-TU entry points (host functions, enqueue only).
 int launch_residual(const LaunchCtx &c, const double *u, double *out);
 int launch_stage(const LaunchCtx &c, int stage, const double *u, const double *un, double *out, bool want_speed);
@@ -105,5 +162,12 @@ int launch_mlp_forward(const uint16_t *x, int n, int F, const uint16_t *W, const
 int launch_mlp_gradient(const uint16_t *x, const float *y, const float *w, int n, int F, const uint16_t *W,
                         const float *M, float *G, uint16_t *dh1, float *loss, void *stream);
 int launch_mlp_adam(float *M, float *m1, float *m2, float *G, uint16_t *W, int F, float lr, int step, void *stream);
+
+// Batched execution.  finalize = 0: rebuild the queues only (call start).
+int batch_launch_decide(const BatchCtx &b, int finalize);
+int batch_launch_speed(const BatchCtx &b, int order);
+// stage 0: residual of u into A (used to time tile shapes); 1..3: SSP-RK3 stages
+int batch_launch_stage(const BatchCtx &b, int order, int stage, int grid);
+int batch_launch_limit(const BatchCtx &b, int order, int slot);
 
 }  // namespace dg

@@ -830,20 +830,23 @@ __device__ inline void llf_pair(double l0, double l1, double r0, double r1, bool
   F1 = 0.5 * (fl1 + fr1) - 0.5 * al * (r1 - l1);
 }
 
+// One tile: columns [bx*kPairStrip, +kPairStrip) of rows [by*rows, +rows),
+// marched row by row by one wavefront.  `row` is the wavefront's LDS
+// staging area of 2 (N+1)^2 64 doubles (the current row's modes of each
+// lane's two variables, [k*NM+q][lane]).
 template <int N, int STAGE>
-__global__ __launch_bounds__(64, 2) void k_stage_2d_euler_pair(StageArgs a, int rows_per_block) {
+__device__ __forceinline__ void euler_pair_tile(const StageArgs &a, int bx, int by, int rows_per_block,
+                                                double *__restrict__ row) {
   constexpr int NP = N + 1, NM = NP * NP;
-  // the current row's modes of this lane's two variables, [k*NM+q][lane]
-  __shared__ double row[2 * NM * 64];
   const OrderTables &T = c_tab[N];
   const Geometry &g = a.geo;
   if (STAGE != 0 && a.sc->done) return;
   const int lane = threadIdx.x, slot = lane >> 1, half = lane & 1;
   const bool h1 = half != 0;
-  int col = blockIdx.x * kPairStrip + slot - 1;
+  int col = bx * kPairStrip + slot - 1;
   if (col > g.nx) col = g.nx;
   const bool owner = slot >= 1 && slot <= kPairStrip && col < g.nx;
-  const int j0 = blockIdx.y * rows_per_block;
+  const int j0 = by * rows_per_block;
   const int j1 = min(j0 + rows_per_block, g.ny);
   const long plane = (long)g.nx * g.ny;
   const double dt = STAGE == 0 ? 0.0 : a.sc->dt;
@@ -1074,6 +1077,12 @@ __global__ __launch_bounds__(64, 2) void k_stage_2d_euler_pair(StageArgs a, int 
   }
 }
 
+template <int N, int STAGE>
+__global__ __launch_bounds__(64, 2) void k_stage_2d_euler_pair(StageArgs a, int rows_per_block) {
+  __shared__ double row[2 * (N + 1) * (N + 1) * 64];
+  euler_pair_tile<N, STAGE>(a, blockIdx.x, blockIdx.y, rows_per_block, row);
+}
+
 // ---------------------------------------------------------------------------
 // Spectral radius of cell means (first step of a dg_step call, dg_cfl_dt).
 // ---------------------------------------------------------------------------
@@ -1108,8 +1117,8 @@ __global__ __launch_bounds__(kBlock) void k_speed(const double *__restrict__ u, 
 
 // One thread: time step of the CFL rule (or the fixed one), clipped at
 // t_end; marks the run done; clears the per-step accumulators.
-__global__ void k_dt_finalize(DevScalars *sc, int dim, double cfl, double hx, double hy) {
-  if (threadIdx.x != 0 || sc->done) return;
+__device__ inline void decide_dt(DevScalars *sc, int dim, double cfl, double hx, double hy) {
+  if (sc->done) return;
   if (sc->steps >= sc->max_steps || !(sc->t < sc->t_end)) {
     sc->done = 1;
     sc->dt = 0.0;
@@ -1139,6 +1148,10 @@ __global__ void k_dt_finalize(DevScalars *sc, int dim, double cfl, double hx, do
   sc->smax[0] = 0ull;
   sc->smax[1] = 0ull;
   sc->count[0] = sc->count[1] = sc->count[2] = 0;
+}
+
+__global__ void k_dt_finalize(DevScalars *sc, int dim, double cfl, double hx, double hy) {
+  if (threadIdx.x == 0) decide_dt(sc, dim, cfl, hx, hy);
 }
 
 __global__ void k_reset(DevScalars *sc, int what) {
@@ -1343,122 +1356,127 @@ __device__ inline double interval_mean(const OrderTables &T, int k, int n) {
   return T.sub[k < N ? k : k - N - 1][n];
 }
 
+// Reconstruction of variable v of the troubled cell `cell` from the
+// pre-limit state u; the non-mean modes are written to `side`.
 template <int N, int EQ, int DIM>
-__global__ __launch_bounds__(kBlock) void k_csweno(LimitArgs a) {
-  constexpr int NP = N + 1, NM = DIM == 1 ? NP : NP * NP, NV = Phys<EQ, DIM>::NV;
+__device__ inline void csweno_cell(const double *__restrict__ u, double *__restrict__ side, const Geometry &g,
+                                   long cell, int v) {
+  constexpr int NP = N + 1, NM = DIM == 1 ? NP : NP * NP;
   constexpr int NS = 2 * N + 1, NG = num_points<N>();
   const OrderTables &T = c_tab[N];
-  const Geometry &g = a.geo;
-  if (a.check_done && a.sc->done) return;
   const long plane = (long)g.nx * g.ny;
-  const long total = (long)(*a.count) * NV;
   const bool raw = g.negw_raw != 0;
-  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-    const int v = (int)(t % NV);
-    const long cell = a.list[t / NV];
-    const int i = (int)(cell % g.nx), j = (int)(cell / g.nx);
-    if (DIM == 1) {
-      double st[NS];
+  const int i = (int)(cell % g.nx), j = (int)(cell / g.nx);
+  if (DIM == 1) {
+    double st[NS];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        CellIdx ci = map_cell(g, i + c - 1, 0);
-        double md[NP];
+    for (int c = 0; c < 3; ++c) {
+      CellIdx ci = map_cell(g, i + c - 1, 0);
+      double md[NP];
 #pragma unroll
-        for (int n = 0; n < NP; ++n) {
-          double s = a.u[(long)(v * NM + n) * plane + ci.idx];
-          md[n] = (ci.fx && (n & 1)) ? -s : s;
-        }
-        const int k0 = c == 0 ? 0 : (c == 1 ? N : N + 1), k1 = c == 0 ? N : (c == 1 ? N + 1 : NS);
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-          if (k < k0 || k >= k1) continue;
-          double s = 0.0;
-#pragma unroll
-          for (int n = 0; n < NP; ++n) s += md[n] * interval_mean<N>(T, k, n);
-          st[k] = s;
-        }
+      for (int n = 0; n < NP; ++n) {
+        double s = u[(long)(v * NM + n) * plane + ci.idx];
+        md[n] = (ci.fx && (n & 1)) ? -s : s;
       }
-      double uG[NG];
-      weno_row<N>(T, st, uG, g.eps, raw);
+      const int k0 = c == 0 ? 0 : (c == 1 ? N : N + 1), k1 = c == 0 ? N : (c == 1 ? N + 1 : NS);
 #pragma unroll
-      for (int n = 1; n < NP; ++n) {
+      for (int k = 0; k < NS; ++k) {
+        if (k < k0 || k >= k1) continue;
         double s = 0.0;
 #pragma unroll
-        for (int G = 0; G < NG; ++G) s += T.wg[G] * uG[G] * T.bg[n][G];
-        a.side[(long)(v * NM + n) * plane + cell] = s;
-      }
-    } else {
-      // (2N+1)^2 sub-rectangle means of the 3x3 block, [iy][ix]
-      double st[NS][NS];
-#pragma unroll
-      for (int cy = 0; cy < 3; ++cy)
-#pragma unroll
-        for (int cx = 0; cx < 3; ++cx) {
-          CellIdx ci = map_cell(g, i + cx - 1, j + cy - 1);
-          double md[NM];
-#pragma unroll
-          for (int q = 0; q < NM; ++q) {
-            int m = q % NP, n = q / NP;
-            double s = a.u[(long)(v * NM + q) * plane + ci.idx];
-            bool flip = (ci.fx && (m & 1)) != (ci.fy && (n & 1));
-            md[q] = flip ? -s : s;
-          }
-          const int x0 = cx == 0 ? 0 : (cx == 1 ? N : N + 1), x1 = cx == 0 ? N : (cx == 1 ? N + 1 : NS);
-          const int y0 = cy == 0 ? 0 : (cy == 1 ? N : N + 1), y1 = cy == 0 ? N : (cy == 1 ? N + 1 : NS);
-#pragma unroll
-          for (int ix = 0; ix < NS; ++ix) {
-            if (ix < x0 || ix >= x1) continue;
-            double tn[NP];
-#pragma unroll
-            for (int n = 0; n < NP; ++n) {
-              double s = 0.0;
-#pragma unroll
-              for (int m = 0; m < NP; ++m) s += md[m + NP * n] * interval_mean<N>(T, ix, m);
-              tn[n] = s;
-            }
-#pragma unroll
-            for (int iy = 0; iy < NS; ++iy) {
-              if (iy < y0 || iy >= y1) continue;
-              double s = 0.0;
-#pragma unroll
-              for (int n = 0; n < NP; ++n) s += tn[n] * interval_mean<N>(T, iy, n);
-              st[iy][ix] = s;
-            }
-          }
-        }
-      // x-sweeps: y-interval means at the x-points
-      double vy[NG][NS];
-#pragma unroll
-      for (int iy = 0; iy < NS; ++iy) {
-        double r[NG];
-        weno_row<N>(T, st[iy], r, g.eps, raw);
-#pragma unroll
-        for (int G = 0; G < NG; ++G) vy[G][iy] = r[G];
-      }
-      // y-sweeps at every x-point, then the tensor projection
-      double s[NG][NP];  // s[G][n] = sum_H wg[H] u(G,H) psi_n(y_H)
-#pragma unroll
-      for (int G = 0; G < NG; ++G) {
-        double u[NG];
-        weno_row<N>(T, vy[G], u, g.eps, raw);
-#pragma unroll
-        for (int n = 0; n < NP; ++n) {
-          double acc = 0.0;
-#pragma unroll
-          for (int H = 0; H < NG; ++H) acc += T.wg[H] * u[H] * T.bg[n][H];
-          s[G][n] = acc;
-        }
-      }
-#pragma unroll
-      for (int q = 1; q < NM; ++q) {
-        const int m = q % NP, n = q / NP;
-        double acc = 0.0;
-#pragma unroll
-        for (int G = 0; G < NG; ++G) acc += T.wg[G] * T.bg[m][G] * s[G][n];
-        a.side[(long)(v * NM + q) * plane + cell] = acc;
+        for (int n = 0; n < NP; ++n) s += md[n] * interval_mean<N>(T, k, n);
+        st[k] = s;
       }
     }
+    double uG[NG];
+    weno_row<N>(T, st, uG, g.eps, raw);
+#pragma unroll
+    for (int n = 1; n < NP; ++n) {
+      double s = 0.0;
+#pragma unroll
+      for (int G = 0; G < NG; ++G) s += T.wg[G] * uG[G] * T.bg[n][G];
+      side[(long)(v * NM + n) * plane + cell] = s;
+    }
+  } else {
+    // (2N+1)^2 sub-rectangle means of the 3x3 block, [iy][ix]
+    double st[NS][NS];
+#pragma unroll
+    for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+      for (int cx = 0; cx < 3; ++cx) {
+        CellIdx ci = map_cell(g, i + cx - 1, j + cy - 1);
+        double md[NM];
+#pragma unroll
+        for (int q = 0; q < NM; ++q) {
+          int m = q % NP, n = q / NP;
+          double s = u[(long)(v * NM + q) * plane + ci.idx];
+          bool flip = (ci.fx && (m & 1)) != (ci.fy && (n & 1));
+          md[q] = flip ? -s : s;
+        }
+        const int x0 = cx == 0 ? 0 : (cx == 1 ? N : N + 1), x1 = cx == 0 ? N : (cx == 1 ? N + 1 : NS);
+        const int y0 = cy == 0 ? 0 : (cy == 1 ? N : N + 1), y1 = cy == 0 ? N : (cy == 1 ? N + 1 : NS);
+#pragma unroll
+        for (int ix = 0; ix < NS; ++ix) {
+          if (ix < x0 || ix >= x1) continue;
+          double tn[NP];
+#pragma unroll
+          for (int n = 0; n < NP; ++n) {
+            double s = 0.0;
+#pragma unroll
+            for (int m = 0; m < NP; ++m) s += md[m + NP * n] * interval_mean<N>(T, ix, m);
+            tn[n] = s;
+          }
+#pragma unroll
+          for (int iy = 0; iy < NS; ++iy) {
+            if (iy < y0 || iy >= y1) continue;
+            double s = 0.0;
+#pragma unroll
+            for (int n = 0; n < NP; ++n) s += tn[n] * interval_mean<N>(T, iy, n);
+            st[iy][ix] = s;
+          }
+        }
+      }
+    // x-sweeps: y-interval means at the x-points
+    double vy[NG][NS];
+#pragma unroll
+    for (int iy = 0; iy < NS; ++iy) {
+      double r[NG];
+      weno_row<N>(T, st[iy], r, g.eps, raw);
+#pragma unroll
+      for (int G = 0; G < NG; ++G) vy[G][iy] = r[G];
+    }
+    // y-sweeps at every x-point, then the tensor projection
+    double s[NG][NP];  // s[G][n] = sum_H wg[H] u(G,H) psi_n(y_H)
+#pragma unroll
+    for (int G = 0; G < NG; ++G) {
+      double u[NG];
+      weno_row<N>(T, vy[G], u, g.eps, raw);
+#pragma unroll
+      for (int n = 0; n < NP; ++n) {
+        double acc = 0.0;
+#pragma unroll
+        for (int H = 0; H < NG; ++H) acc += T.wg[H] * u[H] * T.bg[n][H];
+        s[G][n] = acc;
+      }
+    }
+#pragma unroll
+    for (int q = 1; q < NM; ++q) {
+      const int m = q % NP, n = q / NP;
+      double acc = 0.0;
+#pragma unroll
+      for (int G = 0; G < NG; ++G) acc += T.wg[G] * T.bg[m][G] * s[G][n];
+      side[(long)(v * NM + q) * plane + cell] = acc;
+    }
   }
+}
+
+template <int N, int EQ, int DIM>
+__global__ __launch_bounds__(kBlock) void k_csweno(LimitArgs a) {
+  constexpr int NV = Phys<EQ, DIM>::NV;
+  if (a.check_done && a.sc->done) return;
+  const long total = (long)(*a.count) * NV;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x)
+    csweno_cell<N, EQ, DIM>(a.u, a.side, a.geo, a.list[t / NV], (int)(t % NV));
 }
 
 template <int NM, int NV>
@@ -1476,6 +1494,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(LimitArgs a, double *dst) {
 }
 
 #include "dg_mlp.hpp"
+#include "dg_batch.hpp"
 
 // ---------------------------------------------------------------------------
 // L2 projection of point values (rows j0..j0+nrows-1).
@@ -1721,6 +1740,81 @@ int launch_mlp_adam(float *M, float *m1, float *m2, float *G, uint16_t *W, int F
   hipLaunchKernelGGL(k_mlp_adam, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, (hipStream_t)stream, M,
                      m1, m2, G, W, lay, lr, step);
   return check_launch();
+}
+
+// ---------------------------------------------------------------------------
+// Batched execution launchers.
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename F>
+int order_dispatch(int order, F &&f) {
+  switch (order) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    default: return DG_ERR_UNSUPPORTED;
+  }
+  return check_launch();
+}
+
+}  // namespace
+
+int batch_launch_decide(const BatchCtx &b, int finalize) {
+  hipLaunchKernelGGL(k_batch_decide, dim3(1), dim3(1024), 0, (hipStream_t)b.stream, b.inst, b.n, b.queue, b.active,
+                     finalize);
+  return check_launch();
+}
+
+int batch_launch_speed(const BatchCtx &b, int order) {
+  return order_dispatch(order, [&](auto NN) {
+    hipLaunchKernelGGL((k_batch_speed<decltype(NN)::value>), dim3(b.grid_cap), dim3(64), 0, (hipStream_t)b.stream,
+                       b.inst, b.queue + order);
+  });
+}
+
+int batch_launch_stage(const BatchCtx &b, int order, int stage, int grid) {
+  if (stage < 0 || stage > 3 || grid < 1) return DG_ERR_INVALID_ARG;
+  return order_dispatch(order, [&](auto NN) {
+    constexpr int n = decltype(NN)::value;
+    const hipStream_t st = (hipStream_t)b.stream;
+    const BatchQueue *q = b.queue + order;
+    if (stage == 0) hipLaunchKernelGGL((k_batch_stage<n, 0>), dim3(grid), dim3(64), 0, st, b.inst, q);
+    else if (stage == 1) hipLaunchKernelGGL((k_batch_stage<n, 1>), dim3(grid), dim3(64), 0, st, b.inst, q);
+    else if (stage == 2) hipLaunchKernelGGL((k_batch_stage<n, 2>), dim3(grid), dim3(64), 0, st, b.inst, q);
+    else hipLaunchKernelGGL((k_batch_stage<n, 3>), dim3(grid), dim3(64), 0, st, b.inst, q);
+  });
+}
+
+int batch_launch_limit(const BatchCtx &b, int order, int slot) {
+  if (slot < 0 || slot > 2) return DG_ERR_INVALID_ARG;
+  if (b.indicator == DG_IND_LEARNED && !b.learned[order].W) return DG_ERR_INVALID_ARG;
+  return order_dispatch(order, [&](auto NN) {
+    constexpr int n = decltype(NN)::value;
+    const hipStream_t st = (hipStream_t)b.stream;
+    BatchQueue *q = b.queue + order;
+    long long *list = b.list[order];
+    const BatchLearned L = b.learned[order];
+    auto go = [&](auto SL) {
+      constexpr int s = decltype(SL)::value;
+      if (b.indicator == DG_IND_LEARNED)
+        hipLaunchKernelGGL((k_batch_indicator<n, s, DG_IND_LEARNED>), dim3(b.grid_cap), dim3(64), 0, st, b.inst, q,
+                           list, L);
+      else if (b.indicator == DG_IND_ALL)
+        hipLaunchKernelGGL((k_batch_indicator<n, s, DG_IND_ALL>), dim3(4 * b.grid_cap), dim3(64), 0, st, b.inst, q,
+                           list, L);
+      else
+        hipLaunchKernelGGL((k_batch_indicator<n, s, DG_IND_TVB>), dim3(4 * b.grid_cap), dim3(64), 0, st, b.inst, q,
+                           list, L);
+      if (b.limiter == DG_LIM_CSWENO) {
+        hipLaunchKernelGGL((k_batch_csweno<n, s>), dim3(b.grid_cap), dim3(kBlock), 0, st, b.inst, q, list);
+        hipLaunchKernelGGL((k_batch_scatter<n, s>), dim3(b.grid_cap), dim3(kBlock), 0, st, b.inst, q, list);
+      }
+    };
+    if (slot == 0) go(std::integral_constant<int, 0>{});
+    else if (slot == 1) go(std::integral_constant<int, 1>{});
+    else go(std::integral_constant<int, 2>{});
+  });
 }
 
 }  // namespace dg

@@ -408,21 +408,18 @@ struct LearnedArgs {
   float *prob;  // may be null: per-cell probability
 };
 
+// Network probabilities of the 64 cells (i0 + lane, j) of one row segment
+// (columns beyond the mesh repeat the last one); returns this lane's p.  One
+// wavefront; feat/scratch are its LDS areas.
 template <int N, int EQ>
-__global__ __launch_bounds__(64) void k_indicator_learned(LimitArgs a, LearnedArgs L) {
+__device__ inline float learned_probability(const double *__restrict__ u, const Geometry &g, int i0, int j,
+                                            const LearnedArgs &L, uint16_t *feat, uint16_t *scratch, float *zs) {
   constexpr int NM = (N + 1) * (N + 1), NV = Phys<EQ, 2>::NV, F = 5 * NM * NV, KP = (F + 15) / 16 * 16;
-  __shared__ uint16_t feat[64 * KP];
-  __shared__ uint16_t scratch[16 * kHidden];
-  __shared__ float zs[64];
-  const Geometry &g = a.geo;
-  if (a.check_done && a.sc->done) return;
   const int lane = threadIdx.x;
-  const int i = blockIdx.x * 64 + lane, j = blockIdx.y;
-  const bool active = i < g.nx && j < g.ny;
-  const long cell = (long)j * g.nx + i;
+  const int i = i0 + lane;
 #pragma unroll 1
   for (int v = 0; v < NV; ++v)
-    cell_features<N, NV>(a.u, g, active ? i : g.nx - 1, j, v, feat + lane * KP + v * 5 * NM, nullptr);
+    cell_features<N, NV>(u, g, i < g.nx ? i : g.nx - 1, j, v, feat + lane * KP + v * 5 * NM, nullptr);
   for (int k = F; k < KP; ++k) feat[lane * KP + k] = 0;
   __syncthreads();
   const int r = lane & 15, gq = lane >> 4;
@@ -437,10 +434,27 @@ __global__ __launch_bounds__(64) void k_indicator_learned(LimitArgs a, LearnedAr
       for (int q = 0; q < 4; ++q) zs[16 * t + 4 * gq + q] = z[q];
   }
   __syncthreads();
+  const float p = 1.f / (1.f + __expf(-zs[lane]));
+  __syncthreads();  // feat and zs are reused by the next segment
+  return p;
+}
+
+template <int N, int EQ>
+__global__ __launch_bounds__(64) void k_indicator_learned(LimitArgs a, LearnedArgs L) {
+  constexpr int NM = (N + 1) * (N + 1), NV = Phys<EQ, 2>::NV, F = 5 * NM * NV, KP = (F + 15) / 16 * 16;
+  __shared__ uint16_t feat[64 * KP];
+  __shared__ uint16_t scratch[16 * kHidden];
+  __shared__ float zs[64];
+  const Geometry &g = a.geo;
+  if (a.check_done && a.sc->done) return;
+  const int lane = threadIdx.x;
+  const int i = blockIdx.x * 64 + lane, j = blockIdx.y;
+  const bool active = i < g.nx && j < g.ny;
+  const long cell = (long)j * g.nx + i;
+  const float p = learned_probability<N, EQ>(a.u, g, blockIdx.x * 64, j, L, feat, scratch, zs);
   bool flag = false;
   double mg = INFINITY;
   if (active) {
-    const float p = 1.f / (1.f + __expf(-zs[lane]));
     if (L.prob) L.prob[cell] = p;
     if (a.ovr) flag = a.ovr[cell] != 0;
     else if (p > L.band_hi) flag = true;

@@ -28,7 +28,9 @@ NEGW_SPLIT, NEGW_RAW = 0, 1
 # every symbol include/dg.h declares
 EXPORTS = ("dg_workspace_bytes", "dg_init", "dg_destroy", "dg_proj_nodes", "dg_project", "dg_residual",
            "dg_limit", "dg_cfl_dt", "dg_step", "dg_status", "dg_strerror", "dg_profile_enable", "dg_profile_read",
-           "dg_mlp_layout", "dg_mlp_features", "dg_mlp_forward", "dg_mlp_gradient", "dg_mlp_adam", "dg_set_learned")
+           "dg_mlp_layout", "dg_mlp_features", "dg_mlp_forward", "dg_mlp_gradient", "dg_mlp_adam", "dg_set_learned",
+           "dg_batch_workspace_bytes", "dg_batch_init", "dg_batch_destroy", "dg_batch_autotune", "dg_batch_set_tiles",
+           "dg_batch_step", "dg_batch_set_learned")
 PROF_KINDS = ("stage1", "stage23", "limiter", "dt")
 
 
@@ -97,6 +99,13 @@ def lib():
             "dg_mlp_gradient": [vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp],
             "dg_mlp_adam": [vp, vp, vp, vp, vp, i32, ctypes.c_float, i32, vp],
             "dg_set_learned": [vp, vp, vp, d, d, vp],
+            "dg_batch_workspace_bytes": [P(Config), i32, P(ctypes.c_size_t)],
+            "dg_batch_init": [P(Config), i32, vp, ctypes.c_size_t, vp, P(vp)],
+            "dg_batch_destroy": [vp],
+            "dg_batch_autotune": [vp, vp, P(ctypes.c_int64), P(i32), P(i32), P(ctypes.c_float)],
+            "dg_batch_set_tiles": [vp, i32, i32],
+            "dg_batch_step": [vp, vp, P(ctypes.c_int64), P(d), P(d), i32, P(i32), P(i32), P(ctypes.c_int64)],
+            "dg_batch_set_learned": [vp, i32, vp, vp, d, d],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -292,3 +301,128 @@ def initial_state(prob, wl, limit=True, rows_per_chunk=None):
     if limit:
         prob.limit(state, want_margin=False)
     return state
+
+
+class Batch:
+    """Independent 2D Euler problems of any sizes and orders advanced together
+    (dg_batch_*): one states buffer holds every instance at 32-element aligned
+    offsets; `view(i)` is instance i's [4][(N+1)^2][ny][nx] state."""
+
+    def __init__(self, cfgs, device="cuda", stream=None):
+        import numpy as np
+        self.n = len(cfgs)
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
+        self.cfgs = [dict(c) for c in cfgs]
+        arr = (Config * self.n)(*[make_config(**c) for c in cfgs])
+        self._cfg_arr = arr
+        self.shapes = []
+        offs, o = [], 0
+        for c in arr:
+            shp = (4, (c.order + 1) ** 2, c.ny, c.nx)
+            self.shapes.append(shp)
+            offs.append(o)
+            o += (int(np.prod(shp)) + 31) // 32 * 32
+        self.offsets = np.array(offs, dtype=np.int64)
+        self._off_c = (ctypes.c_int64 * self.n)(*offs)
+        nbytes = ctypes.c_size_t()
+        rc = lib().dg_batch_workspace_bytes(arr, self.n, ctypes.byref(nbytes))
+        if rc:
+            raise DGError(rc, "dg_batch_workspace_bytes")
+        with torch.cuda.device(self.device):
+            self.states = torch.zeros(max(o, 1), dtype=torch.float64, device=self.device)
+            self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            handle = ctypes.c_void_p()
+            rc = lib().dg_batch_init(arr, self.n, ctypes.c_void_p(self.workspace.data_ptr()), nbytes.value,
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle))
+        if rc:
+            raise DGError(rc, "dg_batch_init")
+        self._h = handle
+        self._learned = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def view(self, i):
+        import numpy as np
+        shp = self.shapes[i]
+        o = int(self.offsets[i])
+        return self.states[o:o + int(np.prod(shp))].view(shp)
+
+    def dofs(self, active=None):
+        import numpy as np
+        idx = range(self.n) if active is None else [i for i in range(self.n) if active[i]]
+        return int(sum(np.prod(self.shapes[i]) for i in idx))
+
+    def autotune(self):
+        """{order: (rows, tiles, ms)} of the orders present."""
+        rows = (ctypes.c_int32 * 4)()
+        tiles = (ctypes.c_int32 * 4)()
+        ms = (ctypes.c_float * 4)()
+        rc = lib().dg_batch_autotune(self._h, _ptr(self.states), self._off_c, rows, tiles, ms)
+        if rc:
+            raise DGError(rc, "dg_batch_autotune")
+        return {o: (rows[o], tiles[o], ms[o]) for o in range(1, 4) if rows[o]}
+
+    def set_tiles(self, order, rows):
+        rc = lib().dg_batch_set_tiles(self._h, int(order), int(rows))
+        if rc:
+            raise DGError(rc, "dg_batch_set_tiles")
+
+    def set_learned(self, order, w_bf16, master, band=(0.2, 0.8)):
+        self._learned[order] = (w_bf16, master)  # the library keeps the pointers
+        rc = lib().dg_batch_set_learned(self._h, int(order), _ptr(w_bf16), _ptr(master), float(band[0]),
+                                        float(band[1]))
+        if rc:
+            raise DGError(rc, "dg_batch_set_learned")
+
+    def step(self, t, t_end, max_steps=2**31 - 1, allow_nonphysical=False):
+        """Advance every instance from t[i] towards t_end[i] (sequences or
+        scalars); returns (t, steps, status, troubled) as numpy arrays and an
+        int."""
+        import numpy as np
+        tv = np.broadcast_to(np.asarray(t, dtype=np.float64), (self.n,)).copy()
+        te = np.broadcast_to(np.asarray(t_end, dtype=np.float64), (self.n,)).copy()
+        tc = (ctypes.c_double * self.n)(*tv)
+        tec = (ctypes.c_double * self.n)(*te)
+        steps = (ctypes.c_int32 * self.n)()
+        status = (ctypes.c_int32 * self.n)()
+        tr = ctypes.c_int64()
+        rc = lib().dg_batch_step(self._h, _ptr(self.states), self._off_c, tc, tec, int(max_steps), steps, status,
+                                 ctypes.byref(tr))
+        if rc and not (rc == DG_ERR_NONPHYSICAL and allow_nonphysical):
+            raise DGError(rc, "dg_batch_step")
+        return (np.array(tc[:]), np.array(steps[:], dtype=np.int64), np.array(status[:], dtype=np.int64),
+                tr.value)
+
+
+def batch_from_workloads(wls, device="cuda", limit=True, **over):
+    """A Batch of 2D Euler workloads with each instance's initial state
+    projected (and limited) through a single-mesh problem of the same
+    configuration."""
+    cfgs = []
+    for wl in wls:
+        kw = dict(dim=2, equation=wl.equation, order=wl.order, nx=wl.nx, ny=wl.ny, x0=wl.x0, x1=wl.x1,
+                  y0=wl.y0, y1=wl.y1, bc=tuple(wl.bc), gamma=wl.gamma, cfl=wl.cfl)
+        kw.update(over)
+        cfgs.append(kw)
+    b = Batch(cfgs, device=device)
+    for i, wl in enumerate(wls):
+        p = Problem(device=device, **cfgs[i])
+        st = initial_state(p, wl, limit=limit)
+        b.view(i).copy_(st)
+        p.close()
+        del st, p
+    torch.cuda.synchronize(b.device)
+    return b
+

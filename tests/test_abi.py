@@ -72,3 +72,32 @@ def test_init_rejects_small_workspace_without_touching_device(dg):
     assert rc == dg.DG_ERR_WORKSPACE
     rc = dg.lib().dg_init(ctypes.byref(c), ctypes.c_void_p(4096 + 8), 1 << 30, None, ctypes.byref(h))
     assert rc == dg.DG_ERR_WORKSPACE  # misaligned
+
+
+def test_batch_workspace_and_validation(dg):
+    """Batch sizes and rules are checked on the host before any device work."""
+    def arr(*cfgs):
+        return (dg.Config * len(cfgs))(*[dg.make_config(**c) for c in cfgs])
+
+    def nbytes(*cfgs):
+        n = ctypes.c_size_t()
+        rc = dg.lib().dg_batch_workspace_bytes(arr(*cfgs), len(cfgs), ctypes.byref(n))
+        return rc, n.value
+
+    e2 = dict(dim=2, equation=dg.EULER, bc=(1, 1, 1, 1))
+    rc, n = nbytes(dict(e2, order=1, nx=64, ny=64), dict(e2, order=3, nx=100, ny=80))
+    states = 64 * 64 * 4 * 4 * 8 + 100 * 80 * 16 * 4 * 8
+    assert rc == 0 and 2 * states <= n < 2 * states + 4 * 50000 * 4 + 8 * 20000 + 4 * 4096
+    assert nbytes(dict(dim=1, equation=dg.EULER, order=2, nx=16))[0] == dg.DG_ERR_UNSUPPORTED
+    assert nbytes(dict(e2, order=2, nx=8, ny=8, equation=dg.BURGERS))[0] == dg.DG_ERR_UNSUPPORTED
+    assert nbytes(dict(e2, order=2, nx=8, ny=8), dict(e2, order=2, nx=8, ny=8, limiter=dg.LIM_NONE))[0] == \
+        dg.DG_ERR_INVALID_ARG
+    assert nbytes(dict(e2, order=2, nx=8, ny=8), dict(e2, order=1, nx=8, ny=8, indicator=dg.IND_ALL))[0] == \
+        dg.DG_ERR_INVALID_ARG
+    assert nbytes(dict(e2, order=2, nx=50000, ny=50000))[0] == dg.DG_ERR_UNSUPPORTED
+    n = ctypes.c_size_t()
+    assert dg.lib().dg_batch_workspace_bytes(arr(dict(e2, order=2, nx=8, ny=8)), 0, ctypes.byref(n)) == \
+        dg.DG_ERR_INVALID_ARG
+    h = ctypes.c_void_p()
+    one = arr(dict(e2, order=2, nx=8, ny=8))
+    assert dg.lib().dg_batch_init(one, 1, None, 0, None, ctypes.byref(h)) == dg.DG_ERR_WORKSPACE
