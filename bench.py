@@ -67,6 +67,115 @@ def cpu_baseline(n_window=1024, seed=12345, min_seconds=10.0, max_steps=20):
                       f"seed {seed}; {el:.2f} s"}
 
 
+def learned_nets(device):
+    """The committed trained indicators, by order (missing files are skipped)."""
+    from paper_1904_11147_amd import learned
+    nets = {}
+    for o in (1, 2, 3):
+        path = os.path.join(ROOT, "paper_1904_11147_amd", "weights", f"indicator_q{o}.npz")
+        if os.path.exists(path):
+            nets[o] = learned.MLP.load(path, device=device)
+    return nets
+
+
+def learned_leg(wl, state0, t0, steps, warmup, nets):
+    """The same problem and state with the learned indicator (Q2 network)."""
+    import torch
+    from paper_1904_11147_amd import dg, learned
+    if 2 not in nets:
+        return None
+    prob = dg.problem_from_workload(wl, device="cuda:0", indicator=dg.IND_LEARNED)
+    learned.attach(prob, nets[2])
+    state = state0.clone()
+    t, _ = prob.step(state, t0, wl.t_end, max_steps=warmup)
+    prob.profile_read(reset=True)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    t, n = prob.step(state, t, wl.t_end, max_steps=steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - a
+    _, troubled = prob.profile_read(reset=True)
+    prob.close()
+    return {"value": wl.dofs * n / el, "ms_per_step": 1e3 * el / n, "steps": n,
+            "troubled_fraction": troubled / max(1, 3 * wl.cells * n)}
+
+
+def batched_leg(steps, warmup, count=256, nets=None):
+    """256 mixed four-state Riemann problems (side uniform in [64,512], order
+    uniform in {1,2,3}, one seed each): every instance advanced alone through
+    dg_step, then all together through dg_batch_step (autotuned tiles), plain
+    TVB and with the learned indicators.  Each instance takes the same number
+    of steps in every variant; cell-DOF updates / wall time of the stepping.
+    Instances that reach a non-physical state within those steps (no
+    positivity limiter is applied) are listed and left out of all variants."""
+    import numpy as np
+    import torch
+    from paper_1904_11147_amd import dg, workloads as W
+    wls_all = W.riemann2d_batch(count=count)
+    # each instance alone
+    el_seq, keep, excluded = 0.0, [], []
+    for wl in wls_all:
+        p = dg.problem_from_workload(wl, device="cuda:0")
+        st = dg.initial_state(p, wl, limit=True)
+        t, _ = p.step(st, 0.0, wl.t_end, max_steps=warmup, allow_nonphysical=True)
+        bad = p.status() != 0
+        if not bad:
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            p.step(st, t, wl.t_end, max_steps=steps, allow_nonphysical=True)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - a
+            bad = p.status() != 0
+        if bad:
+            excluded.append({"seed": wl.seed, "n": wl.nx, "order": wl.order})
+        else:
+            el_seq += el
+            keep.append(wl)
+        p.close()
+        del st
+    wls = keep
+    dofs = np.array([wl.dofs for wl in wls], dtype=np.float64)
+    t_end = np.array([wl.t_end for wl in wls])
+    res = {"workload": f"riemann2d_batch{count}: {count} 2D Euler four-state Riemann problems, side uniform in "
+                       "[64,512], order uniform in {1,2,3} (CFL 0.1, Q3 0.05), seeds 10000+, transmissive, "
+                       "TVB M=1 + CSWENO",
+           "instances": len(wls), "excluded_nonphysical": excluded, "dofs": int(dofs.sum()),
+           "orders": {o: int(sum(w.order == o for w in wls)) for o in (1, 2, 3)}, "steps_each": steps,
+           "sequential": {"value": dofs.sum() * steps / el_seq, "ms_per_step": 1e3 * el_seq / steps}}
+    b = dg.batch_from_workloads(wls, device="cuda:0")
+    init = b.states.clone()
+
+    def run(batch):
+        t, _, _, _ = batch.step(0.0, t_end, max_steps=warmup)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        t, n, status, troubled = batch.step(t, t_end, max_steps=steps, allow_nonphysical=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - a
+        cells = float(sum(wl.cells * k for wl, k in zip(wls, n)))
+        return {"value": float((dofs * n).sum() / el), "ms_per_step": 1e3 * el / steps,
+                "troubled_fraction": troubled / max(1.0, 3.0 * cells), "nonphysical": int((status != 0).sum())}
+
+    res["autotune"] = {str(o): {"rows": r, "tiles": n, "stage_ms": ms} for o, (r, n, ms) in b.autotune().items()}
+    res["batched"] = run(b)
+    b.close()
+    del b
+    if nets and all(o in nets for o in (1, 2, 3)):
+        cfgs = [dict(dim=2, equation=wl.equation, order=wl.order, nx=wl.nx, ny=wl.ny, x0=wl.x0, x1=wl.x1, y0=wl.y0,
+                     y1=wl.y1, bc=tuple(wl.bc), gamma=wl.gamma, cfl=wl.cfl, indicator=dg.IND_LEARNED) for wl in wls]
+        bl = dg.Batch(cfgs, device="cuda:0")
+        bl.states.copy_(init)
+        for o in (1, 2, 3):
+            bl.set_learned(o, nets[o].w, nets[o].master)
+        bl.autotune()
+        res["batched_learned"] = run(bl)
+        bl.close()
+    res["speedup_batched_vs_sequential"] = res["batched"]["value"] / res["sequential"]["value"]
+    if "batched_learned" in res:
+        res["speedup_batched_learned_vs_sequential"] = res["batched_learned"]["value"] / res["sequential"]["value"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +184,8 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--seed", type=int, default=12345)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 256-instance batched comparison")
+    ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run a plain 1 GiB device copy kernel three times "
                          "(the known-size reference for rocprofv3 FETCH_SIZE/WRITE_SIZE)")
@@ -94,6 +205,7 @@ def main():
     t = 0.0
     if args.warmup:
         t, _ = prob.step(state, t, wl.t_end, max_steps=args.warmup)
+    state_warm, t_warm = state.clone(), t
     # timed region: kernel events on, the wall clock around it
     prob.profile(True)
     prob.profile_read(reset=True)
@@ -167,6 +279,14 @@ def main():
             "t_after": t,
         },
     }
+    nets = learned_nets("cuda:0")
+    out["learned"] = learned_leg(wl, state_warm, t_warm, args.steps, 2, nets)
+    del state_warm
+    prob.close()
+    del state
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = batched_leg(args.batched_steps, 2, nets=nets)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(seed=args.seed)
     print(json.dumps(out), flush=True)

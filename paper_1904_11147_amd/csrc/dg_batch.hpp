@@ -147,8 +147,9 @@ template <int N, int STAGE>
 __global__ __launch_bounds__(64, 2) void k_batch_stage(const BatchInst *__restrict__ inst,
                                                        const BatchQueue *__restrict__ q) {
   __shared__ double row[2 * (N + 1) * (N + 1) * 64];
-  const int w = blockIdx.x;
-  if (w >= q->total_tiles) return;
+  const int total = q->total_tiles;
+  if ((int)blockIdx.x >= total) return;
+  const int w = xcd_tile(blockIdx.x, total);
   const int k = queue_find(q->tile_end, q->n_active, w);
   const BatchInst &I = inst[q->inst[k]];
   const int local = w - (k ? q->tile_end[k - 1] : 0);

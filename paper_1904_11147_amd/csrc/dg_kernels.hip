@@ -1077,10 +1077,22 @@ __device__ __forceinline__ void euler_pair_tile(const StageArgs &a, int bx, int 
   }
 }
 
+// Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
+// dispatch index L.  This maps L to a tile index so that every XCD receives
+// one contiguous range of tiles: x-neighbouring tiles, which read the same
+// halo cache lines, then run on the same L2.  A bijection on [0, total).
+__device__ inline int xcd_tile(int L, int total) {
+  constexpr int kXcd = 8;
+  const int q = total / kXcd, r = total % kXcd, x = L % kXcd;
+  return x * q + min(x, r) + L / kXcd;
+}
+
 template <int N, int STAGE>
 __global__ __launch_bounds__(64, 2) void k_stage_2d_euler_pair(StageArgs a, int rows_per_block) {
   __shared__ double row[2 * (N + 1) * (N + 1) * 64];
-  euler_pair_tile<N, STAGE>(a, blockIdx.x, blockIdx.y, rows_per_block, row);
+  const int tiles_x = gridDim.x;
+  const int w = xcd_tile(blockIdx.x + blockIdx.y * tiles_x, tiles_x * gridDim.y);
+  euler_pair_tile<N, STAGE>(a, w % tiles_x, w / tiles_x, rows_per_block, row);
 }
 
 // ---------------------------------------------------------------------------

@@ -281,12 +281,18 @@ def problem_from_workload(wl, device="cuda", **over):
     return Problem(device=device, **kw)
 
 
-def initial_state(prob, wl, limit=True, rows_per_chunk=None):
+def initial_state(prob, wl, limit=True, rows_per_chunk=None, state=None):
     """Project the workload's initial data (evaluated at this library's nodes)
     and apply the limiter once."""
     r, _ = prob.proj_nodes()
-    state = prob.empty_state()
-    if prob.dim == 1:
+    state = prob.empty_state() if state is None else state
+    if prob.dim == 2 and wl.point_values_device(r, 0, 1, prob.device) is not None:
+        nq = len(r)
+        rows = rows_per_chunk or max(1, min(prob.ny, (1 << 30) // (prob.nv * nq * nq * prob.nx * 8)))
+        for j0 in range(0, prob.ny, rows):
+            nr = min(rows, prob.ny - j0)
+            prob.project(wl.point_values_device(r, j0, nr, prob.device), state, j0=j0)
+    elif prob.dim == 1:
         pv = torch.from_numpy(wl.point_values(r)).to(prob.device)
         prob.project(pv, state)
     else:
@@ -419,10 +425,9 @@ def batch_from_workloads(wls, device="cuda", limit=True, **over):
     b = Batch(cfgs, device=device)
     for i, wl in enumerate(wls):
         p = Problem(device=device, **cfgs[i])
-        st = initial_state(p, wl, limit=limit)
-        b.view(i).copy_(st)
+        initial_state(p, wl, limit=limit, state=b.view(i))
         p.close()
-        del st, p
+        del p
     torch.cuda.synchronize(b.device)
     return b
 

@@ -2,7 +2,7 @@
 
     python -m paper_1904_11147_amd.train_indicator --seeds 0:200 --out weights.npz
 
-Data: seeded 64 x 64 four-state Riemann problems (2D Euler Q2), see
+Data: seeded 64 x 64 four-state Riemann problems (2D Euler, Q1..Q3), see
 paper_1904_11147_amd.learned.  Progress is printed per seed block and per
 epoch; the evaluation compares plain and learned runs on held-out seeds.
 """
@@ -24,22 +24,26 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--seeds", default="0:200")
     ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--order", type=int, default=2)
     ap.add_argument("--every", type=int, default=10)
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--out", default="indicator_q2.npz")
+    ap.add_argument("--out", default=None, help="default: indicator_q<order>.npz")
     ap.add_argument("--eval-seeds", default="1000:1004")
     ap.add_argument("--eval-n", type=int, default=128)
     ap.add_argument("--eval-json", default=None)
     args = ap.parse_args()
+    if args.out is None:
+        args.out = f"indicator_q{args.order}.npz"
 
     seeds = list(_range(args.seeds))
     t0 = time.time()
     xs, ys, ws = [], [], []
     block = 20
     for k in range(0, len(seeds), block):
-        x, y, w = learned.generate_samples(seeds[k:k + block], n=args.n, every=args.every)
+        x, y, w = learned.generate_samples(seeds[k:k + block], n=args.n, order=args.order,
+                                           every=args.every)
         xs.append(x)
         ys.append(y)
         ws.append(w)
@@ -48,7 +52,7 @@ def main():
     x, y, w = torch.cat(xs), torch.cat(ys), torch.cat(ws)
     print(f"data: {x.shape[0]} samples, troubled fraction {y.mean().item():.3f}, F={x.shape[1]}; "
           f"runs stopped at a non-physical state: {learned.SKIPPED}", flush=True)
-    net = learned.MLP(180, seed=0)
+    net = learned.MLP(5 * (args.order + 1) ** 2 * 4, seed=0)
     t1 = time.time()
     hist = learned.train(net, x, y, w, epochs=args.epochs, batch=args.batch, lr=args.lr,
                          log=lambda s: print(s, flush=True))
@@ -60,7 +64,7 @@ def main():
           flush=True)
     net.save(args.out)
     print(f"saved {args.out}", flush=True)
-    ev = learned.evaluate(net, list(_range(args.eval_seeds)), n=args.eval_n)
+    ev = learned.evaluate(net, list(_range(args.eval_seeds)), n=args.eval_n, order=args.order)
     for r in ev:
         print(json.dumps(r), flush=True)
     if args.eval_json:

@@ -114,6 +114,30 @@ class Workload:
         return np.ascontiguousarray(np.stack([np.asarray(v, dtype=np.float64) for v in vals]))
 
 
+    def point_values_device(self, r_nodes, j0, nrows, device):
+        """As point_values, built on a torch device, for four-state Riemann
+        data (whose quadrant test separates into an x and a y part); None for
+        other workloads.  Each node's conserved values are the same numbers
+        point_values gives."""
+        if "states" not in self.extra or self.dim != 2:
+            return None
+        import torch
+        st = self.extra["states"]
+        xc, yc = self.extra.get("center", (0.5, 0.5))
+        r = np.asarray(r_nodes, dtype=np.float64)
+        hx = (self.x1 - self.x0) / self.nx
+        hy = (self.y1 - self.y0) / self.ny
+        X = self.x0 + (np.arange(self.nx)[None, :] + 0.5 * (1.0 + r[:, None])) * hx  # [qx, i]
+        Y = self.y0 + (np.arange(j0, j0 + nrows)[None, :] + 0.5 * (1.0 + r[:, None])) * hy  # [qy, j]
+        east = torch.from_numpy(X >= xc).to(device)[None, None, :, None, :]
+        north = torch.from_numpy(Y >= yc).to(device)[None, :, None, :, None]
+        cons = {q: torch.tensor([float(c) for c in euler2d_conserved(*st[q], gamma=self.gamma)],
+                                dtype=torch.float64, device=device)[:, None, None, None, None]
+                for q in QUADRANTS}
+        return torch.where(north, torch.where(east, cons["NE"], cons["NW"]),
+                           torch.where(east, cons["SE"], cons["SW"])).contiguous()
+
+
 # ---------------------------------------------------------------------------
 # conserved variables from primitive ones (input preparation only)
 # ---------------------------------------------------------------------------
@@ -234,7 +258,7 @@ def riemann2d(n=2048, order=2, seed=12345, t_end=0.25, cfl=None, xc=0.5, yc=0.5)
             prim.append(np.where(north, np.where(east, ne, nw), np.where(east, se, sw)))
         return euler2d_conserved(*prim)
     return Workload(f"riemann2d_{n}_q{order}_s{seed}", 2, EULER, order, n, n, 0.0, 1.0, 0.0, 1.0,
-                    (TRANSMISSIVE,) * 4, cfl, t_end, ic, seed=seed, extra=dict(states=st))
+                    (TRANSMISSIVE,) * 4, cfl, t_end, ic, seed=seed, extra=dict(states=st, center=(xc, yc)))
 
 
 def riemann2d_batch(count=256, first_seed=10000, nmin=64, nmax=512, t_end=0.25):
