@@ -60,7 +60,7 @@ int validate_config(const dg_config *c) {
   if (c->limiter != DG_LIM_NONE && c->limiter != DG_LIM_CSWENO) return DG_ERR_INVALID_ARG;
   if (c->indicator != DG_IND_TVB && c->indicator != DG_IND_ALL && c->indicator != DG_IND_LEARNED)
     return DG_ERR_UNSUPPORTED;
-  if (c->indicator == DG_IND_LEARNED && c->dim != 2) return DG_ERR_UNSUPPORTED;
+  if (c->indicator == DG_IND_LEARNED && (c->dim != 2 || c->equation != DG_EQ_EULER)) return DG_ERR_UNSUPPORTED;
   if (c->negw_mode != DG_NEGW_SPLIT && c->negw_mode != DG_NEGW_RAW) return DG_ERR_INVALID_ARG;
   if (!(c->x1 > c->x0) || (c->dim == 2 && !(c->y1 > c->y0))) return DG_ERR_INVALID_ARG;
   if (c->equation == DG_EQ_EULER && !(c->gamma > 1.0)) return DG_ERR_INVALID_ARG;

@@ -192,13 +192,11 @@ __device__ inline void append_batch(BatchQueue *q, int slot, long long *list, De
 // Troubled-cell indicator over the queued row segments (one wavefront per
 // segment).  IND: DG_IND_TVB, DG_IND_ALL or DG_IND_LEARNED.
 template <int N, int SLOT, int IND>
-__global__ __launch_bounds__(64) void k_batch_indicator(const BatchInst *__restrict__ inst, BatchQueue *q,
-                                                        long long *__restrict__ list, BatchLearned BL) {
+__global__ __launch_bounds__(64, 2) void k_batch_indicator(const BatchInst *__restrict__ inst, BatchQueue *q,
+                                                           long long *__restrict__ list, BatchLearned BL) {
   constexpr int NM = (N + 1) * (N + 1), F = 5 * NM * 4, KP = (F + 15) / 16 * 16;
-  constexpr int LF = IND == DG_IND_LEARNED ? 64 * KP : 1, LS = IND == DG_IND_LEARNED ? 16 * kHidden : 1;
-  __shared__ uint16_t feat[LF];
-  __shared__ uint16_t scratch[LS];
   __shared__ float zs[64];
+  __shared__ uint16_t feat[IND == DG_IND_LEARNED ? learned_feat_lds<N>() : 1];
   const LearnedArgs L{BL.W, BL.M, MlpLayout{F, KP}, BL.band_lo, BL.band_hi, nullptr};
   const int total = q->total_segs;
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
@@ -210,7 +208,7 @@ __global__ __launch_bounds__(64) void k_batch_indicator(const BatchInst *__restr
     bool flag = false;
     double mg = INFINITY;
     if (IND == DG_IND_LEARNED) {
-      const float p = learned_probability<N, 1>(u, g, s.i0, s.j, L, feat, scratch, zs);
+      const float p = learned_probability<N, 1>(u, g, s.i0, s.j, L, zs, feat);
       if (i < g.nx) flag = p > BL.band_hi ? true : (p < BL.band_lo ? false : tvb_cell<N, 1, 2>(u, g, i, s.j, mg));
     } else if (i < g.nx) {
       flag = IND == DG_IND_ALL ? true : tvb_cell<N, 1, 2>(u, g, i, s.j, mg);

@@ -1642,13 +1642,17 @@ int launch_limit(const LaunchCtx &c, double *u, double *side, int count_slot, ui
     constexpr int NM = d == 1 ? n + 1 : (n + 1) * (n + 1);
     constexpr int NV = Phys<e, d>::NV;
     dim3 block, grid = cell_grid(c, block);
-    if (d == 2 && c.indicator == DG_IND_LEARNED && !flags_override) {
-      LearnedArgs L{c.mlp_w, c.mlp_m, MlpLayout{5 * NM * NV, (5 * NM * NV + 15) / 16 * 16}, (float)c.band_lo,
-                    (float)c.band_hi, c.mlp_prob};
-      hipLaunchKernelGGL((k_indicator_learned<n, e>), dim3((c.geo.nx + 63) / 64, c.geo.ny), dim3(64), 0, S(c), a, L);
-    } else {
-      hipLaunchKernelGGL((k_indicator<n, e, d>), grid, block, 0, S(c), a);
+    bool learned = false;
+    if constexpr (d == 2 && e == DG_EQ_EULER) {
+      if (c.indicator == DG_IND_LEARNED && !flags_override) {
+        LearnedArgs L{c.mlp_w, c.mlp_m, MlpLayout{5 * NM * NV, (5 * NM * NV + 15) / 16 * 16}, (float)c.band_lo,
+                      (float)c.band_hi, c.mlp_prob};
+        hipLaunchKernelGGL((k_indicator_learned<n, e>), dim3((c.geo.nx + 63) / 64, c.geo.ny), dim3(64), 0, S(c), a,
+                           L);
+        learned = true;
+      }
     }
+    if (!learned) hipLaunchKernelGGL((k_indicator<n, e, d>), grid, block, 0, S(c), a);
     if (c.limiter == DG_LIM_CSWENO) {
       hipLaunchKernelGGL((k_csweno<n, e, d>), dim3(c.grid_cap), dim3(kBlock), 0, S(c), a);
       hipLaunchKernelGGL((k_scatter<NM, NV>), dim3(c.grid_cap), dim3(kBlock), 0, S(c), a, u);
@@ -1748,7 +1752,7 @@ int launch_mlp_gradient(const uint16_t *x, const float *y, const float *w, int n
 
 int launch_mlp_adam(float *M, float *m1, float *m2, float *G, uint16_t *W, int F, float lr, int step, void *stream) {
   MlpLayout lay{F, (F + 15) / 16 * 16};
-  const long n = lay.nmaster();
+  const long n = lay.nmaster() + lay.npad();
   hipLaunchKernelGGL(k_mlp_adam, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, (hipStream_t)stream, M,
                      m1, m2, G, W, lay, lr, step);
   return check_launch();

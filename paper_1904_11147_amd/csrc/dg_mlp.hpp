@@ -39,14 +39,27 @@ __device__ inline bf16x4_t pack4(float a, float b, float c, float d) {
 
 __device__ inline bf16x4_t load4(const uint16_t *p) { return *reinterpret_cast<const bf16x4_t *>(p); }
 
-// Offsets into the bf16 weight buffer: W1 [64][KP] | W2 [64][64] | W2T [64][64] | w3 [64].
+// Offsets into the bf16 weight buffer: W1 [64][KP] | W2 [64][64] | W2T [64][64] | w3 [64] | W1P.
+//
+// W1P is W1 rearranged for the limiter's inference kernel, where each of the
+// four lane groups of an MFMA fragment handles one of the four conserved
+// variables: the F = 4 FV features split into four per-variable blocks of FV,
+// each padded to BV = 4 ceil(FV / 4) (so 4 BV = KP for FV = 5 (N+1)^2), and
+// stored as [nb][kb][lane][4] A-fragments: element e of lane (r, g) of
+// k-block kb and output block nb is W1[16 nb + r][g FV + 4 kb + e] (zero in
+// the padding).  Defined when F is a multiple of 4 with 4 BV = KP.
 struct MlpLayout {
   int F, KP;
   __host__ __device__ long w1() const { return 0; }
   __host__ __device__ long w2() const { return (long)kHidden * KP; }
   __host__ __device__ long w2t() const { return w2() + kHidden * kHidden; }
   __host__ __device__ long w3() const { return w2t() + kHidden * kHidden; }
-  __host__ __device__ long nbf16() const { return w3() + kHidden; }
+  __host__ __device__ long w1p() const { return w3() + kHidden; }
+  __host__ __device__ long nbf16() const { return w1p() + (long)kHidden * KP; }
+  __host__ __device__ int fv() const { return F / 4; }
+  __host__ __device__ int bv() const { return (F / 4 + 3) / 4 * 4; }
+  __host__ __device__ bool has_w1p() const { return F % 4 == 0 && 4 * bv() == KP; }
+  __host__ __device__ long npad() const { return has_w1p() ? (long)kHidden * 4 * (bv() - fv()) : 0; }
   // master fp32: W1 [64][F] | W2 [64][64] | w3 [64] | b1 [64] | b2 [64] | b3
   __host__ __device__ long mW2() const { return (long)kHidden * F; }
   __host__ __device__ long mw3() const { return mW2() + kHidden * kHidden; }
@@ -370,7 +383,15 @@ __global__ __launch_bounds__(64) void k_mlp_wgrad1(const uint16_t *__restrict__ 
 __global__ __launch_bounds__(kBlock) void k_mlp_adam(float *M, float *m1, float *m2, float *G, uint16_t *W,
                                                      MlpLayout lay, float lr, int step) {
   const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= lay.nmaster()) return;
+  const int KB = lay.bv() / 4;
+  if (k >= lay.nmaster()) {  // zeros in the padding of W1P
+    const long idx = k - lay.nmaster();
+    if (idx >= lay.npad()) return;
+    const int pad = lay.bv() - lay.fv();
+    const int o = (int)(idx / (4 * pad)), v = (int)(idx / pad % 4), f = lay.fv() + (int)(idx % pad);
+    W[lay.w1p() + ((long)((o / 16) * KB + f / 4) * 64 + v * 16 + o % 16) * 4 + f % 4] = 0;
+    return;
+  }
   float w = M[k];
   if (step > 0) {
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
@@ -388,6 +409,10 @@ __global__ __launch_bounds__(kBlock) void k_mlp_adam(float *M, float *m1, float 
   if (k < lay.mW2()) {
     const long o = k / lay.F, c = k % lay.F;
     W[lay.w1() + o * lay.KP + c] = f2bf(w);
+    if (lay.has_w1p()) {
+      const int v = (int)(c / lay.fv()), f = (int)(c % lay.fv());
+      W[lay.w1p() + ((long)((o / 16) * KB + f / 4) * 64 + v * 16 + o % 16) * 4 + f % 4] = f2bf(w);
+    }
   } else if (k < lay.mw3()) {
     const long o = (k - lay.mW2()) / kHidden, c = (k - lay.mW2()) % kHidden;
     W[lay.w2() + o * kHidden + c] = f2bf(w);
@@ -410,48 +435,136 @@ struct LearnedArgs {
 
 // Network probabilities of the 64 cells (i0 + lane, j) of one row segment
 // (columns beyond the mesh repeat the last one); returns this lane's p.  One
-// wavefront; feat/scratch are its LDS areas.
+// wavefront; zs is a 64-float LDS area and feat one of learned_feat_lds<N>()
+// bf16 values.  2D Euler only.
+//
+// The layers are evaluated transposed, H^T = W X^T, with the weights as the
+// MFMA A operand: lane (r, g) builds the B fragments of cell r from
+// variable g's features (the per-variable normalisation stays in the lane),
+// and each layer's output fragments are the next layer's B fragments.  The
+// weight fragments are loaded once per two 16-cell tiles.  Features go
+// through the lane's own LDS slots, from which the fragments are read.
+constexpr int kLearnedTiles = 2;
+template <int N>
+constexpr int learned_feat_lds() {
+  return kLearnedTiles * ((5 * (N + 1) * (N + 1) + 3) / 4) * 64 * 4;
+}
+
 template <int N, int EQ>
 __device__ inline float learned_probability(const double *__restrict__ u, const Geometry &g, int i0, int j,
-                                            const LearnedArgs &L, uint16_t *feat, uint16_t *scratch, float *zs) {
-  constexpr int NM = (N + 1) * (N + 1), NV = Phys<EQ, 2>::NV, F = 5 * NM * NV, KP = (F + 15) / 16 * 16;
-  const int lane = threadIdx.x;
-  const int i = i0 + lane;
+                                            const LearnedArgs &L, float *zs, uint16_t *feat) {
+  static_assert(EQ == 1, "learned indicator: 2D Euler");
+  constexpr int NP = N + 1, NM = NP * NP, FV = 5 * NM, BV = (FV + 3) / 4 * 4, KB = BV / 4;
+  constexpr int TILES = kLearnedTiles;
+  const int lane = threadIdx.x, r = lane & 15, gv = lane >> 4;  // cell r of a tile, variable gv
+  const long plane = (long)g.nx * g.ny;
+  const uint16_t *__restrict__ W = L.W;
+  const float *__restrict__ M = L.M;
+  const MlpLayout &lay = L.lay;
+  const double *__restrict__ up = u + (long)gv * NM * plane;
+  const int di[5] = {0, -1, 1, 0, 0}, dj[5] = {0, 0, 0, -1, 1};
 #pragma unroll 1
-  for (int v = 0; v < NV; ++v)
-    cell_features<N, NV>(u, g, i < g.nx ? i : g.nx - 1, j, v, feat + lane * KP + v * 5 * NM, nullptr);
-  for (int k = F; k < KP; ++k) feat[lane * KP + k] = 0;
-  __syncthreads();
-  const int r = lane & 15, gq = lane >> 4;
+  for (int t0 = 0; t0 < 4; t0 += TILES) {
 #pragma unroll 1
-  for (int t = 0; t < 4; ++t) {
-    auto loadA = [&](int kb) -> bf16x4_t { return load4(feat + (16 * t + r) * KP + 16 * kb + 4 * gq); };
-    f32x4_t h1[4], h2[4];
-    float z[4];
-    mlp_tile_forward<KP>(loadA, L.W, L.M, L.lay, scratch, h1, h2, z);
-    if (r == 0)
+    for (int tt = 0; tt < TILES; ++tt) {
+      int i = i0 + 16 * (t0 + tt) + r;
+      if (i >= g.nx) i = g.nx - 1;
+      const double c0 = up[(long)j * g.nx + i];
+      double mx = g.tvb_Mx;
+      double vals[FV];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) zs[16 * t + 4 * gq + q] = z[q];
+      for (int c = 0; c < 5; ++c) {
+        const CellIdx ci = map_cell(g, i + di[c], j + dj[c]);
+#pragma unroll
+        for (int q = 0; q < NM; ++q) {
+          const int m = q % NP, n = q / NP;
+          double v = up[(long)q * plane + ci.idx];
+          if ((ci.fx && (m & 1)) != (ci.fy && (n & 1))) v = -v;
+          if (q == 0) v -= c0;
+          mx = fmax(mx, fabs(v));
+          vals[c * NM + q] = v;
+        }
+      }
+      const double inv = 1.0 / mx;
+      uint16_t *fl = feat + (long)tt * KB * 256 + lane * 4;  // element f at fl[(f / 4) * 256 + f % 4]
+#pragma unroll
+      for (int f = 0; f < FV; ++f) fl[(f / 4) * 256 + f % 4] = f2bf((float)(vals[f] * inv));
+#pragma unroll
+      for (int f = FV; f < BV; ++f) fl[(f / 4) * 256 + f % 4] = 0;
+    }
+    // layer 1: H1^T = W1 X^T
+    f32x4_t h[TILES][4];
+#pragma unroll
+    for (int tt = 0; tt < TILES; ++tt)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) h[tt][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int kb = 0; kb < KB; ++kb) {
+      bf16x4_t xf[TILES];
+#pragma unroll
+      for (int tt = 0; tt < TILES; ++tt) xf[tt] = load4(feat + ((long)(tt * KB + kb) * 64 + lane) * 4);
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const bf16x4_t a = load4(W + lay.w1p() + ((long)(nb * KB + kb) * 64 + lane) * 4);
+#pragma unroll
+        for (int tt = 0; tt < TILES; ++tt) h[tt][nb] = mfma16(a, xf[tt], h[tt][nb]);
+      }
+    }
+    bf16x4_t h1[TILES][4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float b = M[lay.mb1() + 16 * nb + 4 * gv + e];
+#pragma unroll
+        for (int tt = 0; tt < TILES; ++tt) h1[tt][nb][e] = (short)f2bf(fmaxf(h[tt][nb][e] + b, 0.f));
+      }
+    // layer 2: H2^T = W2 H1^T
+#pragma unroll
+    for (int tt = 0; tt < TILES; ++tt)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) h[tt][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const bf16x4_t a = load4(W + lay.w2() + (16 * nb + r) * kHidden + 16 * kb + 4 * gv);
+#pragma unroll
+        for (int tt = 0; tt < TILES; ++tt) h[tt][nb] = mfma16(a, h1[tt][kb], h[tt][nb]);
+      }
+    // layer 3: z = w3 . h2 + b3, summed over the lane's 16 hidden units, then over the 4 groups
+#pragma unroll
+    for (int tt = 0; tt < TILES; ++tt) {
+      float part = 0.f;
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = 16 * nb + 4 * gv + e;
+          part += bf2f(f2bf(fmaxf(h[tt][nb][e] + M[lay.mb2() + k], 0.f))) * bf2f(W[lay.w3() + k]);
+        }
+      part += __shfl_xor(part, 16);
+      part += __shfl_xor(part, 32);
+      if (gv == 0) zs[16 * (t0 + tt) + r] = part + M[lay.mb3()];
+    }
   }
-  __syncthreads();
+  __syncthreads();  // one wavefront per block: orders zs
   const float p = 1.f / (1.f + __expf(-zs[lane]));
-  __syncthreads();  // feat and zs are reused by the next segment
+  __syncthreads();  // zs is reused by the next segment
   return p;
 }
 
 template <int N, int EQ>
-__global__ __launch_bounds__(64) void k_indicator_learned(LimitArgs a, LearnedArgs L) {
-  constexpr int NM = (N + 1) * (N + 1), NV = Phys<EQ, 2>::NV, F = 5 * NM * NV, KP = (F + 15) / 16 * 16;
-  __shared__ uint16_t feat[64 * KP];
-  __shared__ uint16_t scratch[16 * kHidden];
+__global__ __launch_bounds__(64, 2) void k_indicator_learned(LimitArgs a, LearnedArgs L) {
   __shared__ float zs[64];
+  __shared__ uint16_t feat[learned_feat_lds<N>()];
   const Geometry &g = a.geo;
   if (a.check_done && a.sc->done) return;
   const int lane = threadIdx.x;
   const int i = blockIdx.x * 64 + lane, j = blockIdx.y;
   const bool active = i < g.nx && j < g.ny;
   const long cell = (long)j * g.nx + i;
-  const float p = learned_probability<N, EQ>(a.u, g, blockIdx.x * 64, j, L, feat, scratch, zs);
+  const float p = learned_probability<N, EQ>(a.u, g, blockIdx.x * 64, j, L, zs, feat);
   bool flag = false;
   double mg = INFINITY;
   if (active) {
