@@ -201,6 +201,7 @@ def main():
     wl = W.riemann2d(n=args.n, order=2, seed=args.seed)
     prob = dg.problem_from_workload(wl, device="cuda:0")
     state = dg.initial_state(prob, wl, limit=True)
+    tuned_rows, tuned_ms = prob.autotune(state)
     torch.cuda.synchronize()
     t = 0.0
     if args.warmup:
@@ -269,6 +270,7 @@ def main():
             "traffic": traffic_for(bytes_launch),
             "algorithmic_bytes_per_launch": bytes_launch,
             "avg_launch_ms": avg_ms,
+            "autotuned_rows": tuned_rows,
         },
         "step": {
             "algorithmic_bytes": 64 * dofs,

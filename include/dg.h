@@ -184,6 +184,14 @@ int dg_profile_read(dg_problem *p, double *ms, int64_t *launches, int64_t *troub
  * W2 [64][64] | W2^T [64][64] | w3 [64].  All buffers below are DEVICE memory
  * owned by the caller; "stream" is a hipStream_t. */
 
+/* Tile-shape autotuner of one problem (2D; 1D problems return rows 0 and
+ * change nothing): times the stage kernel (a residual evaluation of state
+ * into the workspace; state is not changed) for each tile height (rows
+ * marched per wavefront: 4, 8, 16, 32, 64) and keeps the fastest for later
+ * calls; rows and ms (host, may be NULL) receive the choice and its time.
+ * Results do not depend on the tile height. */
+int dg_autotune(dg_problem *p, const double *state, int32_t *rows, float *ms);
+
 /* Sizes for F features: padded width, master and bf16 element counts (host). */
 int dg_mlp_layout(int32_t features, int32_t *padded, int64_t *n_master, int64_t *n_bf16);
 

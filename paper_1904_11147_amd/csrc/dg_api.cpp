@@ -282,6 +282,7 @@ int dg_init(const dg_config *cfg, void *workspace, size_t workspace_bytes, void 
   c.indicator = cfg->indicator;
   c.grid_cap = 2048;
   c.use_march = 1;
+  c.rows = 0;
   c.mlp_w = nullptr;
   c.mlp_m = nullptr;
   c.mlp_prob = nullptr;
@@ -431,6 +432,48 @@ int dg_step(dg_problem *p, double *state, double *t, double t_end, double dt, in
   *t = h.t;
   if (steps_taken) *steps_taken = h.steps;
   return h.status ? DG_ERR_NONPHYSICAL : DG_OK;
+}
+
+int dg_autotune(dg_problem *p, const double *state, int32_t *rows, float *ms) {
+  if (!p || !state) return DG_ERR_INVALID_ARG;
+  if (rows) *rows = 0;
+  if (ms) *ms = 0.f;
+  if (p->cfg.dim != 2) return DG_OK;
+  static const int kChoices[] = {4, 8, 16, 32, 64};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return DG_ERR_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return DG_ERR_HIP;
+  }
+  int rc = DG_OK, best_rows = 0;
+  float best = 1e30f;
+  for (int r : kChoices) {
+    p->ctx.rows = r;
+    if ((rc = dg::launch_residual(p->ctx, state, p->ctx.bufA))) break;  // warm-up
+    constexpr int reps = 3;
+    (void)hipEventRecord(e0, p->user_stream);
+    for (int k = 0; k < reps && !rc; ++k) rc = dg::launch_residual(p->ctx, state, p->ctx.bufA);
+    (void)hipEventRecord(e1, p->user_stream);
+    if (rc || (rc = hip_ok(hipEventSynchronize(e1)))) break;
+    float t = 0.f;
+    if ((rc = hip_ok(hipEventElapsedTime(&t, e0, e1)))) break;
+    if (t / reps < best) {
+      best = t / reps;
+      best_rows = r;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->ctx.rows = rc ? 0 : best_rows;
+  if (p->graph) {  // the captured step holds the old grid
+    (void)hipGraphExecDestroy(p->graph);
+    p->graph = nullptr;
+  }
+  if (rc) return rc;
+  if (rows) *rows = best_rows;
+  if (ms) *ms = best;
+  return sync_status(p, nullptr) == DG_ERR_HIP ? DG_ERR_HIP : DG_OK;
 }
 
 int dg_status(dg_problem *p) {

@@ -23,7 +23,9 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 constexpr int kRowChoices[] = {4, 8, 16, 32, 64};
-constexpr int kPairStripHost = 30;  // columns per stage tile (the stage kernel's strip width)
+// columns per stage tile (the stage kernel's strip width: two lanes per cell
+// for Q1, Q2, four for Q3)
+constexpr int strip_cols(int order) { return order == 3 ? 14 : 30; }
 
 struct BatchLayout {
   size_t active, scalars, inst, queue, list[kMaxN + 1], bufs, total;
@@ -266,7 +268,7 @@ int dg_batch_init(const dg_config *cfgs, int32_t n, void *workspace, size_t work
     off += align_up(L.state_bytes[i]);
     I.sc = b->sc + i;
     I.order = cf.order;
-    I.tiles_x = (cf.nx + kPairStripHost - 1) / kPairStripHost;
+    I.tiles_x = (cf.nx + strip_cols(cf.order) - 1) / strip_cols(cf.order);
     I.segs = (cf.nx + 63) / 64 * cf.ny;
     I.indicator = cf.indicator;
     I.cfl = cf.cfl;

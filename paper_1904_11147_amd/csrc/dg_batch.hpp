@@ -146,7 +146,7 @@ __global__ __launch_bounds__(64) void k_batch_speed(const BatchInst *__restrict_
 template <int N, int STAGE>
 __global__ __launch_bounds__(64, 2) void k_batch_stage(const BatchInst *__restrict__ inst,
                                                        const BatchQueue *__restrict__ q) {
-  __shared__ double row[2 * (N + 1) * (N + 1) * 64];
+  __shared__ double row[euler_vpl(N) * (N + 1) * (N + 1) * 64];
   const int total = q->total_tiles;
   if ((int)blockIdx.x >= total) return;
   const int w = xcd_tile(blockIdx.x, total);
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(64, 2) void k_batch_stage(const BatchInst *__restri
   a.sc = I.sc;
   a.geo = I.geo;
   a.want_speed = 1;
-  euler_pair_tile<N, STAGE>(a, local % I.tiles_x, local / I.tiles_x, I.rows, row);
+  euler_tile<N, STAGE>(a, local % I.tiles_x, local / I.tiles_x, I.rows, row);
 }
 
 // Buffers of the limiter pass after stage SLOT+1: the state it limits and the

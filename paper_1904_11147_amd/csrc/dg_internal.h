@@ -84,6 +84,7 @@ struct LaunchCtx {
   int limiter, indicator;
   int grid_cap;          // blocks for list-driven kernels
   int use_march;         // 2D: marching stage kernel where registers allow
+  int rows;              // 2D marching kernels: rows per tile (0: a rule from the mesh size)
   const uint16_t *mlp_w; // learned indicator: bf16 weights (caller-owned)
   const float *mlp_m;    // fp32 master parameters (biases read from here)
   float *mlp_prob;       // optional per-cell probability output

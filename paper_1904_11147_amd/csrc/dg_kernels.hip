@@ -750,7 +750,6 @@ __global__ __launch_bounds__(64) void k_stage_2d_march(StageArgs a, int rows_per
 // its own flux components.  The wavefront marches up a chunk of rows over a
 // strip of 30 columns (slots 1..30; slots 0 and 31 are the x-halo).
 // ---------------------------------------------------------------------------
-constexpr int kPairStrip = 30;
 
 struct EulerPrim {
   double ir, vx, vy, p;
@@ -782,85 +781,107 @@ __device__ inline double fast_sqrt(double a) {
   return a > 0.0 ? gq : (a == 0.0 ? 0.0 : __builtin_nan(""));
 }
 
-// Full state (rho, mx, my, E) from the lane's pair (a0, a1) and its partner's.
-__device__ inline EulerPrim euler_prim(double a0, double a1, double b0, double b1, bool h1, double g, bool &bad) {
-  const double rho = h1 ? b0 : a0, mx = h1 ? b1 : a1, my = h1 ? a0 : b0, E = h1 ? a1 : b1;
-  EulerPrim s;
-  s.ir = fast_rcp(rho);
-  s.vx = mx * s.ir;
-  s.vy = my * s.ir;
-  s.p = (g - 1.0) * (E - 0.5 * rho * (s.vx * s.vx + s.vy * s.vy));
-  bad |= !(rho > 0.0 && s.p > 0.0);
-  return s;
-}
-
-// Own flux components in direction DIR: f = w vx + (0, p, 0, p vx),
-// g = w vy + (0, 0, p, p vy), for the lane's variables 2h, 2h+1.
-template <int DIR>
-__device__ inline void euler_flux_pair(const EulerPrim &s, double a0, double a1, bool h1, double &f0, double &f1) {
-  const double vn = DIR == 0 ? s.vx : s.vy;
-  if (DIR == 0) {
-    f0 = a0 * vn;
-    f1 = a1 * vn + (h1 ? s.p * vn : s.p);
-  } else {
-    f0 = a0 * vn + (h1 ? s.p : 0.0);
-    f1 = a1 * vn + (h1 ? s.p * vn : 0.0);
-  }
-}
-
 template <int DIR>
 __device__ inline double euler_speed(const EulerPrim &s, double rho, double g) {
   return fabs(DIR == 0 ? s.vx : s.vy) + fast_sqrt(g * s.p * s.ir);
 }
 
-// LLF flux at one face point for the lane's two variables: left/lower state
-// (l0, l1) and right/upper (r0, r1) are the lane's own components.
-template <int DIR>
-__device__ inline void llf_pair(double l0, double l1, double r0, double r1, bool h1, double g, double &F0, double &F1,
-                                bool &bad) {
-  const double pl0 = __shfl_xor(l0, 1), pl1 = __shfl_xor(l1, 1);
-  const double pr0 = __shfl_xor(r0, 1), pr1 = __shfl_xor(r1, 1);
-  const EulerPrim sl = euler_prim(l0, l1, pl0, pl1, h1, g, bad);
-  const EulerPrim sr = euler_prim(r0, r1, pr0, pr1, h1, g, bad);
-  const double al = fmax(euler_speed<DIR>(sl, 0.0, g), euler_speed<DIR>(sr, 0.0, g));
-  double fl0, fl1, fr0, fr1;
-  euler_flux_pair<DIR>(sl, l0, l1, h1, fl0, fl1);
-  euler_flux_pair<DIR>(sr, r0, r1, h1, fr0, fr1);
-  F0 = 0.5 * (fl0 + fr0) - 0.5 * al * (r0 - l0);
-  F1 = 0.5 * (fl1 + fr1) - 0.5 * al * (r1 - l1);
+// Lanes of one cell: VPL = 2 variables per lane (lanes 2s, 2s+1 hold
+// variables {0,1}, {2,3}; Q1, Q2) or VPL = 1 (lanes 4s+v hold variable v;
+// Q3, whose modes would not fit two variables per lane).  `part` is the
+// lane's index within its cell.
+
+// The full state (rho, mx, my, E) at a point from the cell's lanes.
+template <int VPL>
+__device__ inline void gather_state(const double (&a)[VPL], int part, double (&w)[4]) {
+  if constexpr (VPL == 2) {
+    const double b0 = __shfl_xor(a[0], 1), b1 = __shfl_xor(a[1], 1);
+    const bool h1 = part != 0;
+    w[0] = h1 ? b0 : a[0];
+    w[1] = h1 ? b1 : a[1];
+    w[2] = h1 ? a[0] : b0;
+    w[3] = h1 ? a[1] : b1;
+  } else {
+    const double x1 = __shfl_xor(a[0], 1), x2 = __shfl_xor(a[0], 2), x3 = __shfl_xor(a[0], 3);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int d = v ^ part;
+      w[v] = d == 0 ? a[0] : (d == 1 ? x1 : (d == 2 ? x2 : x3));
+    }
+  }
 }
 
-// One tile: columns [bx*kPairStrip, +kPairStrip) of rows [by*rows, +rows),
-// marched row by row by one wavefront.  `row` is the wavefront's LDS
-// staging area of 2 (N+1)^2 64 doubles (the current row's modes of each
-// lane's two variables, [k*NM+q][lane]).
+__device__ inline EulerPrim prim_of(const double (&w)[4], double g, bool &bad) {
+  EulerPrim s;
+  s.ir = fast_rcp(w[0]);
+  s.vx = w[1] * s.ir;
+  s.vy = w[2] * s.ir;
+  s.p = (g - 1.0) * (w[3] - 0.5 * w[0] * (s.vx * s.vx + s.vy * s.vy));
+  bad |= !(w[0] > 0.0 && s.p > 0.0);
+  return s;
+}
+
+// Flux component of variable var (the lane's own value a) in direction DIR:
+// f = w vx + (0, p, 0, p vx), g = w vy + (0, 0, p, p vy).
+template <int DIR>
+__device__ inline double flux_comp(const EulerPrim &s, double a, int var) {
+  const double vn = DIR == 0 ? s.vx : s.vy;
+  if (DIR == 0) return (var & 1) ? a * vn + (var == 3 ? s.p * vn : s.p) : a * vn;
+  return a * vn + (var == 2 ? s.p : (var == 3 ? s.p * vn : 0.0));
+}
+
+// LLF flux at one face point for the lane's variables: left/lower trace l,
+// right/upper trace r (the lane's own components).
+template <int DIR, int VPL>
+__device__ inline void llf_lane(const double (&l)[VPL], const double (&r)[VPL], int part, double g,
+                                double (&F)[VPL], bool &bad) {
+  double wl[4], wr[4];
+  gather_state<VPL>(l, part, wl);
+  gather_state<VPL>(r, part, wr);
+  const EulerPrim sl = prim_of(wl, g, bad);
+  const EulerPrim sr = prim_of(wr, g, bad);
+  const double al = fmax(euler_speed<DIR>(sl, 0.0, g), euler_speed<DIR>(sr, 0.0, g));
+#pragma unroll
+  for (int k = 0; k < VPL; ++k) {
+    const double fl = flux_comp<DIR>(sl, l[k], VPL * part + k), fr = flux_comp<DIR>(sr, r[k], VPL * part + k);
+    F[k] = 0.5 * (fl + fr) - 0.5 * al * (r[k] - l[k]);
+  }
+}
+
+__host__ __device__ constexpr int euler_vpl(int N) { return N == 3 ? 1 : 2; }
+// columns owned by one wavefront's tile (the other two cell slots are the x-halo)
+__host__ __device__ constexpr int euler_strip(int N) { return 64 * euler_vpl(N) / 4 - 2; }
+
+// One tile: columns [bx*STRIP, +STRIP) of rows [by*rows, +rows), marched
+// row by row by one wavefront.  `row` is the wavefront's LDS staging area of
+// VPL (N+1)^2 64 doubles (the current row's modes of each lane's variables,
+// [k*NM+q][lane]).
 template <int N, int STAGE>
-__device__ __forceinline__ void euler_pair_tile(const StageArgs &a, int bx, int by, int rows_per_block,
-                                                double *__restrict__ row) {
-  constexpr int NP = N + 1, NM = NP * NP;
+__device__ __forceinline__ void euler_tile(const StageArgs &a, int bx, int by, int rows_per_block,
+                                           double *__restrict__ row) {
+  constexpr int NP = N + 1, NM = NP * NP, VPL = euler_vpl(N), LPC = 4 / VPL, STRIP = euler_strip(N);
   const OrderTables &T = c_tab[N];
   const Geometry &g = a.geo;
   if (STAGE != 0 && a.sc->done) return;
-  const int lane = threadIdx.x, slot = lane >> 1, half = lane & 1;
-  const bool h1 = half != 0;
-  int col = bx * kPairStrip + slot - 1;
+  const int lane = threadIdx.x, slot = lane / LPC, part = lane % LPC;
+  int col = bx * STRIP + slot - 1;
   if (col > g.nx) col = g.nx;
-  const bool owner = slot >= 1 && slot <= kPairStrip && col < g.nx;
+  const bool owner = slot >= 1 && slot <= STRIP && col < g.nx;
   const int j0 = by * rows_per_block;
   const int j1 = min(j0 + rows_per_block, g.ny);
   const long plane = (long)g.nx * g.ny;
   const double dt = STAGE == 0 ? 0.0 : a.sc->dt;
-  const int v0 = 2 * half;  // first owned variable
+  const int v0 = VPL * part;  // first owned variable
   bool bad = false;
   double spx = 0.0, spy = 0.0;
 
-  // lane's two variables start at plane (2 half) * NM; offsets fit 32 bits
+  // the lane's variables start at plane v0 * NM; offsets fit 32 bits
   const double *ubase = a.u + (size_t)v0 * NM * plane;
-  auto load2 = [&](const CellIdx &c, double (&U)[2][NM]) {
+  auto load2 = [&](const CellIdx &c, double (&U)[VPL][NM]) {
     const unsigned idx = (unsigned)c.idx;
     const unsigned long long sx = c.fx ? 0x8000000000000000ull : 0ull, sy = c.fy ? 0x8000000000000000ull : 0ull;
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < VPL; ++k)
 #pragma unroll
       for (int q = 0; q < NM; ++q) {
         const int m = q % NP, n = q / NP;
@@ -876,9 +897,9 @@ __device__ __forceinline__ void euler_pair_tile(const StageArgs &a, int bx, int 
   auto rd = [&](int k, int q) -> double { return row[(k * NM + q) * 64 + lane]; };
   // trace of the two own variables on a face (dirf 0: x-face, 1: y-face)
   // from modes given by a getter
-  auto trace2 = [&](auto get, const double *b, int dirf, double (&out)[2][NP]) {
+  auto trace2 = [&](auto get, const double *b, int dirf, double (&out)[VPL][NP]) {
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < VPL; ++k) {
       double c[NP];
 #pragma unroll
       for (int t = 0; t < NP; ++t) {
@@ -896,9 +917,9 @@ __device__ __forceinline__ void euler_pair_tile(const StageArgs &a, int bx, int 
       }
     }
   };
-  auto lift2 = [&](const double (&F)[2][NP], const double *b, int dirf, int side, double scale, double (&L)[2][NM]) {
+  auto lift2 = [&](const double (&F)[VPL][NP], const double *b, int dirf, int side, double scale, double (&L)[VPL][NM]) {
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < VPL; ++k) {
       double phi[NP];
 #pragma unroll
       for (int t = 0; t < NP; ++t) {
@@ -919,56 +940,73 @@ __device__ __forceinline__ void euler_pair_tile(const StageArgs &a, int bx, int 
   };
 
   // south-face flux of row j0 from the halo row below; row j0 into LDS
-  double FS[2][NP];
+  double FS[VPL][NP];
   {
-    double P[2][NM], tn[2][NP], ts[2][NP];
+    double P[VPL][NM], tn[VPL][NP], ts[VPL][NP];
     load2(map_cell(g, col, j0 - 1), P);
     trace2([&](int k, int q) { return P[k][q]; }, T.bp, 1, tn);
     load2(map_cell(g, col, j0), P);
     trace2([&](int k, int q) { return P[k][q]; }, T.bm, 1, ts);
 #pragma unroll
-    for (int e = 0; e < NP; ++e) llf_pair<1>(tn[0][e], tn[1][e], ts[0][e], ts[1][e], h1, g.gamma, FS[0][e], FS[1][e], bad);
+    for (int e = 0; e < NP; ++e) {
+      double l[VPL], r[VPL], F[VPL];
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+      for (int k = 0; k < VPL; ++k) {
+        l[k] = tn[k][e];
+        r[k] = ts[k][e];
+      }
+      llf_lane<1, VPL>(l, r, part, g.gamma, F, bad);
+#pragma unroll
+      for (int k = 0; k < VPL; ++k) FS[k][e] = F[k];
+    }
+#pragma unroll
+    for (int k = 0; k < VPL; ++k)
 #pragma unroll
       for (int q = 0; q < NM; ++q) row[(k * NM + q) * 64 + lane] = P[k][q];
   }
   for (int j = j0; j < j1; ++j) {
     // next row in flight while this row is computed
-    double P[2][NM];
+    double P[VPL][NM];
     load2(map_cell(g, col, j + 1), P);
     const long cellj = (long)j * g.nx + col;
-    double L[2][NM];
+    double L[VPL][NM];
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < VPL; ++k)
 #pragma unroll
       for (int q = 0; q < NM; ++q) L[k][q] = 0.0;
     // x-faces: west face from slot-1's east trace; east flux from slot+1
     {
-      double te[2][NP], tw[2][NP], FW[2][NP], FE[2][NP];
+      double te[VPL][NP], tw[VPL][NP], FW[VPL][NP], FE[VPL][NP];
       trace2(rd, T.bp, 0, te);
       trace2(rd, T.bm, 0, tw);
 #pragma unroll
       for (int e = 0; e < NP; ++e) {
-        const double l0 = __shfl_up(te[0][e], 2), l1 = __shfl_up(te[1][e], 2);
-        llf_pair<0>(l0, l1, tw[0][e], tw[1][e], h1, g.gamma, FW[0][e], FW[1][e], bad);
+        double l[VPL], r[VPL], F[VPL];
+#pragma unroll
+        for (int k = 0; k < VPL; ++k) {
+          l[k] = __shfl_up(te[k][e], LPC);
+          r[k] = tw[k][e];
+        }
+        llf_lane<0, VPL>(l, r, part, g.gamma, F, bad);
+#pragma unroll
+        for (int k = 0; k < VPL; ++k) FW[k][e] = F[k];
       }
 #pragma unroll
-      for (int k = 0; k < 2; ++k)
+      for (int k = 0; k < VPL; ++k)
 #pragma unroll
-        for (int e = 0; e < NP; ++e) FE[k][e] = __shfl_down(FW[k][e], 2);
+        for (int e = 0; e < NP; ++e) FE[k][e] = __shfl_down(FW[k][e], LPC);
       lift2(FW, T.bm, 0, -1, g.rhx, L);
       lift2(FE, T.bp, 0, +1, g.rhx, L);
     }
     // volume term
 #pragma unroll 1
     for (int qy = 0; qy < NP; ++qy) {
-      double Fx[2][NP], Gy[2][NP];
+      double Fx[VPL][NP], Gy[VPL][NP];
 #pragma unroll
       for (int qx = 0; qx < NP; ++qx) {
-        double uq[2];
+        double uq[VPL];
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < VPL; ++k) {
           double s = 0.0;
 #pragma unroll
           for (int n = 0; n < NP; ++n) {
@@ -979,19 +1017,18 @@ __device__ __forceinline__ void euler_pair_tile(const StageArgs &a, int bx, int 
           }
           uq[k] = s;
         }
-        const double b0 = __shfl_xor(uq[0], 1), b1 = __shfl_xor(uq[1], 1);
-        const EulerPrim st = euler_prim(uq[0], uq[1], b0, b1, h1, g.gamma, bad);
-        double f0, f1, g0, g1;
-        euler_flux_pair<0>(st, uq[0], uq[1], h1, f0, f1);
-        euler_flux_pair<1>(st, uq[0], uq[1], h1, g0, g1);
+        double wst[4];
+        gather_state<VPL>(uq, part, wst);
+        const EulerPrim st = prim_of(wst, g.gamma, bad);
         const double w = T.wq[qx] * T.wq[qy];
-        Fx[0][qx] = w * g.rhx * f0;
-        Fx[1][qx] = w * g.rhx * f1;
-        Gy[0][qx] = w * g.rhy * g0;
-        Gy[1][qx] = w * g.rhy * g1;
+#pragma unroll
+        for (int k = 0; k < VPL; ++k) {
+          Fx[k][qx] = w * g.rhx * flux_comp<0>(st, uq[k], v0 + k);
+          Gy[k][qx] = w * g.rhy * flux_comp<1>(st, uq[k], v0 + k);
+        }
       }
 #pragma unroll
-      for (int k = 0; k < 2; ++k)
+      for (int k = 0; k < VPL; ++k)
 #pragma unroll
         for (int m = 0; m < NP; ++m) {
           double sa = 0.0, sb = 0.0;
@@ -1004,36 +1041,49 @@ __device__ __forceinline__ void euler_pair_tile(const StageArgs &a, int bx, int 
           for (int n = 0; n < NP; ++n) L[k][m + NP * n] += sa * T.bq[n][qy] + sb * T.dbq[n][qy];
         }
     }
-    // this row's u^n in flight during the y-face work
-    double Un[2][NM];
-    if (STAGE >= 2) {
+    // this row's u^n, in flight during the y-face work (Q3: loaded after it,
+    // as its registers are needed there)
+    double Un[VPL][NM];
+    auto load_un = [&]() {
       __builtin_amdgcn_sched_barrier(0);
       const double *nbase = a.un + (size_t)v0 * NM * plane;
       const unsigned idx = (unsigned)(owner ? cellj : 0);
 #pragma unroll
-      for (int k = 0; k < 2; ++k)
+      for (int k = 0; k < VPL; ++k)
 #pragma unroll
         for (int q = 0; q < NM; ++q) Un[k][q] = nbase[(size_t)(k * NM + q) * plane + idx];
-    }
+    };
+    if (STAGE >= 2 && N <= 2) load_un();
     // y-faces: carried south flux, north flux from the next row's south trace
     {
-      double tn[2][NP], ts[2][NP], FN[2][NP];
+      double tn[VPL][NP], ts[VPL][NP], FN[VPL][NP];
       trace2(rd, T.bp, 1, tn);
       trace2([&](int k, int q) { return P[k][q]; }, T.bm, 1, ts);
 #pragma unroll
-      for (int e = 0; e < NP; ++e) llf_pair<1>(tn[0][e], tn[1][e], ts[0][e], ts[1][e], h1, g.gamma, FN[0][e], FN[1][e], bad);
+      for (int e = 0; e < NP; ++e) {
+        double l[VPL], r[VPL], F[VPL];
+#pragma unroll
+        for (int k = 0; k < VPL; ++k) {
+          l[k] = tn[k][e];
+          r[k] = ts[k][e];
+        }
+        llf_lane<1, VPL>(l, r, part, g.gamma, F, bad);
+#pragma unroll
+        for (int k = 0; k < VPL; ++k) FN[k][e] = F[k];
+      }
       lift2(FS, T.bm, 1, -1, g.rhy, L);
       lift2(FN, T.bp, 1, +1, g.rhy, L);
 #pragma unroll
-      for (int k = 0; k < 2; ++k)
+      for (int k = 0; k < VPL; ++k)
 #pragma unroll
         for (int e = 0; e < NP; ++e) FS[k][e] = FN[k][e];
     }
+    if (STAGE >= 2 && N > 2) load_un();
     // RK stage combination (u^(s) of this row from LDS)
-    double m0 = 0.0, m1 = 0.0;
+    double mm[VPL];
     {
 #pragma unroll
-      for (int k = 0; k < 2; ++k)
+      for (int k = 0; k < VPL; ++k)
 #pragma unroll
         for (int q = 0; q < NM; ++q) {
           const long kk = (long)((v0 + k) * NM + q) * plane + cellj;
@@ -1046,20 +1096,21 @@ __device__ __forceinline__ void euler_pair_tile(const StageArgs &a, int bx, int 
             else r = Un[k][q] / 3.0 + 2.0 * (uo + dt * L[k][q]) / 3.0;
             a.out[kk] = r;
           }
-          if (q == 0) (k == 0 ? m0 : m1) = r * (T.b0[0] * T.b0[0]);
+          if (q == 0) mm[k] = r * (T.b0[0] * T.b0[0]);
         }
     }
     if (STAGE == 3 && a.want_speed) {
-      const double p0 = __shfl_xor(m0, 1), p1 = __shfl_xor(m1, 1);
+      double wm[4];
+      gather_state<VPL>(mm, part, wm);
       if (owner) {
-        const EulerPrim s = euler_prim(m0, m1, p0, p1, h1, g.gamma, bad);
+        const EulerPrim s = prim_of(wm, g.gamma, bad);
         spx = fmax(spx, euler_speed<0>(s, 0.0, g.gamma));
         spy = fmax(spy, euler_speed<1>(s, 0.0, g.gamma));
       }
     }
     // the next row becomes the current one (each lane touches only its own slots)
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < VPL; ++k)
 #pragma unroll
       for (int q = 0; q < NM; ++q) row[(k * NM + q) * 64 + lane] = P[k][q];
   }
@@ -1088,11 +1139,11 @@ __device__ inline int xcd_tile(int L, int total) {
 }
 
 template <int N, int STAGE>
-__global__ __launch_bounds__(64, 2) void k_stage_2d_euler_pair(StageArgs a, int rows_per_block) {
-  __shared__ double row[2 * (N + 1) * (N + 1) * 64];
+__global__ __launch_bounds__(64, 2) void k_stage_2d_euler(StageArgs a, int rows_per_block) {
+  __shared__ double row[euler_vpl(N) * (N + 1) * (N + 1) * 64];
   const int tiles_x = gridDim.x;
   const int w = xcd_tile(blockIdx.x + blockIdx.y * tiles_x, tiles_x * gridDim.y);
-  euler_pair_tile<N, STAGE>(a, w % tiles_x, w / tiles_x, rows_per_block, row);
+  euler_tile<N, STAGE>(a, w % tiles_x, w / tiles_x, rows_per_block, row);
 }
 
 // ---------------------------------------------------------------------------
@@ -1578,6 +1629,7 @@ dim3 cell_grid(const LaunchCtx &c, dim3 &block) {
 
 // Rows per marching wavefront: enough waves to fill 256 CUs several times.
 int march_rows(const LaunchCtx &c, int strip = kStrip) {
+  if (c.rows > 0) return c.rows;
   const long strips = (c.geo.nx + strip - 1) / strip;
   int rows = 32;
   while (rows > 4 && strips * ((c.geo.ny + rows - 1) / rows) < 8192) rows /= 2;
@@ -1588,9 +1640,10 @@ template <int D, int E, int NN, int STAGE>
 void stage_launch(const LaunchCtx &c, const StageArgs &a) {
   constexpr bool march = D == 2 && E == 0;
   if (D == 2 && E == 1 && c.use_march) {
-    const int rows = march_rows(c, kPairStrip);
-    dim3 grid((c.geo.nx + kPairStrip - 1) / kPairStrip, (c.geo.ny + rows - 1) / rows, 1);
-    hipLaunchKernelGGL((k_stage_2d_euler_pair<NN, STAGE>), grid, dim3(64), 0, S(c), a, rows);
+    constexpr int strip = euler_strip(NN);
+    const int rows = march_rows(c, strip);
+    dim3 grid((c.geo.nx + strip - 1) / strip, (c.geo.ny + rows - 1) / rows, 1);
+    hipLaunchKernelGGL((k_stage_2d_euler<NN, STAGE>), grid, dim3(64), 0, S(c), a, rows);
     return;
   }
   if (D == 2 && march && c.use_march) {

@@ -28,7 +28,7 @@ NEGW_SPLIT, NEGW_RAW = 0, 1
 # every symbol include/dg.h declares
 EXPORTS = ("dg_workspace_bytes", "dg_init", "dg_destroy", "dg_proj_nodes", "dg_project", "dg_residual",
            "dg_limit", "dg_cfl_dt", "dg_step", "dg_status", "dg_strerror", "dg_profile_enable", "dg_profile_read",
-           "dg_mlp_layout", "dg_mlp_features", "dg_mlp_forward", "dg_mlp_gradient", "dg_mlp_adam", "dg_set_learned",
+           "dg_autotune", "dg_mlp_layout", "dg_mlp_features", "dg_mlp_forward", "dg_mlp_gradient", "dg_mlp_adam", "dg_set_learned",
            "dg_batch_workspace_bytes", "dg_batch_init", "dg_batch_destroy", "dg_batch_autotune", "dg_batch_set_tiles",
            "dg_batch_step", "dg_batch_set_learned")
 PROF_KINDS = ("stage1", "stage23", "limiter", "dt")
@@ -93,6 +93,7 @@ def lib():
             "dg_status": [vp],
             "dg_profile_enable": [vp, ctypes.c_int],
             "dg_profile_read": [vp, P(d), P(ctypes.c_int64), P(ctypes.c_int64), ctypes.c_int],
+            "dg_autotune": [vp, vp, P(i32), P(ctypes.c_float)],
             "dg_mlp_layout": [i32, P(i32), P(ctypes.c_int64), P(ctypes.c_int64)],
             "dg_mlp_features": [vp, vp, vp, vp],
             "dg_mlp_forward": [vp, i32, i32, vp, vp, vp, vp],
@@ -261,6 +262,14 @@ class Problem:
 
     def status(self):
         return lib().dg_status(self._h)
+
+    def autotune(self, state):
+        """Tile height of the 2D stage kernels timed on this state: (rows, ms)."""
+        self._check_state(state)
+        rows = ctypes.c_int32()
+        ms = ctypes.c_float()
+        self._rc(lib().dg_autotune(self._h, _ptr(state), ctypes.byref(rows), ctypes.byref(ms)), "dg_autotune", True)
+        return rows.value, ms.value
 
     def profile(self, enable=True):
         self._rc(lib().dg_profile_enable(self._h, 1 if enable else 0), "dg_profile_enable")

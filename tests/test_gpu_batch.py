@@ -154,3 +154,18 @@ def test_batch_finished_instances_untouched():
     assert steps[0] == 0 and steps[2] == 0 and steps[1] > 0 and t[1] == 0.004
     assert torch.equal(b.view(0), before[: b.view(0).numel()].view(b.shapes[0]))
 
+
+
+def test_single_mesh_autotune_changes_no_result():
+    from paper_1904_11147_amd import dg
+    from paper_1904_11147_amd import workloads as W
+    wl = W.riemann2d(n=96, order=2, seed=41).with_(ny=70)
+    p = dg.problem_from_workload(wl)
+    s0 = dg.initial_state(p, wl, limit=True)
+    a = s0.clone()
+    t_a, n_a = p.step(a, 0.0, wl.t_end, max_steps=5)
+    rows, ms = p.autotune(s0)
+    assert rows in (4, 8, 16, 32, 64) and ms > 0.0
+    b = s0.clone()
+    t_b, n_b = p.step(b, 0.0, wl.t_end, max_steps=5)
+    assert (t_a, n_a) == (t_b, n_b) and torch.equal(a, b)
