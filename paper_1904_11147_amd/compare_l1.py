@@ -1,0 +1,123 @@
+"""Plain per-instance runs vs batched runs (plain and learned indicator) of a
+mixed batch of four-state Riemann problems, each to its final time: whole-run
+throughput and the final L1 error of every instance.
+
+    python -m paper_1904_11147_amd.compare_l1 --count 24 --nmin 64 --nmax 128 --out result.json
+
+L1 is that of the density cell means against the plain method on the
+2x-refined mesh, averaged down (the refined run is the reference for every
+variant).  Instances whose plain or reference run meets a non-physical state
+(no positivity limiter is part of the method) are reported and left out of
+the L1 comparison.  Progress is printed per instance and per variant.
+"""
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import dg, learned
+from . import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _means(state):
+    return (state[0, 0] / 2.0).double()
+
+
+def _down(fine):
+    ny, nx = fine.shape
+    return fine.reshape(ny // 2, 2, nx // 2, 2).mean(dim=(1, 3))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--count", type=int, default=24)
+    ap.add_argument("--first-seed", type=int, default=20000)
+    ap.add_argument("--nmin", type=int, default=64)
+    ap.add_argument("--nmax", type=int, default=128)
+    ap.add_argument("--t-end", type=float, default=0.25)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+
+    wls = W.riemann2d_batch(count=a.count, first_seed=a.first_seed, nmin=a.nmin, nmax=a.nmax, t_end=a.t_end)
+    nets = {o: learned.MLP.load(os.path.join(HERE, "weights", f"indicator_q{o}.npz")) for o in (1, 2, 3)}
+    rows = []
+    # references and plain per-instance runs
+    t_plain = 0.0
+    dofs_plain = 0.0
+    for i, wl in enumerate(wls):
+        r = {"seed": wl.seed, "n": wl.nx, "order": wl.order}
+        wf = W.riemann2d(n=2 * wl.nx, order=wl.order, seed=wl.seed, t_end=wl.t_end)
+        pf = dg.problem_from_workload(wf)
+        sf = dg.initial_state(pf, wf, limit=True)
+        pf.step(sf, 0.0, wf.t_end, allow_nonphysical=True)
+        r["reference_nonphysical"] = pf.status() != 0
+        r["_ref"] = _down(_means(sf))
+        pf.close()
+        del sf
+        p = dg.problem_from_workload(wl)
+        s = dg.initial_state(p, wl, limit=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, n = p.step(s, 0.0, wl.t_end, allow_nonphysical=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        r["plain_nonphysical"] = p.status() != 0
+        r["plain_steps"] = n
+        r["plain_L1"] = float((_means(s) - r["_ref"]).abs().mean())
+        t_plain += el
+        dofs_plain += wl.dofs * n
+        p.close()
+        rows.append(r)
+        print(f"instance {i}: n={wl.nx} Q{wl.order} plain {n} steps", flush=True)
+    res = {"count": a.count, "sizes": [a.nmin, a.nmax], "t_end": a.t_end,
+           "plain_per_instance": {"seconds": t_plain, "dof_updates_per_s": dofs_plain / t_plain}}
+    for kind in ("batched_plain", "batched_learned"):
+        over = {"indicator": dg.IND_LEARNED} if kind == "batched_learned" else {}
+        b = dg.batch_from_workloads(wls, limit=False, **over)
+        for i, wl in enumerate(wls):  # the same TVB-limited initial states
+            p = dg.problem_from_workload(wl)
+            p.limit(b.view(i), want_margin=False)
+            p.close()
+        if kind == "batched_learned":
+            for o in (1, 2, 3):
+                b.set_learned(o, nets[o].w, nets[o].master)
+        b.autotune()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t, steps, status, troubled = b.step(0.0, [wl.t_end for wl in wls], allow_nonphysical=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        dofs = float(sum(wl.dofs * k for wl, k in zip(wls, steps)))
+        res[kind] = {"seconds": el, "dof_updates_per_s": dofs / el,
+                     "troubled_cell_stages": int(troubled)}
+        for i, r in enumerate(rows):
+            r[kind + "_nonphysical"] = bool(status[i] != 0)
+            r[kind + "_steps"] = int(steps[i])
+            r[kind + "_L1"] = float((_means(b.view(i)) - r["_ref"]).abs().mean())
+        b.close()
+        print(f"{kind}: {el:.2f} s", flush=True)
+    ok = [r for r in rows if not (r["reference_nonphysical"] or r["plain_nonphysical"] or
+                                  r["batched_learned_nonphysical"])]
+    res["compared"] = len(ok)
+    res["L1_ratio_learned_over_plain"] = {
+        "mean": float(np.mean([r["batched_learned_L1"] / r["plain_L1"] for r in ok])) if ok else None,
+        "max": float(np.max([r["batched_learned_L1"] / r["plain_L1"] for r in ok])) if ok else None}
+    res["speedup_batched_learned_over_plain"] = (res["batched_learned"]["dof_updates_per_s"] /
+                                                 res["plain_per_instance"]["dof_updates_per_s"])
+    res["speedup_batched_plain_over_plain"] = (res["batched_plain"]["dof_updates_per_s"] /
+                                               res["plain_per_instance"]["dof_updates_per_s"])
+    for r in rows:
+        r.pop("_ref")
+    res["instances"] = rows
+    print(json.dumps({k: v for k, v in res.items() if k != "instances"}), flush=True)
+    if a.out:
+        json.dump(res, open(a.out, "w"), indent=1)
+
+
+if __name__ == "__main__":
+    main()

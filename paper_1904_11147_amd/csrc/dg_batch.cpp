@@ -270,6 +270,8 @@ int dg_batch_init(const dg_config *cfgs, int32_t n, void *workspace, size_t work
     I.order = cf.order;
     I.tiles_x = (cf.nx + strip_cols(cf.order) - 1) / strip_cols(cf.order);
     I.segs = (cf.nx + 63) / 64 * cf.ny;
+    I.ltiles = ((cf.nx + dg::kLmStrip - 1) / dg::kLmStrip + dg::lm_waves(cf.order) - 1) / dg::lm_waves(cf.order) *
+               ((cf.ny + dg::kLmRows - 1) / dg::kLmRows);
     I.indicator = cf.indicator;
     I.cfl = cf.cfl;
     b->state_elems[i] = L.state_bytes[i] / sizeof(double);

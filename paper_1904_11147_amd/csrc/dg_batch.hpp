@@ -46,26 +46,28 @@ __global__ __launch_bounds__(1024) void k_batch_decide(BatchInst *__restrict__ i
   if (wave < 1 || wave > kMaxN) return;
   const int order = wave;
   BatchQueue &q = queue[order];
-  int base = 0, tiles = 0, segs = 0;
+  int base = 0, tiles = 0, segs = 0, ltiles = 0;
   for (int i0 = 0; i0 < n; i0 += 64) {
     const int i = i0 + lane;
-    int ca = 0, ct = 0, cs = 0;
+    int ca = 0, ct = 0, cs = 0, cl = 0;
     if (i < n) {
       const BatchInst &I = inst[i];
       if (I.order == order && !I.sc->done) {
         ca = 1;
         ct = I.tiles_x * I.tiles_y;
         cs = I.segs;
+        cl = I.ltiles;
       }
     }
     const bool act = ca != 0;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-      const int a = __shfl_up(ca, o), b = __shfl_up(ct, o), c = __shfl_up(cs, o);
+      const int a = __shfl_up(ca, o), b = __shfl_up(ct, o), c = __shfl_up(cs, o), d = __shfl_up(cl, o);
       if (lane >= o) {
         ca += a;
         ct += b;
         cs += c;
+        cl += d;
       }
     }
     if (act) {
@@ -73,15 +75,18 @@ __global__ __launch_bounds__(1024) void k_batch_decide(BatchInst *__restrict__ i
       q.inst[k] = i;
       q.tile_end[k] = tiles + ct;
       q.seg_end[k] = segs + cs;
+      q.ltile_end[k] = ltiles + cl;
     }
     base += __shfl(ca, 63);
     tiles += __shfl(ct, 63);
     segs += __shfl(cs, 63);
+    ltiles += __shfl(cl, 63);
   }
   if (lane == 0) {
     q.n_active = base;
     q.total_tiles = tiles;
     q.total_segs = segs;
+    q.total_ltiles = ltiles;
     q.count[0] = q.count[1] = q.count[2] = q.count[3] = 0;
     atomicAdd(active, base);
   }
@@ -190,31 +195,49 @@ __device__ inline void append_batch(BatchQueue *q, int slot, long long *list, De
 }
 
 // Troubled-cell indicator over the queued row segments (one wavefront per
-// segment).  IND: DG_IND_TVB, DG_IND_ALL or DG_IND_LEARNED.
+// segment).  IND: DG_IND_TVB or DG_IND_ALL.
 template <int N, int SLOT, int IND>
-__global__ __launch_bounds__(64, 2) void k_batch_indicator(const BatchInst *__restrict__ inst, BatchQueue *q,
-                                                           long long *__restrict__ list, BatchLearned BL) {
-  constexpr int NM = (N + 1) * (N + 1), F = 5 * NM * 4, KP = (F + 15) / 16 * 16;
-  __shared__ float zs[64];
-  __shared__ uint16_t feat[IND == DG_IND_LEARNED ? learned_feat_lds<N>() : 1];
-  const LearnedArgs L{BL.W, BL.M, MlpLayout{F, KP}, BL.band_lo, BL.band_hi, nullptr};
+__global__ __launch_bounds__(64) void k_batch_indicator(const BatchInst *__restrict__ inst, BatchQueue *q,
+                                                        long long *__restrict__ list) {
   const int total = q->total_segs;
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const SegItem s = seg_item(inst, q, w);
     const BatchInst &I = inst[s.id];
     const Geometry &g = I.geo;
-    const double *u = limit_target<SLOT>(I);
     const int i = s.i0 + threadIdx.x;
     bool flag = false;
     double mg = INFINITY;
-    if (IND == DG_IND_LEARNED) {
-      const float p = learned_probability<N, 1>(u, g, s.i0, s.j, L, zs, feat);
-      if (i < g.nx) flag = p > BL.band_hi ? true : (p < BL.band_lo ? false : tvb_cell<N, 1, 2>(u, g, i, s.j, mg));
-    } else if (i < g.nx) {
-      flag = IND == DG_IND_ALL ? true : tvb_cell<N, 1, 2>(u, g, i, s.j, mg);
-    }
+    if (i < g.nx) flag = IND == DG_IND_ALL ? true : tvb_cell<N, 1, 2>(limit_target<SLOT>(I), g, i, s.j, mg);
     const long long cell = (long long)s.j * g.nx + i;
     append_batch(q, SLOT, list, I.sc, flag, ((long long)s.id << 32) | cell);
+  }
+}
+
+// The learned indicator over the queued learned tiles (lm_waves(N) strips of
+// kLmRows rows each); the block keeps the order's network in LDS.
+template <int N, int SLOT>
+__global__ __launch_bounds__(64 * lm_waves(N), 2) void k_batch_learned(const BatchInst *__restrict__ inst, BatchQueue *q,
+                                                                    long long *__restrict__ list, BatchLearned BL) {
+  using S = LmShape<N>;
+  __shared__ __align__(16) uint16_t lds[S::LDS];
+  const LearnedArgs L{BL.W, BL.M, MlpLayout{4 * S::FV, S::KP}, BL.band_lo, BL.band_hi, nullptr};
+  lm_load_weights<N>(L, lds);
+  const int wave = threadIdx.x >> 6;
+  const int total = q->total_ltiles;
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int k = queue_find(q->ltile_end, q->n_active, w);
+    const int id = q->inst[k];
+    const BatchInst &I = inst[id];
+    const Geometry &g = I.geo;
+    const int local = w - (k ? q->ltile_end[k - 1] : 0);
+    const int groups = ((g.nx + kLmStrip - 1) / kLmStrip + S::WAVES - 1) / S::WAVES;
+    const int x0 = ((local % groups) * S::WAVES + wave) * kLmStrip;
+    const int j0 = (local / groups) * kLmRows, j1 = min(j0 + kLmRows, g.ny);
+    if (x0 >= g.nx) continue;  // no barrier in the loop
+    lm_strip<N>(limit_target<SLOT>(I), g, x0, j0, j1, L, lds, lds + S::W1 + S::W2 + wave * S::FEAT,
+                [&](bool active, bool flag, double, float, long cell) {
+                  append_batch(q, SLOT, list, I.sc, active && flag, ((long long)id << 32) | cell);
+                });
   }
 }
 

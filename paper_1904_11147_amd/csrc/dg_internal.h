@@ -91,6 +91,11 @@ struct LaunchCtx {
   double band_lo, band_hi;
 };
 
+// Work layout of the learned indicator kernels: blocks of lm_waves(N)
+// wavefronts, each marching kLmRows rows of a kLmStrip-column strip.
+constexpr int kLmStrip = 14, kLmRows = 16;
+constexpr int lm_waves(int order) { return order == 3 ? 8 : 4; }  // constexpr: usable in device code too
+
 // ---------------------------------------------------------------------------
 // Batched execution: many independent 2D Euler meshes of any size and order,
 // each with its own time step, advanced together.
@@ -107,7 +112,9 @@ struct BatchInst {
   int32_t rows;        // rows per stage-kernel tile
   int32_t tiles_x, tiles_y;
   int32_t segs;        // 64-cell row segments (indicator work items)
+  int32_t ltiles;      // learned-indicator blocks (lm_waves strips x kLmRows rows)
   int32_t indicator;   // DG_IND_*
+  int32_t pad;
   double cfl;
 };
 
@@ -115,11 +122,12 @@ struct BatchInst {
 // time-step decision.  Entries are the active instances in index order with
 // inclusive prefix sums of their stage tiles and indicator segments.
 struct BatchQueue {
-  int32_t n_active, total_tiles, total_segs, pad0;
+  int32_t n_active, total_tiles, total_segs, total_ltiles;
   int32_t count[4];  // troubled-list length of the limiter pass after stage 1, 2, 3
   int32_t inst[kBatchMax];
   int32_t tile_end[kBatchMax];
   int32_t seg_end[kBatchMax];
+  int32_t ltile_end[kBatchMax];
 };
 
 struct BatchLearned {  // learned indicator of one order (null weights: not set)

@@ -1700,8 +1700,10 @@ int launch_limit(const LaunchCtx &c, double *u, double *side, int count_slot, ui
       if (c.indicator == DG_IND_LEARNED && !flags_override) {
         LearnedArgs L{c.mlp_w, c.mlp_m, MlpLayout{5 * NM * NV, (5 * NM * NV + 15) / 16 * 16}, (float)c.band_lo,
                       (float)c.band_hi, c.mlp_prob};
-        hipLaunchKernelGGL((k_indicator_learned<n, e>), dim3((c.geo.nx + 63) / 64, c.geo.ny), dim3(64), 0, S(c), a,
-                           L);
+        constexpr int waves = lm_waves(n);
+        const int groups = ((c.geo.nx + kLmStrip - 1) / kLmStrip + waves - 1) / waves;
+        hipLaunchKernelGGL((k_indicator_learned<n, e>), dim3(groups, (c.geo.ny + kLmRows - 1) / kLmRows),
+                           dim3(64 * waves), 0, S(c), a, L, kLmRows);
         learned = true;
       }
     }
@@ -1867,14 +1869,14 @@ int batch_launch_limit(const BatchCtx &b, int order, int slot) {
     auto go = [&](auto SL) {
       constexpr int s = decltype(SL)::value;
       if (b.indicator == DG_IND_LEARNED)
-        hipLaunchKernelGGL((k_batch_indicator<n, s, DG_IND_LEARNED>), dim3(b.grid_cap), dim3(64), 0, st, b.inst, q,
+        hipLaunchKernelGGL((k_batch_learned<n, s>), dim3(b.grid_cap / 2), dim3(64 * lm_waves(n)), 0, st, b.inst, q,
                            list, L);
       else if (b.indicator == DG_IND_ALL)
         hipLaunchKernelGGL((k_batch_indicator<n, s, DG_IND_ALL>), dim3(4 * b.grid_cap), dim3(64), 0, st, b.inst, q,
-                           list, L);
+                           list);
       else
         hipLaunchKernelGGL((k_batch_indicator<n, s, DG_IND_TVB>), dim3(4 * b.grid_cap), dim3(64), 0, st, b.inst, q,
-                           list, L);
+                           list);
       if (b.limiter == DG_LIM_CSWENO) {
         hipLaunchKernelGGL((k_batch_csweno<n, s>), dim3(b.grid_cap), dim3(kBlock), 0, st, b.inst, q, list);
         hipLaunchKernelGGL((k_batch_scatter<n, s>), dim3(b.grid_cap), dim3(kBlock), 0, st, b.inst, q, list);

@@ -422,9 +422,10 @@ __global__ __launch_bounds__(kBlock) void k_mlp_adam(float *M, float *m1, float 
   }
 }
 
-// The limiter's learned indicator (2D): one wavefront per 64 consecutive cells
-// of a row.  Features -> LDS (bf16) -> four 16-cell tiles through the network;
-// p > band_hi flags, p < band_lo clears, otherwise the TVB decision.
+// ---------------------------------------------------------------------------
+// The limiter's learned indicator (2D Euler): p > band_hi flags a cell,
+// p < band_lo clears it, and the TVB decision settles the band in between.
+// ---------------------------------------------------------------------------
 struct LearnedArgs {
   const uint16_t *W;
   const float *M;
@@ -433,148 +434,204 @@ struct LearnedArgs {
   float *prob;  // may be null: per-cell probability
 };
 
-// Network probabilities of the 64 cells (i0 + lane, j) of one row segment
-// (columns beyond the mesh repeat the last one); returns this lane's p.  One
-// wavefront; zs is a 64-float LDS area and feat one of learned_feat_lds<N>()
-// bf16 values.  2D Euler only.
-//
-// The layers are evaluated transposed, H^T = W X^T, with the weights as the
-// MFMA A operand: lane (r, g) builds the B fragments of cell r from
-// variable g's features (the per-variable normalisation stays in the lane),
-// and each layer's output fragments are the next layer's B fragments.  The
-// weight fragments are loaded once per two 16-cell tiles.  Features go
-// through the lane's own LDS slots, from which the fragments are read.
-constexpr int kLearnedTiles = 2;
+// Work layout: a block of lm_waves(N) wavefronts shares the network's
+// weights in LDS; each wavefront owns a strip of kLmStrip columns (lane
+// slots 1..14 of its 16; slots 0 and 15 are the x-halo) and marches up a
+// chunk of rows.  Lane (r, g) holds variable g of slot r.  The rows below,
+// at and above the current one are kept in registers (one load per value),
+// west and east neighbours come from the adjacent slots.  The network is
+// evaluated transposed, H^T = W X^T, with the weights as the MFMA A operand:
+// a lane's features (variable g of cell r) are its B fragments and each
+// layer's output fragments are the next layer's B fragments.
 template <int N>
-constexpr int learned_feat_lds() {
-  return kLearnedTiles * ((5 * (N + 1) * (N + 1) + 3) / 4) * 64 * 4;
+struct LmShape {
+  static constexpr int NP = N + 1, NM = NP * NP, FV = 5 * NM, BV = (FV + 3) / 4 * 4, KB = BV / 4;
+  static constexpr int KP = 4 * BV;  // padded input width (= (F + 15) / 16 * 16 for F = 4 FV)
+  static constexpr int W1 = kHidden * KP, W2 = kHidden * kHidden, FEAT = KB * 256;
+  static constexpr int WAVES = lm_waves(N);
+  static constexpr int LDS = W1 + W2 + WAVES * FEAT;
+};
+
+// Copies the weights into LDS in fragment order (whole block), then a barrier.
+template <int N>
+__device__ inline void lm_load_weights(const LearnedArgs &L, uint16_t *wl) {
+  using S = LmShape<N>;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const uint16_t *__restrict__ W1P = L.W + L.lay.w1p();
+  for (int k = tid; k < S::W1 / 4; k += nt)
+    reinterpret_cast<uint2 *>(wl)[k] = reinterpret_cast<const uint2 *>(W1P)[k];
+  // W2 A-fragments: element e of lane (r, g), k-block kb, output block nb is W2[16 nb + r][16 kb + 4 g + e]
+  const uint16_t *__restrict__ W2 = L.W + L.lay.w2();
+  for (int k = tid; k < S::W2; k += nt) {
+    const int e = k & 3, ln = (k >> 2) & 63, kb = (k >> 8) & 3, nb = k >> 10;
+    wl[S::W1 + k] = W2[(16 * nb + (ln & 15)) * kHidden + 16 * kb + 4 * (ln >> 4) + e];
+  }
+  __syncthreads();
 }
 
-template <int N, int EQ>
-__device__ inline float learned_probability(const double *__restrict__ u, const Geometry &g, int i0, int j,
-                                            const LearnedArgs &L, float *zs, uint16_t *feat) {
-  static_assert(EQ == 1, "learned indicator: 2D Euler");
-  constexpr int NP = N + 1, NM = NP * NP, FV = 5 * NM, BV = (FV + 3) / 4 * 4, KB = BV / 4;
-  constexpr int TILES = kLearnedTiles;
-  const int lane = threadIdx.x, r = lane & 15, gv = lane >> 4;  // cell r of a tile, variable gv
+// One wavefront's strip: columns x0-1 .. x0+14 (owned x0 .. x0+13), rows
+// j0 .. j1-1.  emit(active, flag, margin, p, cell) is called by every lane
+// once per row (active: an owned cell, from lane group 0).
+template <int N, typename Emit>
+__device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g, int x0, int j0, int j1,
+                                const LearnedArgs &L, const uint16_t *__restrict__ wl, uint16_t *__restrict__ feat,
+                                Emit &&emit) {
+  using S = LmShape<N>;
+  constexpr int NP = S::NP, NM = S::NM, FV = S::FV, BV = S::BV, KB = S::KB;
+  const OrderTables &T = c_tab[N];
+  const int lane = threadIdx.x & 63, r = lane & 15, gv = lane >> 4;
+  int col = x0 + r - 1;
+  if (col > g.nx) col = g.nx;
+  const bool owner = r >= 1 && r <= kLmStrip && col < g.nx;
   const long plane = (long)g.nx * g.ny;
-  const uint16_t *__restrict__ W = L.W;
-  const float *__restrict__ M = L.M;
-  const MlpLayout &lay = L.lay;
   const double *__restrict__ up = u + (long)gv * NM * plane;
-  const int di[5] = {0, -1, 1, 0, 0}, dj[5] = {0, 0, 0, -1, 1};
-#pragma unroll 1
-  for (int t0 = 0; t0 < 4; t0 += TILES) {
-#pragma unroll 1
-    for (int tt = 0; tt < TILES; ++tt) {
-      int i = i0 + 16 * (t0 + tt) + r;
-      if (i >= g.nx) i = g.nx - 1;
-      const double c0 = up[(long)j * g.nx + i];
-      double mx = g.tvb_Mx;
-      double vals[FV];
+  const float *__restrict__ M = L.M;
+  const uint16_t *__restrict__ W = L.W;
+  const MlpLayout &lay = L.lay;
+  auto loadrow = [&](int jj, double (&R)[NM]) {
+    if (jj > g.ny) jj = g.ny;
+    const CellIdx ci = map_cell(g, col, jj);
 #pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        const CellIdx ci = map_cell(g, i + di[c], j + dj[c]);
+    for (int q = 0; q < NM; ++q) {
+      const int m = q % NP, n = q / NP;
+      const double v = up[(long)q * plane + ci.idx];
+      R[q] = ((ci.fx && (m & 1)) != (ci.fy && (n & 1))) ? -v : v;
+    }
+  };
+  double Sv[NM], Cv[NM], Nv[NM];
+  loadrow(j0 - 1, Sv);
+  loadrow(j0, Cv);
+  loadrow(j0 + 1, Nv);
+  uint16_t *fl = feat + lane * 4;  // feature f at fl[(f / 4) * 256 + f % 4]
+#pragma unroll
+  for (int f = FV; f < BV; ++f) fl[(f / 4) * 256 + f % 4] = 0;
+  const double k0 = T.b0[0] * T.b0[0];
+  for (int j = j0; j < j1; ++j) {
+    double Pv[NM];
+    loadrow(j + 2, Pv);  // in flight while this row is evaluated
+    double Wv[NM], Ev[NM];
+#pragma unroll
+    for (int q = 0; q < NM; ++q) {
+      Wv[q] = __shfl_up(Cv[q], 1, 16);
+      Ev[q] = __shfl_down(Cv[q], 1, 16);
+    }
+    // TVB decision of this variable (the expressions of tvb_cell), combined over the cell's lanes
+    bool tflag = false;
+    double tmg = INFINITY;
+    {
+      const double mean = Cv[0] * k0;
+#pragma unroll
+      for (int dir = 0; dir < 2; ++dir) {
+        const double Mh2 = dir == 0 ? g.tvb_Mx : g.tvb_My;
+        const double mp = (dir == 0 ? Ev[0] : Nv[0]) * k0, mm = (dir == 0 ? Wv[0] : Sv[0]) * k0;
+        double upv = 0.0, umv = 0.0;
 #pragma unroll
         for (int q = 0; q < NM; ++q) {
           const int m = q % NP, n = q / NP;
-          double v = up[(long)q * plane + ci.idx];
-          if ((ci.fx && (m & 1)) != (ci.fy && (n & 1))) v = -v;
-          if (q == 0) v -= c0;
-          mx = fmax(mx, fabs(v));
-          vals[c * NM + q] = v;
+          const double bu = dir == 0 ? T.bp[m] * T.b0[n] : T.b0[m] * T.bp[n];
+          const double bd = dir == 0 ? T.bm[m] * T.b0[n] : T.b0[m] * T.bm[n];
+          upv += Cv[q] * bu;
+          umv += Cv[q] * bd;
         }
+        const double dp = mp - mean, dm = mean - mm;
+        tflag |= tvb_test(upv - mean, dp, dm, Mh2, tmg);
+        tflag |= tvb_test(mean - umv, dp, dm, Mh2, tmg);
       }
+      int fi = tflag ? 1 : 0;
+      fi |= __shfl_xor(fi, 16);
+      fi |= __shfl_xor(fi, 32);
+      tflag = fi != 0;
+      tmg = fmin(tmg, __shfl_xor(tmg, 16));
+      tmg = fmin(tmg, __shfl_xor(tmg, 32));
+    }
+    // features: C, W, E, S, N of variable gv; mode 0 relative to the centre's; scaled
+    {
+      const double c0 = Cv[0];
+      double mx = g.tvb_Mx;
+      auto val = [&](int f) -> double {
+        const int c = f / NM, q = f % NM;
+        const double v = c == 0 ? Cv[q] : (c == 1 ? Wv[q] : (c == 2 ? Ev[q] : (c == 3 ? Sv[q] : Nv[q])));
+        return q == 0 ? v - c0 : v;
+      };
+#pragma unroll
+      for (int f = 0; f < FV; ++f) mx = fmax(mx, fabs(val(f)));
       const double inv = 1.0 / mx;
-      uint16_t *fl = feat + (long)tt * KB * 256 + lane * 4;  // element f at fl[(f / 4) * 256 + f % 4]
 #pragma unroll
-      for (int f = 0; f < FV; ++f) fl[(f / 4) * 256 + f % 4] = f2bf((float)(vals[f] * inv));
-#pragma unroll
-      for (int f = FV; f < BV; ++f) fl[(f / 4) * 256 + f % 4] = 0;
+      for (int f = 0; f < FV; ++f) fl[(f / 4) * 256 + f % 4] = f2bf((float)(val(f) * inv));
     }
     // layer 1: H1^T = W1 X^T
-    f32x4_t h[TILES][4];
+    f32x4_t h[4];
 #pragma unroll
-    for (int tt = 0; tt < TILES; ++tt)
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb) h[tt][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
+    for (int nb = 0; nb < 4; ++nb) h[nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
     for (int kb = 0; kb < KB; ++kb) {
-      bf16x4_t xf[TILES];
+      const bf16x4_t x = load4(feat + (kb * 64 + lane) * 4);
 #pragma unroll
-      for (int tt = 0; tt < TILES; ++tt) xf[tt] = load4(feat + ((long)(tt * KB + kb) * 64 + lane) * 4);
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
-        const bf16x4_t a = load4(W + lay.w1p() + ((long)(nb * KB + kb) * 64 + lane) * 4);
-#pragma unroll
-        for (int tt = 0; tt < TILES; ++tt) h[tt][nb] = mfma16(a, xf[tt], h[tt][nb]);
-      }
+      for (int nb = 0; nb < 4; ++nb) h[nb] = mfma16(load4(wl + ((nb * KB + kb) * 64 + lane) * 4), x, h[nb]);
     }
-    bf16x4_t h1[TILES][4];
+    bf16x4_t h1[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) h1[nb][e] = (short)f2bf(fmaxf(h[nb][e] + M[lay.mb1() + 16 * nb + 4 * gv + e], 0.f));
+    // layer 2: H2^T = W2 H1^T
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) h[nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+        h[nb] = mfma16(load4(wl + S::W1 + ((nb * 4 + kb) * 64 + lane) * 4), h1[kb], h[nb]);
+    // layer 3 and the decision
+    float part = 0.f;
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const float b = M[lay.mb1() + 16 * nb + 4 * gv + e];
-#pragma unroll
-        for (int tt = 0; tt < TILES; ++tt) h1[tt][nb][e] = (short)f2bf(fmaxf(h[tt][nb][e] + b, 0.f));
+        const int k = 16 * nb + 4 * gv + e;
+        part += bf2f(f2bf(fmaxf(h[nb][e] + M[lay.mb2() + k], 0.f))) * bf2f(W[lay.w3() + k]);
       }
-    // layer 2: H2^T = W2 H1^T
+    part += __shfl_xor(part, 16);
+    part += __shfl_xor(part, 32);
+    const float p = 1.f / (1.f + __expf(-(part + M[lay.mb3()])));
+    bool flag = false;
+    double mg = INFINITY;
+    if (p > L.band_hi) flag = true;
+    else if (!(p < L.band_lo)) {
+      flag = tflag;
+      mg = tmg;
+    }
+    emit(owner && gv == 0, flag, mg, p, (long)j * g.nx + col);
 #pragma unroll
-    for (int tt = 0; tt < TILES; ++tt)
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb) h[tt][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
-        const bf16x4_t a = load4(W + lay.w2() + (16 * nb + r) * kHidden + 16 * kb + 4 * gv);
-#pragma unroll
-        for (int tt = 0; tt < TILES; ++tt) h[tt][nb] = mfma16(a, h1[tt][kb], h[tt][nb]);
-      }
-    // layer 3: z = w3 . h2 + b3, summed over the lane's 16 hidden units, then over the 4 groups
-#pragma unroll
-    for (int tt = 0; tt < TILES; ++tt) {
-      float part = 0.f;
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int k = 16 * nb + 4 * gv + e;
-          part += bf2f(f2bf(fmaxf(h[tt][nb][e] + M[lay.mb2() + k], 0.f))) * bf2f(W[lay.w3() + k]);
-        }
-      part += __shfl_xor(part, 16);
-      part += __shfl_xor(part, 32);
-      if (gv == 0) zs[16 * (t0 + tt) + r] = part + M[lay.mb3()];
+    for (int q = 0; q < NM; ++q) {
+      Sv[q] = Cv[q];
+      Cv[q] = Nv[q];
+      Nv[q] = Pv[q];
     }
   }
-  __syncthreads();  // one wavefront per block: orders zs
-  const float p = 1.f / (1.f + __expf(-zs[lane]));
-  __syncthreads();  // zs is reused by the next segment
-  return p;
 }
 
+// Single mesh: grid (strip groups, row chunks); block = lm_waves(N) wavefronts.
 template <int N, int EQ>
-__global__ __launch_bounds__(64, 2) void k_indicator_learned(LimitArgs a, LearnedArgs L) {
-  __shared__ float zs[64];
-  __shared__ uint16_t feat[learned_feat_lds<N>()];
-  const Geometry &g = a.geo;
+__global__ __launch_bounds__(64 * lm_waves(N), 2) void k_indicator_learned(LimitArgs a, LearnedArgs L, int rows) {
+  static_assert(EQ == 1, "learned indicator: 2D Euler");
+  using S = LmShape<N>;
+  __shared__ __align__(16) uint16_t lds[S::LDS];
   if (a.check_done && a.sc->done) return;
-  const int lane = threadIdx.x;
-  const int i = blockIdx.x * 64 + lane, j = blockIdx.y;
-  const bool active = i < g.nx && j < g.ny;
-  const long cell = (long)j * g.nx + i;
-  const float p = learned_probability<N, EQ>(a.u, g, blockIdx.x * 64, j, L, zs, feat);
-  bool flag = false;
-  double mg = INFINITY;
-  if (active) {
-    if (L.prob) L.prob[cell] = p;
-    if (a.ovr) flag = a.ovr[cell] != 0;
-    else if (p > L.band_hi) flag = true;
-    else if (p < L.band_lo) flag = false;
-    else flag = tvb_cell<N, EQ, 2>(a.u, g, i, j, mg);
-    if (a.flags) a.flags[cell] = flag ? 1 : 0;
-    if (a.margin) a.margin[cell] = mg;
-  }
-  append_troubled(a, flag, cell);
+  lm_load_weights<N>(L, lds);
+  const Geometry &g = a.geo;
+  const int wave = threadIdx.x >> 6;
+  const int x0 = (blockIdx.x * S::WAVES + wave) * kLmStrip;
+  if (x0 >= g.nx) return;  // no barrier follows
+  const int j0 = blockIdx.y * rows, j1 = min(j0 + rows, g.ny);
+  lm_strip<N>(a.u, g, x0, j0, j1, L, lds, lds + S::W1 + S::W2 + wave * S::FEAT,
+              [&](bool active, bool flag, double mg, float p, long cell) {
+                if (active) {
+                  if (L.prob) L.prob[cell] = p;
+                  if (a.ovr) flag = a.ovr[cell] != 0;
+                  if (a.flags) a.flags[cell] = flag ? 1 : 0;
+                  if (a.margin) a.margin[cell] = mg;
+                }
+                append_troubled(a, active && flag, cell);
+              });
 }

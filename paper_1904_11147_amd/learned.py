@@ -194,12 +194,17 @@ def generate_samples(seeds, n=64, order=2, t_end=0.25, every=10, device="cuda", 
     return torch.cat(xs), torch.cat(ys), torch.cat(ws)
 
 
-def train(net, x, y, w, epochs=3, batch=4096, lr=1e-3, seed=0, log=None):
-    """Mini-batch Adam over shuffled samples; returns the per-epoch mean loss."""
+def train(net, x, y, w, epochs=3, batch=4096, lr=1e-3, seed=0, log=None, lr_final=None):
+    """Mini-batch Adam over shuffled samples; the learning rate goes
+    geometrically from lr to lr_final (default: constant) over the epochs.
+    Returns the per-epoch mean loss."""
     gen = torch.Generator(device="cpu").manual_seed(seed)
     n = x.shape[0]
     hist = []
+    lr0 = lr
     for ep in range(epochs):
+        if lr_final is not None and epochs > 1:
+            lr = lr0 * (lr_final / lr0) ** (ep / (epochs - 1))
         perm = torch.randperm(n, generator=gen).to(x.device)
         tot, cnt = 0.0, 0
         for s in range(0, n, batch):

@@ -29,6 +29,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr-final", type=float, default=None, help="geometric decay to this rate by the last epoch")
     ap.add_argument("--out", default=None, help="default: indicator_q<order>.npz")
     ap.add_argument("--eval-seeds", default="1000:1004")
     ap.add_argument("--eval-n", type=int, default=128)
@@ -54,7 +55,7 @@ def main():
           f"runs stopped at a non-physical state: {learned.SKIPPED}", flush=True)
     net = learned.MLP(5 * (args.order + 1) ** 2 * 4, seed=0)
     t1 = time.time()
-    hist = learned.train(net, x, y, w, epochs=args.epochs, batch=args.batch, lr=args.lr,
+    hist = learned.train(net, x, y, w, epochs=args.epochs, batch=args.batch, lr=args.lr, lr_final=args.lr_final,
                          log=lambda s: print(s, flush=True))
     train_s = time.time() - t1
     p = net.forward(x)
