@@ -1,0 +1,104 @@
+"""Parity at the full workload sizes, in the launch configuration of the
+benchmark (dg_step replaying its captured step after dg_autotune):
+
+* 2D Euler four-state Riemann problem, 2048^2 cells, Q2 (seed 12345);
+* 1D Euler shock/entropy-wave interaction, 4000 cells, P3;
+* 2D Burgers, 1024^2 cells, Q2, periodic.
+
+The GPU takes one SSP-RK3 step (CFL time step) of the whole mesh; sampled
+windows are then recomputed by the oracle from the same initial data and the
+GPU's time step.  One step with limiting after each stage reads at most six
+cells in each direction (per stage: one for the residual, one for the
+limiter), so each window carries a six-cell halo (the true boundary condition
+where it meets the domain boundary, wrapped data on periodic domains) and
+only its interior is compared, at 1e-12 relative (the parity bar)."""
+import numpy as np
+import pytest
+import torch
+
+from tests.gpu_common import assert_close
+
+pytestmark = pytest.mark.gpu
+
+HALO = 6
+
+
+def _gpu_one_step(wl):
+    from paper_1904_11147_amd import dg
+    p = dg.problem_from_workload(wl)
+    u0 = dg.initial_state(p, wl, limit=True)
+    p.autotune(u0)
+    u1 = u0.clone()
+    t, n = p.step(u1, 0.0, wl.t_end, max_steps=1)
+    assert n == 1
+    p.close()
+    return u0, u1, t
+
+
+def _window_1d(O, wl, u0, u1, dt, a, b):
+    """Cells [a, b) of the 1D mesh."""
+    nx = wl.nx
+    lo, hi = max(a - HALO, 0), min(b + HALO, nx)
+    h = (wl.x1 - wl.x0) / nx
+    bc = (1, 1, 0, 0)  # transmissive sides: exact at a true boundary, contaminated halo elsewhere
+    op = O.Problem(dim=1, equation=wl.equation, order=wl.order, nx=hi - lo, ny=1, x0=wl.x0 + lo * h,
+                   x1=wl.x0 + hi * h, bc=bc, gamma=wl.gamma, cfl=wl.cfl)
+    U = np.ascontiguousarray(u0[..., lo:hi].cpu().numpy())
+    ref = op.step(U, dt)
+    i0, i1 = a - lo, b - lo
+    assert_close(u1[..., a:b].cpu().numpy(), ref[..., i0:i1], what=f"{wl.name} cells [{a},{b})")
+
+
+def _window_2d(O, wl, u0, u1, dt, ja, ia, w):
+    """Cells [ja, ja+w) x [ia, ia+w); periodic domains take wrapped halos."""
+    ny, nx = wl.ny, wl.nx
+    hx, hy = (wl.x1 - wl.x0) / nx, (wl.y1 - wl.y0) / ny
+    periodic = wl.bc[0] == 0
+    if periodic:
+        ix = np.arange(ia - HALO, ia + w + HALO) % nx
+        jy = np.arange(ja - HALO, ja + w + HALO) % ny
+        U = u0.cpu().numpy()[..., jy[:, None], ix[None, :]]
+        bc = (1, 1, 1, 1)
+        x0, y0 = wl.x0 + (ia - HALO) * hx, wl.y0 + (ja - HALO) * hy
+        nxw = nyw = w + 2 * HALO
+        oi, oj = HALO, HALO
+    else:
+        ilo, ihi = max(ia - HALO, 0), min(ia + w + HALO, nx)
+        jlo, jhi = max(ja - HALO, 0), min(ja + w + HALO, ny)
+        U = u0[..., jlo:jhi, ilo:ihi].cpu().numpy()
+        bc = (1, 1, 1, 1)
+        x0, y0 = wl.x0 + ilo * hx, wl.y0 + jlo * hy
+        nxw, nyw = ihi - ilo, jhi - jlo
+        oi, oj = ia - ilo, ja - jlo
+    op = O.Problem(dim=2, equation=wl.equation, order=wl.order, nx=nxw, ny=nyw, x0=x0, x1=x0 + nxw * hx, y0=y0,
+                   y1=y0 + nyw * hy, bc=bc, gamma=wl.gamma, cfl=wl.cfl)
+    ref = op.step(np.ascontiguousarray(U), dt)
+    got = u1[..., ja:ja + w, ia:ia + w].cpu().numpy()
+    assert_close(got, ref[..., oj:oj + w, oi:oi + w], what=f"{wl.name} window ({ja},{ia}) size {w}")
+
+
+def test_riemann2d_2048_q2_full_size(oracle):
+    from paper_1904_11147_amd import workloads as W
+    wl = W.riemann2d(n=2048, order=2, seed=12345)
+    u0, u1, dt = _gpu_one_step(wl)
+    rng = np.random.default_rng(7)
+    wins = [(1024 - 12, 1024 - 12), (0, 0), (2048 - 24, 2048 - 24), (0, 1500), (1017, 0)]
+    wins += [tuple(int(v) for v in rng.integers(0, 2048 - 24, size=2)) for _ in range(3)]
+    for ja, ia in wins:
+        _window_2d(oracle, wl, u0, u1, dt, ja, ia, 24)
+
+
+def test_shu_osher_k4000_p3_full_size(oracle):
+    from paper_1904_11147_amd import workloads as W
+    wl = W.shu_osher()
+    u0, u1, dt = _gpu_one_step(wl)
+    for a in (0, 90, 100, 1700, 3960):  # the shock sits near cell 100 (x = -4)
+        _window_1d(oracle, wl, u0, u1, dt, a, a + 40)
+
+
+def test_burgers2d_1024_q2_full_size(oracle):
+    from paper_1904_11147_amd import workloads as W
+    wl = W.burgers2d()
+    u0, u1, dt = _gpu_one_step(wl)
+    for ja, ia in ((0, 0), (1024 - 20, 1024 - 20), (500, 3), (7, 800), (333, 666)):
+        _window_2d(oracle, wl, u0, u1, dt, ja, ia, 20)
