@@ -1,8 +1,9 @@
 """Summaries of rocprofv3 output for the committed profiles.
 
     python -m paper_1904_11147_amd.profiling stats  <kernel_stats.csv> --cmd "<command>" --out <summary.txt>
-    python -m paper_1904_11147_amd.profiling traffic --fetch <csv> --write <csv> --kernel <substring>
-            --copy-kernel <substring> --copy-bytes <B> --cmd "<command>" --out <traffic.json>
+    python -m paper_1904_11147_amd.profiling traffic --fetch <csv> --write <csv> --kernel <regex>
+            --copy-kernel <regex> --copy-bytes <B> --cmd "<command>" --out <traffic.json>
+    python -m paper_1904_11147_amd.profiling counters <counter_collection.csv> --cmd "<command>" --out <summary.txt>
 
 `stats` shortens the kernel names of a `--kernel-trace --stats` CSV and keeps
 calls, total, average, min and max duration.  `traffic` turns two `--pmc`
@@ -100,6 +101,31 @@ def traffic(fetch, write, kernel, copy_kernel, copy_bytes, cmd, out):
     print(json.dumps(res, indent=1))
 
 
+def counters(path, cmd, out):
+    """Per-kernel averages per dispatch of SQ counters, and per-wavefront
+    figures (cycles, VALU / LDS / vector-memory instructions, the fraction of
+    a wavefront's cycles with a VALU instruction active or waiting)."""
+    acc, disp = {}, {}
+    for r in csv.DictReader(open(path)):
+        k = short_name(r["Kernel_Name"])
+        acc.setdefault(k, {}).setdefault(r["Counter_Name"], 0.0)
+        acc[k][r["Counter_Name"]] += float(r["Counter_Value"])
+        disp.setdefault(k, set()).add(r["Dispatch_Id"])
+    lines = ["# rocprofv3 SQ counters, averages per dispatch", f"# command: {cmd}", "#",
+             f"{'kernel':<40} {'disp':>5} {'waves':>8} {'cyc/wave':>9} {'valu/wave':>10} {'lds/wave':>9} "
+             f"{'vmem/wave':>10} {'valu_act':>9} {'wait':>6}"]
+    for k in sorted(acc):
+        n = len(disp[k])
+        d = {c: v / n for c, v in acc[k].items()}
+        waves = max(d.get("SQ_WAVES", 0.0), 1.0)
+        wc = max(d.get("SQ_WAVE_CYCLES", 0.0), 1.0)
+        lines.append(f"{k[:40]:<40} {n:>5} {waves:>8.0f} {wc / waves:>9.0f} {d.get('SQ_INSTS_VALU', 0) / waves:>10.0f} "
+                     f"{d.get('SQ_INSTS_LDS', 0) / waves:>9.0f} {d.get('SQ_INSTS_VMEM_RD', 0) / waves:>10.0f} "
+                     f"{d.get('SQ_ACTIVE_INST_VALU', 0) / wc:>9.3f} {d.get('SQ_WAIT_INST_ANY', 0) / wc:>6.3f}")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -115,9 +141,15 @@ def main():
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--cmd", required=True)
     t.add_argument("--out", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("csv")
+    c.add_argument("--cmd", required=True)
+    c.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.what == "stats":
         stats(a.csv, a.cmd, a.out)
+    elif a.what == "counters":
+        counters(a.csv, a.cmd, a.out)
     else:
         traffic(a.fetch, a.write, a.kernel, a.copy_kernel, a.copy_bytes, a.cmd, a.out)
 
