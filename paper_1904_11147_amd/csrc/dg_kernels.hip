@@ -22,6 +22,8 @@
 //   k_speed, k_dt_finalize, k_reset, k_project: time step and set-up.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 #include <type_traits>
 
@@ -1155,16 +1157,15 @@ __global__ __launch_bounds__(kBlock) void k_speed(const double *__restrict__ u, 
   using P = Phys<EQ, DIM>;
   const OrderTables &T = c_tab[N];
   const long plane = (long)g.nx * g.ny;
-  const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const double k0 = DIM == 1 ? T.b0[0] : T.b0[0] * T.b0[0];
   double sx = 0.0, sy = 0.0;
   bool bad = false;
-  if (cell < plane) {
-    const double k0 = DIM == 1 ? T.b0[0] : T.b0[0] * T.b0[0];
+  for (long cell = (long)blockIdx.x * blockDim.x + threadIdx.x; cell < plane; cell += (long)gridDim.x * blockDim.x) {
     double m[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) m[v] = u[(long)(v * NM) * plane + cell] * k0;
-    sx = P::template speed<0>(m, g.gamma, bad);
-    if (DIM == 2) sy = P::template speed<1>(m, g.gamma, bad);
+    sx = fmax(sx, P::template speed<0>(m, g.gamma, bad));
+    if (DIM == 2) sy = fmax(sy, P::template speed<1>(m, g.gamma, bad));
   }
   if (bad) atomicOr(&sc->status, 1);
 #pragma unroll
@@ -1172,7 +1173,20 @@ __global__ __launch_bounds__(kBlock) void k_speed(const double *__restrict__ u, 
     sx = fmax(sx, __shfl_xor(sx, o));
     sy = fmax(sy, __shfl_xor(sy, o));
   }
+  // one atomic per block (a maximum: the order does not matter)
+  __shared__ double red[2][kBlock / 64];
+  const int wave = threadIdx.x >> 6;
   if (__lane_id() == 0) {
+    red[0][wave] = sx;
+    red[1][wave] = sy;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; ++w) {
+      sx = fmax(sx, red[0][w]);
+      sy = fmax(sy, red[1][w]);
+    }
     atomicMax(&sc->smax[0], (unsigned long long)__double_as_longlong(sx));
     if (DIM == 2) atomicMax(&sc->smax[1], (unsigned long long)__double_as_longlong(sy));
   }
@@ -1718,7 +1732,7 @@ int launch_limit(const LaunchCtx &c, double *u, double *side, int count_slot, ui
 int launch_speed(const LaunchCtx &c, const double *u) {
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, S(c), c.sc, 1);
   const long cells = (long)c.geo.nx * c.geo.ny;
-  dim3 grid((unsigned)((cells + kBlock - 1) / kBlock));
+  dim3 grid((unsigned)std::min<long>((cells + kBlock - 1) / kBlock, 2048));
   return dispatch(c, [&](auto D, auto E, auto NN) {
     hipLaunchKernelGGL((k_speed<decltype(NN)::value, decltype(E)::value, decltype(D)::value>), grid, dim3(kBlock),
                        0, S(c), u, c.sc, c.geo);

@@ -23,6 +23,8 @@ __device__ inline uint16_t f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// the same rounding (to nearest even) by the hardware conversion, for the limiter's inference
+__device__ inline uint16_t f2bf_hw(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 __device__ inline f32x4_t mfma16(bf16x4_t a, bf16x4_t b, f32x4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
@@ -448,8 +450,10 @@ struct LmShape {
   static constexpr int NP = N + 1, NM = NP * NP, FV = 5 * NM, BV = (FV + 3) / 4 * 4, KB = BV / 4;
   static constexpr int KP = 4 * BV;  // padded input width (= (F + 15) / 16 * 16 for F = 4 FV)
   static constexpr int W1 = kHidden * KP, W2 = kHidden * kHidden, FEAT = KB * 256;
+  static constexpr int PAR = 2 * (3 * kHidden + 2);  // b1 | b2 | w3 | b3 as floats (in bf16 slots)
   static constexpr int WAVES = lm_waves(N);
-  static constexpr int LDS = W1 + W2 + WAVES * FEAT;
+  static constexpr int LDS = W1 + W2 + PAR + WAVES * FEAT;
+  static constexpr int FEAT0 = W1 + W2 + PAR;  // first per-wave feature slot
 };
 
 // Copies the weights into LDS in fragment order (whole block), then a barrier.
@@ -466,6 +470,13 @@ __device__ inline void lm_load_weights(const LearnedArgs &L, uint16_t *wl) {
     const int e = k & 3, ln = (k >> 2) & 63, kb = (k >> 8) & 3, nb = k >> 10;
     wl[S::W1 + k] = W2[(16 * nb + (ln & 15)) * kHidden + 16 * kb + 4 * (ln >> 4) + e];
   }
+  float *par = reinterpret_cast<float *>(wl + S::W1 + S::W2);
+  for (int k = tid; k < kHidden; k += nt) {
+    par[k] = L.M[L.lay.mb1() + k];
+    par[kHidden + k] = L.M[L.lay.mb2() + k];
+    par[2 * kHidden + k] = bf2f(L.W[L.lay.w3() + k]);
+  }
+  if (tid == 0) par[3 * kHidden] = L.M[L.lay.mb3()];
   __syncthreads();
 }
 
@@ -485,9 +496,7 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
   const bool owner = r >= 1 && r <= kLmStrip && col < g.nx;
   const long plane = (long)g.nx * g.ny;
   const double *__restrict__ up = u + (long)gv * NM * plane;
-  const float *__restrict__ M = L.M;
-  const uint16_t *__restrict__ W = L.W;
-  const MlpLayout &lay = L.lay;
+  const float *par = reinterpret_cast<const float *>(wl + S::W1 + S::W2);  // b1 | b2 | w3 | b3
   auto loadrow = [&](int jj, double (&R)[NM]) {
     if (jj > g.ny) jj = g.ny;
     const CellIdx ci = map_cell(g, col, jj);
@@ -509,12 +518,25 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
   for (int j = j0; j < j1; ++j) {
     double Pv[NM];
     loadrow(j + 2, Pv);  // in flight while this row is evaluated
-    double Wv[NM], Ev[NM];
+    // west and east neighbours from the adjacent slots: kept for Q1, Q2;
+    // Q3 fetches them when each feature is formed (registers)
+    constexpr bool keep_we = N <= 2;
+    double Wv[keep_we ? NM : 1], Ev[keep_we ? NM : 1];
+    if constexpr (keep_we) {
 #pragma unroll
-    for (int q = 0; q < NM; ++q) {
-      Wv[q] = __shfl_up(Cv[q], 1, 16);
-      Ev[q] = __shfl_down(Cv[q], 1, 16);
+      for (int q = 0; q < NM; ++q) {
+        Wv[q] = __shfl_up(Cv[q], 1, 16);
+        Ev[q] = __shfl_down(Cv[q], 1, 16);
+      }
     }
+    auto west = [&](int q) -> double {
+      if constexpr (keep_we) return Wv[q];
+      else return __shfl_up(Cv[q], 1, 16);
+    };
+    auto east = [&](int q) -> double {
+      if constexpr (keep_we) return Ev[q];
+      else return __shfl_down(Cv[q], 1, 16);
+    };
     // TVB decision of this variable (the expressions of tvb_cell), combined over the cell's lanes
     bool tflag = false;
     double tmg = INFINITY;
@@ -523,7 +545,7 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
 #pragma unroll
       for (int dir = 0; dir < 2; ++dir) {
         const double Mh2 = dir == 0 ? g.tvb_Mx : g.tvb_My;
-        const double mp = (dir == 0 ? Ev[0] : Nv[0]) * k0, mm = (dir == 0 ? Wv[0] : Sv[0]) * k0;
+        const double mp = (dir == 0 ? east(0) : Nv[0]) * k0, mm = (dir == 0 ? west(0) : Sv[0]) * k0;
         double upv = 0.0, umv = 0.0;
 #pragma unroll
         for (int q = 0; q < NM; ++q) {
@@ -550,14 +572,14 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
       double mx = g.tvb_Mx;
       auto val = [&](int f) -> double {
         const int c = f / NM, q = f % NM;
-        const double v = c == 0 ? Cv[q] : (c == 1 ? Wv[q] : (c == 2 ? Ev[q] : (c == 3 ? Sv[q] : Nv[q])));
+        const double v = c == 0 ? Cv[q] : (c == 1 ? west(q) : (c == 2 ? east(q) : (c == 3 ? Sv[q] : Nv[q])));
         return q == 0 ? v - c0 : v;
       };
 #pragma unroll
       for (int f = 0; f < FV; ++f) mx = fmax(mx, fabs(val(f)));
       const double inv = 1.0 / mx;
 #pragma unroll
-      for (int f = 0; f < FV; ++f) fl[(f / 4) * 256 + f % 4] = f2bf((float)(val(f) * inv));
+      for (int f = 0; f < FV; ++f) fl[(f / 4) * 256 + f % 4] = f2bf_hw((float)(val(f) * inv));
     }
     // layer 1: H1^T = W1 X^T
     f32x4_t h[4];
@@ -573,7 +595,7 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) h1[nb][e] = (short)f2bf(fmaxf(h[nb][e] + M[lay.mb1() + 16 * nb + 4 * gv + e], 0.f));
+      for (int e = 0; e < 4; ++e) h1[nb][e] = (short)f2bf_hw(fmaxf(h[nb][e] + par[16 * nb + 4 * gv + e], 0.f));
     // layer 2: H2^T = W2 H1^T
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) h[nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
@@ -589,11 +611,11 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int k = 16 * nb + 4 * gv + e;
-        part += bf2f(f2bf(fmaxf(h[nb][e] + M[lay.mb2() + k], 0.f))) * bf2f(W[lay.w3() + k]);
+        part += bf2f(f2bf_hw(fmaxf(h[nb][e] + par[kHidden + k], 0.f))) * par[2 * kHidden + k];
       }
     part += __shfl_xor(part, 16);
     part += __shfl_xor(part, 32);
-    const float p = 1.f / (1.f + __expf(-(part + M[lay.mb3()])));
+    const float p = 1.f / (1.f + __expf(-(part + par[3 * kHidden])));
     bool flag = false;
     double mg = INFINITY;
     if (p > L.band_hi) flag = true;
@@ -624,7 +646,7 @@ __global__ __launch_bounds__(64 * lm_waves(N), 2) void k_indicator_learned(Limit
   const int x0 = (blockIdx.x * S::WAVES + wave) * kLmStrip;
   if (x0 >= g.nx) return;  // no barrier follows
   const int j0 = blockIdx.y * rows, j1 = min(j0 + rows, g.ny);
-  lm_strip<N>(a.u, g, x0, j0, j1, L, lds, lds + S::W1 + S::W2 + wave * S::FEAT,
+  lm_strip<N>(a.u, g, x0, j0, j1, L, lds, lds + S::FEAT0 + wave * S::FEAT,
               [&](bool active, bool flag, double mg, float p, long cell) {
                 if (active) {
                   if (L.prob) L.prob[cell] = p;
