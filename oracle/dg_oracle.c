@@ -41,7 +41,7 @@
 enum { ORC_BURGERS = 0, ORC_EULER = 1 };
 enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1 };
 enum { ORC_LIM_NONE = 0, ORC_LIM_CSWENO = 1 };
-enum { ORC_IND_TVB = 0, ORC_IND_ALL = 1 };
+enum { ORC_IND_TVB = 0, ORC_IND_ALL = 1, ORC_IND_KXRCF = 3 };
 enum { ORC_NEGW_SPLIT = 0, ORC_NEGW_RAW = 1 };
 enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_NONPHYSICAL = -5, ORC_ERR_TABLE = -6 };
 
@@ -428,6 +428,7 @@ typedef struct {
   const orc_tables *T;
   int N, np, nm, nv, nx, ny;
   double hx, hy;
+  double kx_scale; /* KXRCF: 1 / h^((N+1)/2), h the radius of the cell's circumscribed circle */
 } orc_ctx;
 
 static int make_ctx(const orc_config *c, orc_ctx *x) {
@@ -446,6 +447,10 @@ static int make_ctx(const orc_config *c, orc_ctx *x) {
   x->ny = c->ny;
   x->hx = (c->x1 - c->x0) / c->nx;
   x->hy = c->dim == 2 ? (c->y1 - c->y0) / c->ny : 1.0;
+  {
+    double rad = c->dim == 1 ? 0.5 * x->hx : 0.5 * sqrt(x->hx * x->hx + x->hy * x->hy);
+    x->kx_scale = 1.0 / pow(rad, 0.5 * (c->order + 1));
+  }
   return ORC_OK;
 }
 
@@ -725,6 +730,103 @@ static int indicator_cell(const orc_ctx *x, const double *U, int i, int j, doubl
   return flag;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Troubled-cell indicator of Krivodonova, Xin, Remacle, Chevaugeon and      */
+/* Flaherty (the paper's own, Sec. 3 step 1, by citation): per indicator     */
+/* variable, the integral over the cell's inflow boundary of the jump        */
+/* between the cell's trace and the neighbour's, divided by h^((N+1)/2), the */
+/* inflow boundary's measure and the maximum of |u| over the cell's          */
+/* quadrature points; troubled when it exceeds 1.  Inflow faces are those    */
+/* where the cell-average characteristic velocity points into the cell      */
+/* (Burgers: the mean itself; Euler: mean momentum / mean density); the      */
+/* variables are u (Burgers) or density and total energy (Euler).  The       */
+/* margin is min(|I - 1|, |v_x|, |v_y|).                                      */
+/* ------------------------------------------------------------------------ */
+static int kxrcf_cell(const orc_ctx *x, const double *U, int i, int j, double *margin) {
+  const orc_tables *T = x->T;
+  const int dim = x->c->dim, np = x->np;
+  double C[ORC_MAXV][ORC_MAXM], Nb[ORC_MAXV][ORC_MAXM];
+  fetch_cell(x, U, i, j, C);
+  double k0 = cell_mean_factor(x);
+  double vel[2] = {0.0, 0.0};
+  if (x->c->equation == ORC_BURGERS) {
+    vel[0] = vel[1] = C[0][0] * k0;
+  } else {
+    double rho = C[0][0] * k0;
+    vel[0] = C[1][0] * k0 / rho;
+    if (dim == 2) vel[1] = C[2][0] * k0 / rho;
+  }
+  int vars[2], nvar;
+  if (x->c->equation == ORC_BURGERS) {
+    vars[0] = 0;
+    nvar = 1;
+  } else {
+    vars[0] = 0;
+    vars[1] = dim + 1;
+    nvar = 2;
+  }
+  double mg = fabs(vel[0]);
+  if (dim == 2) mg = fmin(mg, fabs(vel[1]));
+  int flag = 0;
+  for (int k = 0; k < nvar; ++k) {
+    const int v = vars[k];
+    double J = 0.0, len = 0.0;
+    for (int dir = 0; dir < dim; ++dir) {
+      if (vel[dir] == 0.0) continue;
+      const int minus = vel[dir] > 0.0; /* inflow through the west / south face */
+      const int di = dir == 0 ? (minus ? -1 : 1) : 0, dj = dir == 1 ? (minus ? -1 : 1) : 0;
+      fetch_cell(x, U, i + di, j + dj, Nb);
+      const double *own = minus ? T->bm : T->bp, *nbr = minus ? T->bp : T->bm;
+      if (dim == 1) {
+        double a[ORC_MAXV], b[ORC_MAXV];
+        point_value(x, C, own, NULL, a);
+        point_value(x, Nb, nbr, NULL, b);
+        J += a[v] - b[v];
+        len += 1.0;
+      } else {
+        const double flen = dir == 0 ? x->hy : x->hx;
+        double integral = 0.0;
+        for (int e = 0; e < np; ++e) {
+          double bs[ORC_MAXP], a[ORC_MAXV], b[ORC_MAXV];
+          for (int n = 0; n < np; ++n) bs[n] = T->bq[n][e];
+          if (dir == 0) {
+            point_value(x, C, own, bs, a);
+            point_value(x, Nb, nbr, bs, b);
+          } else {
+            point_value(x, C, bs, own, a);
+            point_value(x, Nb, bs, nbr, b);
+          }
+          integral += T->wq[e] * (a[v] - b[v]);
+        }
+        J += 0.5 * flen * integral;
+        len += flen;
+      }
+    }
+    /* maximum of |u| over the volume quadrature points */
+    double norm = 0.0;
+    for (int qy = 0; qy < (dim == 2 ? np : 1); ++qy)
+      for (int qx = 0; qx < np; ++qx) {
+        double bx[ORC_MAXP], by[ORC_MAXP], a[ORC_MAXV];
+        for (int n = 0; n < np; ++n) {
+          bx[n] = T->bq[n][qx];
+          by[n] = T->bq[n][qy];
+        }
+        point_value(x, C, bx, by, a);
+        norm = fmax(norm, fabs(a[v]));
+      }
+    const double I = (len > 0.0 && norm > 0.0) ? fabs(J) * x->kx_scale / (len * norm) : 0.0;
+    flag |= I > 1.0;
+    mg = fmin(mg, fabs(I - 1.0));
+  }
+  *margin = mg;
+  return flag;
+}
+
+static int any_indicator(const orc_ctx *x, const double *U, int i, int j, double *margin) {
+  if (x->c->indicator == ORC_IND_KXRCF) return kxrcf_cell(x, U, i, j, margin);
+  return indicator_cell(x, U, i, j, margin);
+}
+
 int orc_indicator(const orc_config *c, const double *U, uint8_t *flags, double *margin) {
   orc_ctx x;
   int rc = make_ctx(c, &x);
@@ -733,7 +835,7 @@ int orc_indicator(const orc_config *c, const double *U, uint8_t *flags, double *
   for (int j = 0; j < x.ny; ++j)
     for (int i = 0; i < x.nx; ++i) {
       double m;
-      int f = indicator_cell(&x, U, i, j, &m);
+      int f = any_indicator(&x, U, i, j, &m);
       size_t k = (size_t)j * x.nx + i;
       if (flags) flags[k] = (uint8_t)f;
       if (margin) margin[k] = m;
@@ -833,7 +935,7 @@ static int limit_state(const orc_ctx *x, double *U, double *work, uint8_t *flags
       int f;
       if (flags_in) f = flags_in[k] != 0;
       else if (x->c->indicator == ORC_IND_ALL) f = 1;
-      else f = indicator_cell(x, work, i, j, &m);
+      else f = any_indicator(x, work, i, j, &m);
       if (flags_out) flags_out[k] = (uint8_t)f;
       if (margin_out) margin_out[k] = m;
       if (f && x->c->limiter == ORC_LIM_CSWENO) limit_cell(x, work, i, j, U);

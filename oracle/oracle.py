@@ -25,7 +25,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 BURGERS, EULER = 0, 1
 PERIODIC, TRANSMISSIVE = 0, 1
 LIM_NONE, LIM_CSWENO = 0, 1
-IND_TVB, IND_ALL = 0, 1
+IND_TVB, IND_ALL, IND_KXRCF = 0, 1, 3
 NEGW_SPLIT, NEGW_RAW = 0, 1
 ERR_NONPHYSICAL = -5
 
