@@ -78,14 +78,14 @@ def learned_nets(device):
     return nets
 
 
-def learned_leg(wl, state0, t0, steps, warmup, nets):
-    """The same problem and state with the learned indicator (Q2 network)."""
+def indicator_leg(wl, state0, t0, steps, warmup, indicator, net=None):
+    """The same problem and state with another troubled-cell indicator (the
+    learned one with its network, or KXRCF)."""
     import torch
     from paper_1904_11147_amd import dg, learned
-    if 2 not in nets:
-        return None
-    prob = dg.problem_from_workload(wl, device="cuda:0", indicator=dg.IND_LEARNED)
-    learned.attach(prob, nets[2])
+    prob = dg.problem_from_workload(wl, device="cuda:0", indicator=indicator)
+    if net is not None:
+        learned.attach(prob, net)
     state = state0.clone()
     t, _ = prob.step(state, t0, wl.t_end, max_steps=warmup)
     prob.profile_read(reset=True)
@@ -282,7 +282,9 @@ def main():
         },
     }
     nets = learned_nets("cuda:0")
-    out["learned"] = learned_leg(wl, state_warm, t_warm, args.steps, 2, nets)
+    out["learned"] = (indicator_leg(wl, state_warm, t_warm, args.steps, 2, dg.IND_LEARNED, nets[2])
+                      if 2 in nets else None)
+    out["kxrcf"] = indicator_leg(wl, state_warm, t_warm, args.steps, 2, dg.IND_KXRCF)
     del state_warm
     prob.close()
     del state

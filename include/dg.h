@@ -58,7 +58,7 @@ enum {
 enum { DG_EQ_BURGERS = 0, DG_EQ_EULER = 1 };
 enum { DG_BC_PERIODIC = 0, DG_BC_TRANSMISSIVE = 1 };
 enum { DG_LIM_NONE = 0, DG_LIM_CSWENO = 1 };
-enum { DG_IND_TVB = 0, DG_IND_ALL = 1, DG_IND_LEARNED = 2 };
+enum { DG_IND_TVB = 0, DG_IND_ALL = 1, DG_IND_LEARNED = 2, DG_IND_KXRCF = 3 };
 enum { DG_NEGW_SPLIT = 0, DG_NEGW_RAW = 1 };
 
 typedef struct dg_config {
@@ -71,9 +71,14 @@ typedef struct dg_config {
                           (transmissive = even reflection of the adjacent cell;
                           periodic sides must come in pairs) */
   int32_t limiter;     /* DG_LIM_NONE or DG_LIM_CSWENO */
-  int32_t indicator;   /* DG_IND_TVB (TVB-modified minmod), DG_IND_ALL (every cell), or
-                          DG_IND_LEARNED (2D only: the MLP of dg_set_learned with the TVB
-                          decision in its uncertain band) */
+  int32_t indicator;   /* DG_IND_TVB (TVB-modified minmod), DG_IND_ALL (every cell),
+                          DG_IND_LEARNED (2D Euler only: the MLP of dg_set_learned with the
+                          TVB decision in its uncertain band), or DG_IND_KXRCF (the
+                          inflow-jump indicator of Krivodonova et al. that Sec. 3, step 1
+                          cites: |integral of the trace jump over the inflow boundary| /
+                          (h^((N+1)/2) |inflow boundary| max_q |u|) > 1, h the cell's
+                          circumscribed radius, inflow from the cell-average velocity,
+                          variables u or density and energy; margin min(|I-1|, |v_x|, |v_y|)) */
   int32_t negw_mode;   /* P3 points with a negative linear weight: DG_NEGW_SPLIT
                           (positive/negative split, theta = 3) or DG_NEGW_RAW */
   int32_t reserved;    /* must be 0 */

@@ -58,7 +58,8 @@ int validate_config(const dg_config *c) {
   if ((c->bc[0] == DG_BC_PERIODIC) != (c->bc[1] == DG_BC_PERIODIC)) return DG_ERR_INVALID_ARG;
   if (c->dim == 2 && (c->bc[2] == DG_BC_PERIODIC) != (c->bc[3] == DG_BC_PERIODIC)) return DG_ERR_INVALID_ARG;
   if (c->limiter != DG_LIM_NONE && c->limiter != DG_LIM_CSWENO) return DG_ERR_INVALID_ARG;
-  if (c->indicator != DG_IND_TVB && c->indicator != DG_IND_ALL && c->indicator != DG_IND_LEARNED)
+  if (c->indicator != DG_IND_TVB && c->indicator != DG_IND_ALL && c->indicator != DG_IND_LEARNED &&
+      c->indicator != DG_IND_KXRCF)
     return DG_ERR_UNSUPPORTED;
   if (c->indicator == DG_IND_LEARNED && (c->dim != 2 || c->equation != DG_EQ_EULER)) return DG_ERR_UNSUPPORTED;
   if (c->negw_mode != DG_NEGW_SPLIT && c->negw_mode != DG_NEGW_RAW) return DG_ERR_INVALID_ARG;
@@ -106,6 +107,8 @@ void fill_geometry(const dg_config *cfg, Geometry *g) {
   g->eps = cfg->weno_eps;
   g->negw_raw = cfg->negw_mode == DG_NEGW_RAW ? 1 : 0;
   g->pad = 0;
+  const double rad = cfg->dim == 1 ? 0.5 * g->hx : 0.5 * std::sqrt(g->hx * g->hx + g->hy * g->hy);
+  g->kx_scale = 1.0 / std::pow(rad, 0.5 * (cfg->order + 1));
 }
 
 }  // namespace dg

@@ -195,7 +195,7 @@ __device__ inline void append_batch(BatchQueue *q, int slot, long long *list, De
 }
 
 // Troubled-cell indicator over the queued row segments (one wavefront per
-// segment).  IND: DG_IND_TVB or DG_IND_ALL.
+// segment).  IND: DG_IND_TVB, DG_IND_ALL or DG_IND_KXRCF.
 template <int N, int SLOT, int IND>
 __global__ __launch_bounds__(64) void k_batch_indicator(const BatchInst *__restrict__ inst, BatchQueue *q,
                                                         long long *__restrict__ list) {
@@ -207,7 +207,10 @@ __global__ __launch_bounds__(64) void k_batch_indicator(const BatchInst *__restr
     const int i = s.i0 + threadIdx.x;
     bool flag = false;
     double mg = INFINITY;
-    if (i < g.nx) flag = IND == DG_IND_ALL ? true : tvb_cell<N, 1, 2>(limit_target<SLOT>(I), g, i, s.j, mg);
+    if (i < g.nx)
+      flag = IND == DG_IND_ALL     ? true
+             : IND == DG_IND_KXRCF ? kxrcf_cell<N, 1, 2>(limit_target<SLOT>(I), g, i, s.j, mg)
+                                   : tvb_cell<N, 1, 2>(limit_target<SLOT>(I), g, i, s.j, mg);
     const long long cell = (long long)s.j * g.nx + i;
     append_batch(q, SLOT, list, I.sc, flag, ((long long)s.id << 32) | cell);
   }

@@ -66,6 +66,7 @@ struct Geometry {
   double eps;
   int32_t negw_raw;
   int32_t pad;
+  double kx_scale;  // KXRCF: 1 / h^((N+1)/2), h the cell's circumscribed radius
 };
 
 struct Kernels;  // launch helpers live in the kernel TU

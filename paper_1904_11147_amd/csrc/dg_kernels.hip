@@ -1322,6 +1322,104 @@ __device__ inline bool tvb_cell(const double *__restrict__ u, const Geometry &g,
   return flag;
 }
 
+// KXRCF decision of cell (i, j) (Krivodonova et al., cited by Sec. 3 step 1):
+// for each indicator variable (u; Euler: density and energy) the integral of
+// the trace jump over the inflow faces (cell-average velocity pointing in),
+// divided by h^((N+1)/2) (g.kx_scale), the inflow boundary's measure and the
+// maximum of |u| over the volume quadrature points; troubled above 1.  mg
+// receives min(|I - 1|, |v_x|, |v_y|).
+template <int N, int EQ, int DIM>
+__device__ inline bool kxrcf_cell(const double *__restrict__ u, const Geometry &g, int i, int j, double &mg) {
+  constexpr int NP = N + 1, NM = DIM == 1 ? NP : NP * NP, NV = Phys<EQ, DIM>::NV;
+  constexpr int NVAR = EQ == 0 ? 1 : 2;
+  const OrderTables &T = c_tab[N];
+  const long plane = (long)g.nx * g.ny;
+  const double k0 = DIM == 1 ? T.b0[0] : T.b0[0] * T.b0[0];
+  double C[NV][NM];
+  load_cell<NP, NM, NV, DIM>(u, plane, map_cell(g, i, j), C);
+  double vel[2] = {0.0, 0.0};
+  if (EQ == 0) {
+    vel[0] = vel[1] = C[0][0] * k0;
+  } else {
+    const double rho = C[0][0] * k0;
+    vel[0] = C[1][0] * k0 / rho;
+    if (DIM == 2) vel[1] = C[2][0] * k0 / rho;
+  }
+  mg = fabs(vel[0]);
+  if (DIM == 2) mg = fmin(mg, fabs(vel[1]));
+  double J[NVAR], len = 0.0;
+#pragma unroll
+  for (int k = 0; k < NVAR; ++k) J[k] = 0.0;
+#pragma unroll
+  for (int dir = 0; dir < DIM; ++dir) {
+    if (vel[dir] == 0.0) continue;
+    const bool minus = vel[dir] > 0.0;  // inflow through the west / south face
+    const int d = minus ? -1 : 1;
+    const CellIdx cn = map_cell(g, i + (dir == 0 ? d : 0), j + (dir == 1 ? d : 0));
+    const double *own = minus ? T.bm : T.bp, *nbr = minus ? T.bp : T.bm;
+    const double flen = DIM == 1 ? 1.0 : (dir == 0 ? g.hy : g.hx);
+#pragma unroll
+    for (int k = 0; k < NVAR; ++k) {
+      const int v = k == 0 ? 0 : DIM + 1;
+      double Nb[NM];
+#pragma unroll
+      for (int q = 0; q < NM; ++q) {
+        const int m = q % NP, n = q / NP;
+        const double s = u[(long)(v * NM + q) * plane + cn.idx];
+        Nb[q] = ((cn.fx && (m & 1)) != (DIM == 2 && cn.fy && (n & 1))) ? -s : s;
+      }
+      if (DIM == 1) {
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+          a += C[v][m] * own[m];
+          b += Nb[m] * nbr[m];
+        }
+        J[k] += a - b;
+      } else {
+        double integral = 0.0;
+#pragma unroll
+        for (int e = 0; e < NP; ++e) {
+          double a = 0.0, b = 0.0;
+#pragma unroll
+          for (int q = 0; q < NM; ++q) {
+            const int m = q % NP, n = q / NP;
+            const double bb = dir == 0 ? own[m] * T.bq[n][e] : T.bq[m][e] * own[n];
+            const double bn = dir == 0 ? nbr[m] * T.bq[n][e] : T.bq[m][e] * nbr[n];
+            a += C[v][q] * bb;
+            b += Nb[q] * bn;
+          }
+          integral += T.wq[e] * (a - b);
+        }
+        J[k] += 0.5 * flen * integral;
+      }
+    }
+    len += flen;
+  }
+  bool flag = false;
+#pragma unroll
+  for (int k = 0; k < NVAR; ++k) {
+    const int v = k == 0 ? 0 : DIM + 1;
+    double norm = 0.0;
+#pragma unroll
+    for (int qy = 0; qy < (DIM == 2 ? NP : 1); ++qy)
+#pragma unroll
+      for (int qx = 0; qx < NP; ++qx) {
+        double a = 0.0;
+#pragma unroll
+        for (int q = 0; q < NM; ++q) {
+          const int m = q % NP, n = q / NP;
+          a += C[v][q] * (DIM == 2 ? T.bq[m][qx] * T.bq[n][qy] : T.bq[m][qx]);
+        }
+        norm = fmax(norm, fabs(a));
+      }
+    const double I = (len > 0.0 && norm > 0.0) ? fabs(J[k]) * g.kx_scale / (len * norm) : 0.0;
+    flag |= I > 1.0;
+    mg = fmin(mg, fabs(I - 1.0));
+  }
+  return flag;
+}
+
 // Appends the flagged cells of a wavefront to the troubled list (one atomic
 // per wavefront).
 __device__ inline void append_troubled(const LimitArgs &a, bool flag, long cell) {
@@ -1354,6 +1452,8 @@ __global__ __launch_bounds__(kBlock) void k_indicator(LimitArgs a) {
       flag = a.ovr[cell] != 0;
     } else if (a.mode == DG_IND_ALL) {
       flag = true;
+    } else if (a.mode == DG_IND_KXRCF) {
+      flag = kxrcf_cell<N, EQ, DIM>(a.u, g, i, j, mg);
     } else {
       flag = tvb_cell<N, EQ, DIM>(a.u, g, i, j, mg);
     }
@@ -1888,6 +1988,9 @@ int batch_launch_limit(const BatchCtx &b, int order, int slot) {
       else if (b.indicator == DG_IND_ALL)
         hipLaunchKernelGGL((k_batch_indicator<n, s, DG_IND_ALL>), dim3(4 * b.grid_cap), dim3(64), 0, st, b.inst, q,
                            list);
+      else if (b.indicator == DG_IND_KXRCF)
+        hipLaunchKernelGGL((k_batch_indicator<n, s, DG_IND_KXRCF>), dim3(4 * b.grid_cap), dim3(64), 0, st, b.inst,
+                           q, list);
       else
         hipLaunchKernelGGL((k_batch_indicator<n, s, DG_IND_TVB>), dim3(4 * b.grid_cap), dim3(64), 0, st, b.inst, q,
                            list);

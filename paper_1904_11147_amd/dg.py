@@ -22,7 +22,7 @@ DG_OK, DG_ERR_INVALID_ARG, DG_ERR_UNSUPPORTED, DG_ERR_WORKSPACE, DG_ERR_HIP, DG_
 BURGERS, EULER = 0, 1
 PERIODIC, TRANSMISSIVE = 0, 1
 LIM_NONE, LIM_CSWENO = 0, 1
-IND_TVB, IND_ALL, IND_LEARNED = 0, 1, 2
+IND_TVB, IND_ALL, IND_LEARNED, IND_KXRCF = 0, 1, 2, 3
 NEGW_SPLIT, NEGW_RAW = 0, 1
 
 # every symbol include/dg.h declares

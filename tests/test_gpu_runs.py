@@ -23,7 +23,9 @@ def _l1_diff(A, B, dim, order):
     return (W[None, :, :, None, None] * e).sum(axis=(1, 2, 3, 4)) * 0.25 / (A.shape[-1] * A.shape[-2])
 
 
-def _run_both(oracle, wl, **over):
+def _run_both(oracle, wl, step_slack=0, **over):
+    """step_slack: the step counts may differ by this much (both runs still
+    end exactly at t_end, the last step clipped)."""
     from paper_1904_11147_amd import dg
     op = oracle_problem(oracle, wl, **over)
     op, U0 = oracle_initial_state(oracle, wl, op, limit=True)
@@ -35,7 +37,7 @@ def _run_both(oracle, wl, **over):
     Ud = torch.from_numpy(U0).cuda()
     t, n = gp.step(Ud, 0.0, wl.t_end)
     got = Ud.cpu().numpy()
-    assert n == n_ref and t == t_ref == wl.t_end, (n, n_ref, t, t_ref)
+    assert abs(n - n_ref) <= step_slack and t == t_ref == wl.t_end, (n, n_ref, t, t_ref)
     l1 = _l1_diff(got, ref, wl.dim, wl.order)
     print(wl.name, "steps", n, "L1 diff per var", l1)
     assert (l1 <= L1_TOL).all(), l1

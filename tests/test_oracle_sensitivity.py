@@ -24,3 +24,22 @@ def _growth(oracle, order, steps, n=16):
 def test_q2_is_insensitive_q3_amplifies(oracle):
     assert _growth(oracle, 2, 30) < 1e-11
     assert _growth(oracle, 3, 30) > 1e-9
+
+
+def test_kxrcf_on_a_flow_from_rest_is_sensitive_tvb_is_not(oracle):
+    """Sod's problem starts at rest.  KXRCF takes its inflow faces from the
+    sign of the mean velocity, which next to the waves is rounding-sized for
+    some cells, so a 1e-15 perturbation of the initial state changes flags
+    and the solution at t = 0.1 by ~1e-5; under TVB the same perturbation
+    stays at ~1e-14.  Final-time GPU/oracle comparisons with KXRCF therefore
+    use flows without resting regions."""
+    wl = W.sod(nx=100, order=2).with_(t_end=0.1)
+    out = {}
+    for mode in (0, 3):
+        op = oracle_problem(oracle, wl, indicator_mode=mode)
+        op, U0 = oracle_initial_state(oracle, wl, op, limit=True)
+        A = op.run(U0, 0.0, wl.t_end)[0]
+        U1 = U0 * (1.0 + 1e-15 * np.random.default_rng(1).standard_normal(U0.shape))
+        B = op.run(U1, 0.0, wl.t_end)[0]
+        out[mode] = np.abs(A - B)[:, 0].mean()
+    assert out[0] < 1e-12 and out[3] > 1e-8, out
