@@ -40,7 +40,7 @@
 
 enum { ORC_BURGERS = 0, ORC_EULER = 1 };
 enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1 };
-enum { ORC_LIM_NONE = 0, ORC_LIM_CSWENO = 1 };
+enum { ORC_LIM_NONE = 0, ORC_LIM_CSWENO = 1, ORC_LIM_CSWENO_CHAR = 2 };
 enum { ORC_IND_TVB = 0, ORC_IND_ALL = 1, ORC_IND_KXRCF = 3 };
 enum { ORC_NEGW_SPLIT = 0, ORC_NEGW_RAW = 1 };
 enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_NONPHYSICAL = -5, ORC_ERR_TABLE = -6 };
@@ -856,7 +856,188 @@ static double interval_mean(const orc_tables *T, int k, int n) {
   return T->sub[sub][n];
 }
 
+/* Eigenvectors of the Euler flux Jacobian in direction dir (0: x, 1: y) at
+ * the conserved state w (1D: 3 components, 2D: 4): R holds the right
+ * eigenvectors as columns (eigenvalues u_n - c, u_n, u_n + c and, in 2D,
+ * u_n for the shear wave), L = R^-1 (rows: left eigenvectors). */
+static void char_eig(int dim, double gamma, int dir, const double *w, double L[ORC_MAXV][ORC_MAXV],
+                     double R[ORC_MAXV][ORC_MAXV]) {
+  const double rho = w[0];
+  double un, ut = 0.0, E;
+  if (dim == 1) {
+    un = w[1] / rho;
+    E = w[2];
+  } else {
+    un = w[1 + dir] / rho;
+    ut = w[2 - dir] / rho;
+    E = w[3];
+  }
+  const double q2 = un * un + ut * ut;
+  const double p = (gamma - 1.0) * (E - 0.5 * rho * q2);
+  const double c = sqrt(gamma * p / rho), H = (E + p) / rho;
+  const double b1 = (gamma - 1.0) / (c * c), b2 = 0.5 * b1 * q2;
+  if (dim == 1) {
+    const double Rm[3][3] = {{1.0, 1.0, 1.0}, {un - c, un, un + c}, {H - un * c, 0.5 * q2, H + un * c}};
+    const double Lm[3][3] = {{0.5 * (b2 + un / c), -0.5 * (b1 * un + 1.0 / c), 0.5 * b1},
+                             {1.0 - b2, b1 * un, -b1},
+                             {0.5 * (b2 - un / c), -0.5 * (b1 * un - 1.0 / c), 0.5 * b1}};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        R[a][b] = Rm[a][b];
+        L[a][b] = Lm[a][b];
+      }
+    return;
+  }
+  /* in the (normal, tangential) ordering of the momentum components */
+  const double Rm[4][4] = {{1.0, 1.0, 1.0, 0.0},
+                           {un - c, un, un + c, 0.0},
+                           {ut, ut, ut, 1.0},
+                           {H - un * c, 0.5 * q2, H + un * c, ut}};
+  const double Lm[4][4] = {{0.5 * (b2 + un / c), -0.5 * (b1 * un + 1.0 / c), -0.5 * b1 * ut, 0.5 * b1},
+                           {1.0 - b2, b1 * un, b1 * ut, -b1},
+                           {0.5 * (b2 - un / c), -0.5 * (b1 * un - 1.0 / c), -0.5 * b1 * ut, 0.5 * b1},
+                           {-ut, 0.0, 1.0, 0.0}};
+  /* back to (rho, rho u, rho v, E): the momentum rows of R and columns of L */
+  const int perm[4] = {0, dir == 0 ? 1 : 2, dir == 0 ? 2 : 1, 3};
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      R[perm[a]][b] = Rm[a][b];
+      L[a][perm[b]] = Lm[a][b];
+    }
+}
+
+int orc_char_eig(const orc_config *c, const double *w, int dir, double *L, double *R) {
+  if (!c || c->equation != ORC_EULER || dir < 0 || dir >= c->dim) return ORC_ERR_ARG;
+  double Lm[ORC_MAXV][ORC_MAXV], Rm[ORC_MAXV][ORC_MAXV];
+  char_eig(c->dim, c->gamma, dir, w, Lm, Rm);
+  const int nv = c->dim + 2;
+  for (int a = 0; a < nv; ++a)
+    for (int b = 0; b < nv; ++b) {
+      L[a * nv + b] = Lm[a][b];
+      R[a * nv + b] = Rm[a][b];
+    }
+  return ORC_OK;
+}
+
+/* Characteristic-field CSWENO (Euler; the paper limits systems in local
+ * characteristic fields, end of Sec. 3): each sweep maps its stencil means to
+ * characteristic fields with L of that sweep's direction, evaluated at the
+ * troubled cell's mean state, reconstructs every field with the same WENO
+ * and maps the point values back with R. */
+static void limit_cell_char(const orc_ctx *x, const double *Uin, int i, int j, double *Uout) {
+  const orc_tables *T = x->T;
+  const int N = x->N, np = x->np, ns = 2 * N + 1, ng = T->ng, nv = x->nv;
+  const double eps = x->c->weno_eps, k0 = cell_mean_factor(x);
+  const int negw = x->c->negw_mode;
+  double w0[ORC_MAXV];
+  if (x->c->dim == 1) {
+    double Cm[ORC_MAXV][ORC_MAXM], C0[ORC_MAXV][ORC_MAXM], Cp[ORC_MAXV][ORC_MAXM];
+    fetch_cell(x, Uin, i - 1, j, Cm);
+    fetch_cell(x, Uin, i, j, C0);
+    fetch_cell(x, Uin, i + 1, j, Cp);
+    for (int v = 0; v < nv; ++v) w0[v] = C0[v][0] * k0;
+    double L[ORC_MAXV][ORC_MAXV], R[ORC_MAXV][ORC_MAXV];
+    char_eig(1, x->c->gamma, 0, w0, L, R);
+    double a[ORC_MAXV][ORC_MAXS], ch[ORC_MAXV][ORC_MAXS], cG[ORC_MAXV][ORC_MAXG];
+    for (int v = 0; v < nv; ++v)
+      for (int k = 0; k < ns; ++k) {
+        double (*src)[ORC_MAXM] = k < N ? Cm : (k == N ? C0 : Cp);
+        double s = 0.0;
+        for (int n = 0; n < np; ++n) s += src[v][n] * interval_mean(T, k, n);
+        a[v][k] = s;
+      }
+    for (int f = 0; f < nv; ++f)
+      for (int k = 0; k < ns; ++k) {
+        double s = 0.0;
+        for (int v = 0; v < nv; ++v) s += L[f][v] * a[v][k];
+        ch[f][k] = s;
+      }
+    for (int f = 0; f < nv; ++f)
+      for (int G = 0; G < ng; ++G) cG[f][G] = orc_weno_point(T, G, ch[f], eps, negw);
+    for (int v = 0; v < nv; ++v)
+      for (int n = 1; n < np; ++n) {
+        double s = 0.0;
+        for (int G = 0; G < ng; ++G) {
+          double uG = 0.0;
+          for (int f = 0; f < nv; ++f) uG += R[v][f] * cG[f][G];
+          s += T->wg[G] * uG * T->bg[n][G];
+        }
+        Uout[at(x, v, n, j, i)] = s;
+      }
+    return;
+  }
+  double B[3][3][ORC_MAXV][ORC_MAXM];
+  for (int dy = -1; dy <= 1; ++dy)
+    for (int dx = -1; dx <= 1; ++dx) fetch_cell(x, Uin, i + dx, j + dy, B[dy + 1][dx + 1]);
+  for (int v = 0; v < nv; ++v) w0[v] = B[1][1][v][0] * k0;
+  double Lx[ORC_MAXV][ORC_MAXV], Rx[ORC_MAXV][ORC_MAXV], Ly[ORC_MAXV][ORC_MAXV], Ry[ORC_MAXV][ORC_MAXV];
+  char_eig(2, x->c->gamma, 0, w0, Lx, Rx);
+  char_eig(2, x->c->gamma, 1, w0, Ly, Ry);
+  double a[ORC_MAXV][ORC_MAXS][ORC_MAXS]; /* [v][iy][ix] */
+  for (int v = 0; v < nv; ++v)
+    for (int iy = 0; iy < ns; ++iy)
+      for (int ix = 0; ix < ns; ++ix) {
+        int cx = ix < N ? 0 : (ix == N ? 1 : 2), cy = iy < N ? 0 : (iy == N ? 1 : 2);
+        double s = 0.0;
+        for (int q = 0; q < x->nm; ++q) {
+          int m = q % np, n = q / np;
+          s += B[cy][cx][v][q] * interval_mean(T, ix, m) * interval_mean(T, iy, n);
+        }
+        a[v][iy][ix] = s;
+      }
+  /* x-sweeps in x-characteristic fields */
+  double vy[ORC_MAXV][ORC_MAXS][ORC_MAXG];
+  for (int iy = 0; iy < ns; ++iy) {
+    double ch[ORC_MAXV][ORC_MAXS], cG[ORC_MAXV][ORC_MAXG];
+    for (int f = 0; f < nv; ++f)
+      for (int ix = 0; ix < ns; ++ix) {
+        double s = 0.0;
+        for (int v = 0; v < nv; ++v) s += Lx[f][v] * a[v][iy][ix];
+        ch[f][ix] = s;
+      }
+    for (int f = 0; f < nv; ++f)
+      for (int G = 0; G < ng; ++G) cG[f][G] = orc_weno_point(T, G, ch[f], eps, negw);
+    for (int v = 0; v < nv; ++v)
+      for (int G = 0; G < ng; ++G) {
+        double s = 0.0;
+        for (int f = 0; f < nv; ++f) s += Rx[v][f] * cG[f][G];
+        vy[v][iy][G] = s;
+      }
+  }
+  /* y-sweeps in y-characteristic fields */
+  double u[ORC_MAXV][ORC_MAXG][ORC_MAXG]; /* [v][G][H] */
+  for (int G = 0; G < ng; ++G) {
+    double ch[ORC_MAXV][ORC_MAXS], cH[ORC_MAXV][ORC_MAXG];
+    for (int f = 0; f < nv; ++f)
+      for (int iy = 0; iy < ns; ++iy) {
+        double s = 0.0;
+        for (int v = 0; v < nv; ++v) s += Ly[f][v] * vy[v][iy][G];
+        ch[f][iy] = s;
+      }
+    for (int f = 0; f < nv; ++f)
+      for (int H = 0; H < ng; ++H) cH[f][H] = orc_weno_point(T, H, ch[f], eps, negw);
+    for (int v = 0; v < nv; ++v)
+      for (int H = 0; H < ng; ++H) {
+        double s = 0.0;
+        for (int f = 0; f < nv; ++f) s += Ry[v][f] * cH[f][H];
+        u[v][G][H] = s;
+      }
+  }
+  for (int v = 0; v < nv; ++v)
+    for (int q = 1; q < x->nm; ++q) {
+      int m = q % np, n = q / np;
+      double s = 0.0;
+      for (int G = 0; G < ng; ++G)
+        for (int H = 0; H < ng; ++H) s += T->wg[G] * T->wg[H] * u[v][G][H] * T->bg[m][G] * T->bg[n][H];
+      Uout[at(x, v, q, j, i)] = s;
+    }
+}
+
 static void limit_cell(const orc_ctx *x, const double *Uin, int i, int j, double *Uout) {
+  if (x->c->limiter == ORC_LIM_CSWENO_CHAR && x->c->equation == ORC_EULER) {
+    limit_cell_char(x, Uin, i, j, Uout);
+    return;
+  }
   const orc_tables *T = x->T;
   int N = x->N, np = x->np, ns = 2 * N + 1, ng = T->ng;
   double eps = x->c->weno_eps;
@@ -938,7 +1119,7 @@ static int limit_state(const orc_ctx *x, double *U, double *work, uint8_t *flags
       else f = any_indicator(x, work, i, j, &m);
       if (flags_out) flags_out[k] = (uint8_t)f;
       if (margin_out) margin_out[k] = m;
-      if (f && x->c->limiter == ORC_LIM_CSWENO) limit_cell(x, work, i, j, U);
+      if (f && x->c->limiter != ORC_LIM_NONE) limit_cell(x, work, i, j, U);
     }
   return ORC_OK;
 }
@@ -1008,7 +1189,7 @@ int orc_step(const orc_config *c, double *U, double dt) {
     return ORC_ERR_ARG;
   }
   int bad = 0;
-  int lim = c->limiter == ORC_LIM_CSWENO;
+  int lim = c->limiter != ORC_LIM_NONE;
   /* stage 1: u1 = u + dt L(u) */
   if (orc_residual(c, U, L)) bad = 1;
   for (size_t k = 0; k < n; ++k) U1[k] = U[k] + dt * L[k];

@@ -24,7 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 BURGERS, EULER = 0, 1
 PERIODIC, TRANSMISSIVE = 0, 1
-LIM_NONE, LIM_CSWENO = 0, 1
+LIM_NONE, LIM_CSWENO, LIM_CSWENO_CHAR = 0, 1, 2
 IND_TVB, IND_ALL, IND_KXRCF = 0, 1, 3
 NEGW_SPLIT, NEGW_RAW = 0, 1
 ERR_NONPHYSICAL = -5
@@ -89,6 +89,7 @@ def lib():
             "orc_quadrature": [ctypes.c_int, ctypes.c_int, P(d), P(d)],
             "orc_basis": [ctypes.c_int, d, P(d), P(d)],
             "orc_num_threads": [],
+            "orc_char_eig": [cfgp, P(d), ctypes.c_int, P(d), P(d)],
         }
         for name, args in sig.items():
             fn = getattr(_lib, name)
@@ -185,6 +186,16 @@ class Problem:
         L = np.empty_like(U)
         self._chk(lib().orc_residual(ctypes.byref(self._c), _dp(U), _dp(L)), "residual")
         return L
+
+    def char_eig(self, w, direction=0):
+        """(L, R): left/right eigenvectors of the Euler flux Jacobian in the given
+        direction at the conserved state w."""
+        nv = self.dim + 2
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        L = np.zeros((nv, nv))
+        R = np.zeros((nv, nv))
+        self._chk(lib().orc_char_eig(ctypes.byref(self._c), _dp(w), int(direction), _dp(L), _dp(R)), "char_eig")
+        return L, R
 
     def indicator(self, U):
         U = np.ascontiguousarray(U, dtype=np.float64)
