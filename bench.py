@@ -78,12 +78,12 @@ def learned_nets(device):
     return nets
 
 
-def indicator_leg(wl, state0, t0, steps, warmup, indicator, net=None):
+def indicator_leg(wl, state0, t0, steps, warmup, indicator=0, net=None, limiter=1):
     """The same problem and state with another troubled-cell indicator (the
-    learned one with its network, or KXRCF)."""
+    learned one with its network, or KXRCF) or limiter (characteristic)."""
     import torch
     from paper_1904_11147_amd import dg, learned
-    prob = dg.problem_from_workload(wl, device="cuda:0", indicator=indicator)
+    prob = dg.problem_from_workload(wl, device="cuda:0", indicator=indicator, limiter=limiter)
     if net is not None:
         learned.attach(prob, net)
     state = state0.clone()
@@ -282,9 +282,10 @@ def main():
         },
     }
     nets = learned_nets("cuda:0")
-    out["learned"] = (indicator_leg(wl, state_warm, t_warm, args.steps, 2, dg.IND_LEARNED, nets[2])
+    out["learned"] = (indicator_leg(wl, state_warm, t_warm, args.steps, 2, dg.IND_LEARNED, net=nets[2])
                       if 2 in nets else None)
     out["kxrcf"] = indicator_leg(wl, state_warm, t_warm, args.steps, 2, dg.IND_KXRCF)
+    out["characteristic"] = indicator_leg(wl, state_warm, t_warm, args.steps, 2, limiter=dg.LIM_CSWENO_CHAR)
     del state_warm
     prob.close()
     del state

@@ -57,7 +57,7 @@ enum {
 
 enum { DG_EQ_BURGERS = 0, DG_EQ_EULER = 1 };
 enum { DG_BC_PERIODIC = 0, DG_BC_TRANSMISSIVE = 1 };
-enum { DG_LIM_NONE = 0, DG_LIM_CSWENO = 1 };
+enum { DG_LIM_NONE = 0, DG_LIM_CSWENO = 1, DG_LIM_CSWENO_CHAR = 2 };
 enum { DG_IND_TVB = 0, DG_IND_ALL = 1, DG_IND_LEARNED = 2, DG_IND_KXRCF = 3 };
 enum { DG_NEGW_SPLIT = 0, DG_NEGW_RAW = 1 };
 
@@ -70,7 +70,10 @@ typedef struct dg_config {
   int32_t bc[4];       /* west, east, south, north: DG_BC_PERIODIC or DG_BC_TRANSMISSIVE
                           (transmissive = even reflection of the adjacent cell;
                           periodic sides must come in pairs) */
-  int32_t limiter;     /* DG_LIM_NONE or DG_LIM_CSWENO */
+  int32_t limiter;     /* DG_LIM_NONE, DG_LIM_CSWENO (componentwise), or DG_LIM_CSWENO_CHAR
+                          (Euler: each WENO sweep in the local characteristic fields of its
+                          direction, eigenvectors of the flux Jacobian at the troubled
+                          cell's mean state, end of Sec. 3; Burgers: as DG_LIM_CSWENO) */
   int32_t indicator;   /* DG_IND_TVB (TVB-modified minmod), DG_IND_ALL (every cell),
                           DG_IND_LEARNED (2D Euler only: the MLP of dg_set_learned with the
                           TVB decision in its uncertain band), or DG_IND_KXRCF (the

@@ -57,7 +57,8 @@ int validate_config(const dg_config *c) {
     if (c->bc[k] != DG_BC_PERIODIC && c->bc[k] != DG_BC_TRANSMISSIVE) return DG_ERR_INVALID_ARG;
   if ((c->bc[0] == DG_BC_PERIODIC) != (c->bc[1] == DG_BC_PERIODIC)) return DG_ERR_INVALID_ARG;
   if (c->dim == 2 && (c->bc[2] == DG_BC_PERIODIC) != (c->bc[3] == DG_BC_PERIODIC)) return DG_ERR_INVALID_ARG;
-  if (c->limiter != DG_LIM_NONE && c->limiter != DG_LIM_CSWENO) return DG_ERR_INVALID_ARG;
+  if (c->limiter != DG_LIM_NONE && c->limiter != DG_LIM_CSWENO && c->limiter != DG_LIM_CSWENO_CHAR)
+    return DG_ERR_INVALID_ARG;
   if (c->indicator != DG_IND_TVB && c->indicator != DG_IND_ALL && c->indicator != DG_IND_LEARNED &&
       c->indicator != DG_IND_KXRCF)
     return DG_ERR_UNSUPPORTED;
@@ -190,7 +191,7 @@ void harvest(dg_problem *p) {
 // One SSP-RK3 step with the limiter after every stage (enqueue only).
 int enqueue_step(dg_problem *p, double *state, bool cfl_mode) {
   LaunchCtx &c = p->ctx;
-  const bool lim = p->cfg.limiter == DG_LIM_CSWENO;
+  const bool lim = p->cfg.limiter != DG_LIM_NONE;
   int rc;
   { Timed t(p, DG_PROF_DT); rc = dg::launch_dt_finalize(c); }
   if (!rc) { Timed t(p, DG_PROF_STAGE1); rc = dg::launch_stage(c, 1, state, nullptr, c.bufA, false); }

@@ -168,7 +168,7 @@ int enqueue_batch_step(dg_batch *b) {
   for (int stage = 1; stage <= 3 && !rc; ++stage) {
     for (int o = 1; o <= kMaxN && !rc; ++o)
       if (b->present[o]) rc = dg::batch_launch_stage(b->ctx, o, stage, b->grid[o]);
-    if (b->ctx.limiter != DG_LIM_CSWENO) continue;
+    if (b->ctx.limiter == DG_LIM_NONE) continue;
     for (int o = 1; o <= kMaxN && !rc; ++o)
       if (b->present[o]) rc = dg::batch_launch_limit(b->ctx, o, stage - 1);
   }

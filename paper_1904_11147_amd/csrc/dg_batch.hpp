@@ -257,6 +257,18 @@ __global__ __launch_bounds__(kBlock) void k_batch_csweno(const BatchInst *__rest
 }
 
 template <int N, int SLOT>
+__global__ __launch_bounds__(kBlock) void k_batch_csweno_char(const BatchInst *__restrict__ inst,
+                                                              const BatchQueue *__restrict__ q,
+                                                              const long long *__restrict__ list) {
+  const long total = q->count[SLOT];
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const long long e = list[t];
+    const BatchInst &I = inst[(int)(e >> 32)];
+    csweno_char_cell<N, 2>(limit_target<SLOT>(I), limit_side<SLOT>(I), I.geo, (long)(e & 0xffffffffll));
+  }
+}
+
+template <int N, int SLOT>
 __global__ __launch_bounds__(kBlock) void k_batch_scatter(const BatchInst *__restrict__ inst,
                                                           const BatchQueue *__restrict__ q,
                                                           const long long *__restrict__ list) {

@@ -1656,6 +1656,240 @@ __global__ __launch_bounds__(kBlock) void k_csweno(LimitArgs a) {
     csweno_cell<N, EQ, DIM>(a.u, a.side, a.geo, a.list[t / NV], (int)(t % NV));
 }
 
+// ---------------------------------------------------------------------------
+// CSWENO in local characteristic fields (Euler; the paper limits systems in
+// characteristic fields, end of Sec. 3).  One thread per troubled cell.
+// ---------------------------------------------------------------------------
+
+// Eigenvectors of the Euler flux Jacobian in direction dir at the conserved
+// state w: R's columns are the right eigenvectors (eigenvalues u_n - c, u_n,
+// u_n + c, and u_n for the 2D shear wave), L = R^-1.
+template <int DIM>
+__device__ inline void char_eig(double gam, int dir, const double (&w)[DIM + 2], double (&L)[DIM + 2][DIM + 2],
+                                double (&R)[DIM + 2][DIM + 2]) {
+  const double rho = w[0];
+  const double un = (DIM == 1 ? w[1] : w[1 + dir]) / rho;
+  const double ut = DIM == 1 ? 0.0 : w[2 - dir] / rho;
+  const double E = w[DIM + 1];
+  const double q2 = un * un + ut * ut;
+  const double p = (gam - 1.0) * (E - 0.5 * rho * q2);
+  const double c = sqrt(gam * p / rho), H = (E + p) / rho;
+  const double b1 = (gam - 1.0) / (c * c), b2 = 0.5 * b1 * q2;
+  if constexpr (DIM == 1) {
+    const double Rm[3][3] = {{1.0, 1.0, 1.0}, {un - c, un, un + c}, {H - un * c, 0.5 * q2, H + un * c}};
+    const double Lm[3][3] = {{0.5 * (b2 + un / c), -0.5 * (b1 * un + 1.0 / c), 0.5 * b1},
+                             {1.0 - b2, b1 * un, -b1},
+                             {0.5 * (b2 - un / c), -0.5 * (b1 * un - 1.0 / c), 0.5 * b1}};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        R[a][b] = Rm[a][b];
+        L[a][b] = Lm[a][b];
+      }
+  } else {
+    // (normal, tangential) momentum ordering, then permuted back to (x, y)
+    const double Rm[4][4] = {{1.0, 1.0, 1.0, 0.0},
+                             {un - c, un, un + c, 0.0},
+                             {ut, ut, ut, 1.0},
+                             {H - un * c, 0.5 * q2, H + un * c, ut}};
+    const double Lm[4][4] = {{0.5 * (b2 + un / c), -0.5 * (b1 * un + 1.0 / c), -0.5 * b1 * ut, 0.5 * b1},
+                             {1.0 - b2, b1 * un, b1 * ut, -b1},
+                             {0.5 * (b2 - un / c), -0.5 * (b1 * un - 1.0 / c), -0.5 * b1 * ut, 0.5 * b1},
+                             {-ut, 0.0, 1.0, 0.0}};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int pa = a == 1 ? 1 + dir : (a == 2 ? 2 - dir : a);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int pb = b == 1 ? 1 + dir : (b == 2 ? 2 - dir : b);
+        R[pa][b] = Rm[a][b];
+        L[a][pb] = Lm[a][b];
+      }
+    }
+  }
+}
+
+// Modes of variable v of cell (i, j) with the boundary reflections applied.
+template <int NP, int NM, int DIM>
+__device__ inline void load_var(const double *__restrict__ u, long plane, const CellIdx &c, int v, double (&md)[NM]) {
+#pragma unroll
+  for (int q = 0; q < NM; ++q) {
+    const int m = q % NP, n = q / NP;
+    const double s = u[(long)(v * NM + q) * plane + c.idx];
+    md[q] = ((c.fx && (m & 1)) != (DIM == 2 && c.fy && (n & 1))) ? -s : s;
+  }
+}
+
+template <int N, int DIM>
+__device__ inline void csweno_char_cell(const double *__restrict__ u, double *__restrict__ side, const Geometry &g,
+                                        long cell) {
+  constexpr int NP = N + 1, NM = DIM == 1 ? NP : NP * NP, NV = DIM + 2;
+  constexpr int NS = 2 * N + 1, NG = num_points<N>();
+  const OrderTables &T = c_tab[N];
+  const long plane = (long)g.nx * g.ny;
+  const bool raw = g.negw_raw != 0;
+  const int i = (int)(cell % g.nx), j = (int)(cell / g.nx);
+  const double k0 = DIM == 1 ? T.b0[0] : T.b0[0] * T.b0[0];
+  double w0[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) w0[v] = u[(long)(v * NM) * plane + cell] * k0;
+  double L[NV][NV], R[NV][NV];
+  if constexpr (DIM == 1) {
+    double a[NV][NS];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const CellIdx ci = map_cell(g, i + c - 1, 0);
+      const int k0c = c == 0 ? 0 : (c == 1 ? N : N + 1), k1c = c == 0 ? N : (c == 1 ? N + 1 : NS);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double md[NM];
+        load_var<NP, NM, 1>(u, plane, ci, v, md);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          if (k < k0c || k >= k1c) continue;
+          double s = 0.0;
+#pragma unroll
+          for (int n = 0; n < NP; ++n) s += md[n] * interval_mean<N>(T, k, n);
+          a[v][k] = s;
+        }
+      }
+    }
+    char_eig<1>(g.gamma, 0, w0, L, R);
+    double cG[NV][NG];
+#pragma unroll
+    for (int f = 0; f < NV; ++f) {
+      double ch[NS];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s += L[f][v] * a[v][k];
+        ch[k] = s;
+      }
+      weno_row<N>(T, ch, cG[f], g.eps, raw);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int n = 1; n < NP; ++n) {
+        double s = 0.0;
+#pragma unroll
+        for (int G = 0; G < NG; ++G) {
+          double uG = 0.0;
+#pragma unroll
+          for (int f = 0; f < NV; ++f) uG += R[v][f] * cG[f][G];
+          s += T.wg[G] * uG * T.bg[n][G];
+        }
+        side[(long)(v * NM + n) * plane + cell] = s;
+      }
+  } else {
+    // x-sweeps on every y-interval, in x-characteristic fields
+    double vy[NV][NS][NG];
+    char_eig<2>(g.gamma, 0, w0, L, R);
+#pragma unroll 1
+    for (int iy = 0; iy < NS; ++iy) {
+      const int cy = iy < N ? 0 : (iy == N ? 1 : 2);
+      double a[NV][NS];
+#pragma unroll
+      for (int cx = 0; cx < 3; ++cx) {
+        const CellIdx ci = map_cell(g, i + cx - 1, j + cy - 1);
+        const int x0 = cx == 0 ? 0 : (cx == 1 ? N : N + 1), x1 = cx == 0 ? N : (cx == 1 ? N + 1 : NS);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          double md[NM];
+          load_var<NP, NM, 2>(u, plane, ci, v, md);
+#pragma unroll
+          for (int ix = 0; ix < NS; ++ix) {
+            if (ix < x0 || ix >= x1) continue;
+            double s = 0.0;
+#pragma unroll
+            for (int n = 0; n < NP; ++n) {
+              double t = 0.0;
+#pragma unroll
+              for (int m = 0; m < NP; ++m) t += md[m + NP * n] * interval_mean<N>(T, ix, m);
+              s += t * interval_mean<N>(T, iy, n);
+            }
+            a[v][ix] = s;
+          }
+        }
+      }
+      double cG[NV][NG];
+#pragma unroll
+      for (int f = 0; f < NV; ++f) {
+        double ch[NS];
+#pragma unroll
+        for (int ix = 0; ix < NS; ++ix) {
+          double s = 0.0;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) s += L[f][v] * a[v][ix];
+          ch[ix] = s;
+        }
+        weno_row<N>(T, ch, cG[f], g.eps, raw);
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int G = 0; G < NG; ++G) {
+          double s = 0.0;
+#pragma unroll
+          for (int f = 0; f < NV; ++f) s += R[v][f] * cG[f][G];
+          vy[v][iy][G] = s;
+        }
+    }
+    // y-sweeps at every x-point, in y-characteristic fields, and the projection
+    char_eig<2>(g.gamma, 1, w0, L, R);
+    double out[NV][NM];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int q = 0; q < NM; ++q) out[v][q] = 0.0;
+#pragma unroll
+    for (int G = 0; G < NG; ++G) {
+      double cH[NV][NG];
+#pragma unroll
+      for (int f = 0; f < NV; ++f) {
+        double ch[NS];
+#pragma unroll
+        for (int iy = 0; iy < NS; ++iy) {
+          double s = 0.0;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) s += L[f][v] * vy[v][iy][G];
+          ch[iy] = s;
+        }
+        weno_row<N>(T, ch, cH[f], g.eps, raw);
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int n = 0; n < NP; ++n) {
+          double sn = 0.0;
+#pragma unroll
+          for (int H = 0; H < NG; ++H) {
+            double uH = 0.0;
+#pragma unroll
+            for (int f = 0; f < NV; ++f) uH += R[v][f] * cH[f][H];
+            sn += T.wg[H] * uH * T.bg[n][H];
+          }
+#pragma unroll
+          for (int m = 0; m < NP; ++m) out[v][m + NP * n] += T.wg[G] * T.bg[m][G] * sn;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int q = 1; q < NM; ++q) side[(long)(v * NM + q) * plane + cell] = out[v][q];
+  }
+}
+
+template <int N, int DIM>
+__global__ __launch_bounds__(kBlock) void k_csweno_char(LimitArgs a) {
+  if (a.check_done && a.sc->done) return;
+  const long total = *a.count;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x)
+    csweno_char_cell<N, DIM>(a.u, a.side, a.geo, a.list[t]);
+}
+
 template <int NM, int NV>
 __global__ __launch_bounds__(kBlock) void k_scatter(LimitArgs a, double *dst) {
   if (a.check_done && a.sc->done) return;
@@ -1822,8 +2056,15 @@ int launch_limit(const LaunchCtx &c, double *u, double *side, int count_slot, ui
       }
     }
     if (!learned) hipLaunchKernelGGL((k_indicator<n, e, d>), grid, block, 0, S(c), a);
-    if (c.limiter == DG_LIM_CSWENO) {
-      hipLaunchKernelGGL((k_csweno<n, e, d>), dim3(c.grid_cap), dim3(kBlock), 0, S(c), a);
+    if (c.limiter != DG_LIM_NONE) {
+      bool chr = false;
+      if constexpr (e == DG_EQ_EULER) {
+        if (c.limiter == DG_LIM_CSWENO_CHAR) {
+          hipLaunchKernelGGL((k_csweno_char<n, d>), dim3(c.grid_cap), dim3(kBlock), 0, S(c), a);
+          chr = true;
+        }
+      }
+      if (!chr) hipLaunchKernelGGL((k_csweno<n, e, d>), dim3(c.grid_cap), dim3(kBlock), 0, S(c), a);
       hipLaunchKernelGGL((k_scatter<NM, NV>), dim3(c.grid_cap), dim3(kBlock), 0, S(c), a, u);
     }
   });
@@ -1994,8 +2235,11 @@ int batch_launch_limit(const BatchCtx &b, int order, int slot) {
       else
         hipLaunchKernelGGL((k_batch_indicator<n, s, DG_IND_TVB>), dim3(4 * b.grid_cap), dim3(64), 0, st, b.inst, q,
                            list);
-      if (b.limiter == DG_LIM_CSWENO) {
-        hipLaunchKernelGGL((k_batch_csweno<n, s>), dim3(b.grid_cap), dim3(kBlock), 0, st, b.inst, q, list);
+      if (b.limiter != DG_LIM_NONE) {
+        if (b.limiter == DG_LIM_CSWENO_CHAR)
+          hipLaunchKernelGGL((k_batch_csweno_char<n, s>), dim3(b.grid_cap), dim3(kBlock), 0, st, b.inst, q, list);
+        else
+          hipLaunchKernelGGL((k_batch_csweno<n, s>), dim3(b.grid_cap), dim3(kBlock), 0, st, b.inst, q, list);
         hipLaunchKernelGGL((k_batch_scatter<n, s>), dim3(b.grid_cap), dim3(kBlock), 0, st, b.inst, q, list);
       }
     };

@@ -21,7 +21,7 @@ DG_ABI_VERSION = 1
 DG_OK, DG_ERR_INVALID_ARG, DG_ERR_UNSUPPORTED, DG_ERR_WORKSPACE, DG_ERR_HIP, DG_ERR_NONPHYSICAL = 0, -1, -2, -3, -4, -5
 BURGERS, EULER = 0, 1
 PERIODIC, TRANSMISSIVE = 0, 1
-LIM_NONE, LIM_CSWENO = 0, 1
+LIM_NONE, LIM_CSWENO, LIM_CSWENO_CHAR = 0, 1, 2
 IND_TVB, IND_ALL, IND_LEARNED, IND_KXRCF = 0, 1, 2, 3
 NEGW_SPLIT, NEGW_RAW = 0, 1
 
