@@ -18,7 +18,10 @@
  * the x-degree and n the y-degree of the tensor Legendre mode (1D: q = m).
  *
  * Parity pins: quadrature, P2 tables, P1 tables, residual, TVB and limiter
- * invariants are pinned by tests/test_oracle_*.py.  The P3 treatment of the
+ * invariants are pinned by tests/test_oracle_*.py; the reflective wall,
+ * inflow and switching boundary sides by mirror images, periodic images and
+ * stage-time checks (test_oracle_boundary.py); the positivity scaling by
+ * bisection on its defining property (test_oracle_positivity.py).  The P3 treatment of the
  * negative linear weights is "parity unpinned" (the paper does not say what
  * it does with them; see orc_weno_point).
  */
@@ -39,7 +42,7 @@
 #define ORC_MAXPQ 10 /* projection nodes per direction: 2 panels x (N+2) */
 
 enum { ORC_BURGERS = 0, ORC_EULER = 1 };
-enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1 };
+enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1, ORC_BC_REFLECTIVE = 2, ORC_BC_INFLOW = 3 };
 enum { ORC_LIM_NONE = 0, ORC_LIM_CSWENO = 1, ORC_LIM_CSWENO_CHAR = 2 };
 enum { ORC_IND_TVB = 0, ORC_IND_ALL = 1, ORC_IND_KXRCF = 3 };
 enum { ORC_NEGW_SPLIT = 0, ORC_NEGW_RAW = 1 };
@@ -50,6 +53,17 @@ typedef struct {
   int32_t bc[4]; /* W, E, S, N */
   int32_t limiter, indicator, negw_mode;
   double gamma, x0, x1, y0, y1, tvb_M, weno_eps, cfl;
+  /* Positivity-preserving scaling of Zhang & Shu (the component the paper
+   * adds for the double Mach reflection, Example 11), after the limiter. */
+  int32_t positivity;
+  /* South/north sides may switch kind along x: kind bc[s] where the ghost
+   * cell's centre x < a + b t, kind bc_beyond[s] from there on (-1: no
+   * switch; west/east sides never switch). */
+  int32_t bc_beyond[4];
+  int32_t pad_;
+  double bc_switch[4][2];   /* [side] {a, b} */
+  double bc_state[4][2][4]; /* conserved ghost state of an inflow part [side][before, beyond][var] */
+  double time;              /* time of the boundary data (orc_step: the step's start time) */
 } orc_config;
 
 /* ------------------------------------------------------------------------ */
@@ -429,6 +443,7 @@ typedef struct {
   int N, np, nm, nv, nx, ny;
   double hx, hy;
   double kx_scale; /* KXRCF: 1 / h^((N+1)/2), h the radius of the cell's circumscribed circle */
+  double time;     /* time of the boundary data */
 } orc_ctx;
 
 static int make_ctx(const orc_config *c, orc_ctx *x) {
@@ -436,7 +451,16 @@ static int make_ctx(const orc_config *c, orc_ctx *x) {
     return ORC_ERR_ARG;
   if (c->dim == 1 && c->ny != 1) return ORC_ERR_ARG;
   if (c->equation != ORC_BURGERS && c->equation != ORC_EULER) return ORC_ERR_ARG;
+  for (int s = 0; s < 4; ++s) {
+    int k = c->bc[s], kb = c->bc_beyond[s];
+    if (k < ORC_BC_PERIODIC || k > ORC_BC_INFLOW) return ORC_ERR_ARG;
+    if (kb < -1 || kb > ORC_BC_INFLOW || kb == ORC_BC_PERIODIC) return ORC_ERR_ARG;
+    if (kb >= 0 && (s < 2 || c->dim == 1 || k == ORC_BC_PERIODIC)) return ORC_ERR_ARG;
+    if ((k == ORC_BC_REFLECTIVE || kb == ORC_BC_REFLECTIVE) && c->equation != ORC_EULER) return ORC_ERR_ARG;
+  }
+  if (c->positivity && c->equation != ORC_EULER) return ORC_ERR_ARG;
   x->c = c;
+  x->time = c->time;
   x->T = tables(c->order);
   if (!x->T) return ORC_ERR_TABLE;
   x->N = c->order;
@@ -458,22 +482,56 @@ static size_t at(const orc_ctx *x, int v, int q, int j, int i) {
   return (((size_t)v * x->nm + q) * x->ny + j) * x->nx + i;
 }
 
+/* Kind of boundary side s (0 W, 1 E, 2 S, 3 N) for a ghost cell whose
+ * centre has tangential coordinate xt, at the context's time; *state gets
+ * the inflow state of that part of the side. */
+static int side_kind(const orc_ctx *x, int s, double xt, const double **state) {
+  const orc_config *c = x->c;
+  int beyond = c->bc_beyond[s] >= 0 && !(xt < c->bc_switch[s][0] + c->bc_switch[s][1] * x->time);
+  *state = c->bc_state[s][beyond];
+  return beyond ? c->bc_beyond[s] : c->bc[s];
+}
+
 /* Modes of cell (i,j), i in [-1,nx], j in [-1,ny], with the boundary
- * conditions: periodic wrap, or transmissive as an even reflection of the
- * adjacent interior cell (odd modes in the normal direction change sign). */
+ * conditions.  Beyond a side the ghost cell is: the periodic image; the
+ * even reflection of the adjacent interior cell (transmissive: odd modes in
+ * the normal direction change sign); that reflection with the normal
+ * momentum negated as well (reflective wall); or the constant inflow state
+ * (all higher modes zero).  The x side is resolved first: a corner ghost
+ * beyond an inflow west/east side is that inflow state; otherwise the
+ * south/north rule applies to the column the x side mapped to. */
 static void fetch_cell(const orc_ctx *x, const double *U, int i, int j, double out[ORC_MAXV][ORC_MAXM]) {
-  int fx = 0, fy = 0;
-  if (i < 0) {
-    if (x->c->bc[0] == ORC_BC_PERIODIC) i += x->nx; else { i = 0; fx = 1; }
-  } else if (i >= x->nx) {
-    if (x->c->bc[1] == ORC_BC_PERIODIC) i -= x->nx; else { i = x->nx - 1; fx = 1; }
-  }
-  if (x->c->dim == 2) {
-    if (j < 0) {
-      if (x->c->bc[2] == ORC_BC_PERIODIC) j += x->ny; else { j = 0; fy = 1; }
-    } else if (j >= x->ny) {
-      if (x->c->bc[3] == ORC_BC_PERIODIC) j -= x->ny; else { j = x->ny - 1; fy = 1; }
+  int fx = 0, fy = 0, negx = 0, negy = 0;
+  const double *inflow = NULL, *st;
+  if (i < 0 || i >= x->nx) {
+    int s = i < 0 ? 0 : 1;
+    int k = side_kind(x, s, 0.0, &st);
+    if (k == ORC_BC_PERIODIC) {
+      i += s ? -x->nx : x->nx;
+    } else {
+      i = s ? x->nx - 1 : 0;
+      fx = 1;
+      negx = k == ORC_BC_REFLECTIVE;
+      if (k == ORC_BC_INFLOW) inflow = st;
     }
+  }
+  if (!inflow && x->c->dim == 2 && (j < 0 || j >= x->ny)) {
+    int s = j < 0 ? 2 : 3;
+    int k = side_kind(x, s, x->c->x0 + (i + 0.5) * x->hx, &st);
+    if (k == ORC_BC_PERIODIC) {
+      j += s == 3 ? -x->ny : x->ny;
+    } else {
+      j = s == 3 ? x->ny - 1 : 0;
+      fy = 1;
+      negy = k == ORC_BC_REFLECTIVE;
+      if (k == ORC_BC_INFLOW) inflow = st;
+    }
+  }
+  if (inflow) {
+    double k0 = x->c->dim == 1 ? x->T->b0[0] : x->T->b0[0] * x->T->b0[0];
+    for (int v = 0; v < x->nv; ++v)
+      for (int q = 0; q < x->nm; ++q) out[v][q] = q == 0 ? inflow[v] / k0 : 0.0;
+    return;
   }
   for (int v = 0; v < x->nv; ++v)
     for (int q = 0; q < x->nm; ++q) {
@@ -481,6 +539,7 @@ static void fetch_cell(const orc_ctx *x, const double *U, int i, int j, double o
       double s = U[at(x, v, q, j, i)];
       if (fx && (m & 1)) s = -s;
       if (fy && (n & 1)) s = -s;
+      if ((negx && v == 1) || (negy && v == 2)) s = -s;
       out[v][q] = s;
     }
 }
@@ -1102,6 +1161,8 @@ static void limit_cell(const orc_ctx *x, const double *Uin, int i, int j, double
   }
 }
 
+static int positivity_state(const orc_ctx *x, double *U, double *theta);
+
 /* Indicator + CSWENO with Jacobi semantics: every decision and every
  * reconstruction reads the state as it was before this call. */
 static int limit_state(const orc_ctx *x, double *U, double *work, uint8_t *flags_out, double *margin_out,
@@ -1133,7 +1194,175 @@ int orc_limit(const orc_config *c, double *U, uint8_t *flags_out, double *margin
   if (!work) return ORC_ERR_ARG;
   rc = limit_state(&x, U, work, flags_out, margin_out, flags_in);
   free(work);
+  if (!rc && c->positivity) rc = positivity_state(&x, U, NULL);
   return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Positivity-preserving scaling of Zhang & Shu for rectangular meshes, the  */
+/* component the paper adds to the limiter for Example 11.                   */
+/* ------------------------------------------------------------------------ */
+
+/* Points where density and pressure are kept at or above eps: the tensor
+ * products of the face rule G ((N+1)-point Gauss) with the L-point
+ * Gauss-Lobatto rule S (smallest L with 2L-3 >= N) in both orders, as Zhang
+ * and Shu require, and also the volume points G x G, so that every point
+ * where the scheme evaluates a flux is admissible.  1D: S and G. */
+static int pos_points(const orc_ctx *x, double *r, double *s) {
+  int N = x->N, L = N == 1 ? 2 : 3, n = 0;
+  double g[ORC_MAXP], gw[ORC_MAXP], l[3], lw[3];
+  gauss_rule(N + 1, g, gw);
+  gauss_lobatto_rule(L, l, lw);
+  if (x->c->dim == 1) {
+    for (int a = 0; a < L; ++a) { r[n] = l[a]; s[n++] = 0.0; }
+    for (int a = 0; a <= N; ++a) { r[n] = g[a]; s[n++] = 0.0; }
+    return n;
+  }
+  for (int a = 0; a <= N; ++a)
+    for (int b = 0; b < L; ++b) { r[n] = g[a]; s[n++] = l[b]; }
+  for (int a = 0; a < L; ++a)
+    for (int b = 0; b <= N; ++b) { r[n] = l[a]; s[n++] = g[b]; }
+  for (int a = 0; a <= N; ++a)
+    for (int b = 0; b <= N; ++b) { r[n] = g[a]; s[n++] = g[b]; }
+  return n;
+}
+
+static double pressure(const orc_ctx *x, const double *w) {
+  double ke = 0.0;
+  for (int d = 1; d <= x->c->dim; ++d) ke += w[d] * w[d];
+  return (x->c->gamma - 1.0) * (w[x->nv - 1] - 0.5 * ke / w[0]);
+}
+
+/* The t in [0,1] where the pressure along wb + t (wq - wb) falls to eps,
+ * for p(wb) >= eps > p(wq) and positive density on the segment.  Multiplied
+ * by the density, p = eps is a quadratic A t^2 + B t + C = 0 with C >= 0 and
+ * A + B + C < 0; pressure is concave along the segment, so the crossing is
+ * unique and is the root where the quadratic decreases,
+ * (-B - sqrt(D)) / (2A) = 2C / (sqrt(D) - B) with D = B^2 - 4AC, taken in
+ * the form without cancellation: the second for B <= 0, the first for B > 0
+ * (where A < 0). */
+static double pos_root(const orc_ctx *x, const double *wb, const double *wq, double eps) {
+  int e = x->nv - 1;
+  double ee = eps / (x->c->gamma - 1.0);
+  double dr = wq[0] - wb[0], dE = wq[e] - wb[e], mm = 0.0, md = 0.0, dd = 0.0;
+  for (int d = 1; d <= x->c->dim; ++d) {
+    double dm = wq[d] - wb[d];
+    mm += wb[d] * wb[d];
+    md += wb[d] * dm;
+    dd += dm * dm;
+  }
+  double A = dE * dr - 0.5 * dd;
+  double B = wb[e] * dr + wb[0] * dE - md - ee * dr;
+  double C = wb[e] * wb[0] - 0.5 * mm - ee * wb[0];
+  if (!(C > 0.0)) return 0.0;
+  double D = B * B - 4.0 * A * C;
+  if (D < 0.0) D = 0.0;
+  double t = B <= 0.0 ? 2.0 * C / (sqrt(D) - B) : (-B - sqrt(D)) / (2.0 * A);
+  return t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+}
+
+/* Floor of density and pressure.  Zhang and Shu use 1e-13; in double
+ * precision the pressure of a scaled point value carries an absolute
+ * rounding error near 1e-16 times the energy, which exceeds 1e-13 once the
+ * energy is in the hundreds (about 560 behind the Mach 10 shock), and a
+ * point left at -1e-14 breaks the sound speed.  1e-10 keeps a margin of
+ * three orders over that error. */
+#define ORC_POS_EPS 1e-10
+
+/* One cell: density scaled towards its mean by theta1 so that it is >= eps
+ * at every point, then the whole state by theta2 so that the pressure is >=
+ * eps at every point; eps = min(ORC_POS_EPS, mean density, mean pressure).
+ * The cell mean never changes.  Returns 1 if the mean itself is not admissible
+ * (the cell is then left as it is). */
+typedef struct {
+  int n;
+  double br[64][ORC_MAXP], bs[64][ORC_MAXP]; /* psi_m(r_k), psi_n(s_k) */
+} pos_table;
+
+static void pos_make_table(const orc_ctx *x, pos_table *P) {
+  double r[64], sv[64];
+  P->n = pos_points(x, r, sv);
+  for (int k = 0; k < P->n; ++k)
+    for (int n = 0; n <= x->N; ++n) {
+      P->br[k][n] = psi(n, r[k]);
+      P->bs[k][n] = psi(n, sv[k]);
+    }
+}
+
+static int positivity_cell(const orc_ctx *x, const pos_table *P, double *U, int i, int j, double *th) {
+  double C[ORC_MAXV][ORC_MAXM], wb[ORC_MAXV];
+  double k0 = cell_mean_factor(x);
+  for (int v = 0; v < x->nv; ++v) {
+    for (int q = 0; q < x->nm; ++q) C[v][q] = U[at(x, v, q, j, i)];
+    wb[v] = C[v][0] * k0;
+  }
+  th[0] = th[1] = 1.0;
+  double pb = pressure(x, wb);
+  if (!(wb[0] > 0.0 && pb > 0.0)) return 1;
+  double eps = fmin(ORC_POS_EPS, fmin(wb[0], pb));
+  double rmin = INFINITY;
+  for (int k = 0; k < P->n; ++k) {
+    double w[ORC_MAXV];
+    point_value(x, C, P->br[k], P->bs[k], w);
+    rmin = fmin(rmin, w[0]);
+  }
+  if (rmin < eps) {
+    th[0] = (wb[0] - eps) / (wb[0] - rmin);
+    for (int q = 1; q < x->nm; ++q) C[0][q] *= th[0];
+  }
+  for (int k = 0; k < P->n; ++k) {
+    double w[ORC_MAXV];
+    point_value(x, C, P->br[k], P->bs[k], w);
+    if (pressure(x, w) < eps) th[1] = fmin(th[1], pos_root(x, wb, w, eps));
+  }
+  if (th[1] < 1.0)
+    for (int v = 0; v < x->nv; ++v)
+      for (int q = 1; q < x->nm; ++q) C[v][q] *= th[1];
+  if (th[0] < 1.0 || th[1] < 1.0)
+    for (int v = 0; v < x->nv; ++v)
+      for (int q = 1; q < x->nm; ++q) U[at(x, v, q, j, i)] = C[v][q];
+  return 0;
+}
+
+/* Every cell; theta (optional): [2][ny][nx] = theta1, theta2. */
+static int positivity_state(const orc_ctx *x, double *U, double *theta) {
+  int bad = 0;
+  pos_table P;
+  pos_make_table(x, &P);
+#pragma omp parallel for schedule(static) reduction(| : bad)
+  for (int j = 0; j < x->ny; ++j)
+    for (int i = 0; i < x->nx; ++i) {
+      double th[2];
+      bad |= positivity_cell(x, &P, U, i, j, th);
+      if (theta) {
+        size_t k = (size_t)j * x->nx + i;
+        theta[k] = th[0];
+        theta[(size_t)x->nx * x->ny + k] = th[1];
+      }
+    }
+  return bad ? ORC_ERR_NONPHYSICAL : ORC_OK;
+}
+
+int orc_positivity(const orc_config *c, double *U, double *theta) {
+  orc_ctx x;
+  int rc = make_ctx(c, &x);
+  if (rc) return rc;
+  if (c->equation != ORC_EULER) return ORC_ERR_ARG;
+  return positivity_state(&x, U, theta);
+}
+
+/* Ghost cell (i, j) outside the mesh (or an interior cell) as the boundary
+ * conditions give it at the configuration's time: out [nv][nm]. */
+int orc_ghost(const orc_config *c, const double *U, int32_t i, int32_t j, double *out) {
+  orc_ctx x;
+  int rc = make_ctx(c, &x);
+  if (rc) return rc;
+  if (i < -1 || i > x.nx || j < (c->dim == 2 ? -1 : 0) || j > (c->dim == 2 ? x.ny : 0)) return ORC_ERR_ARG;
+  double C[ORC_MAXV][ORC_MAXM];
+  fetch_cell(&x, U, i, j, C);
+  for (int v = 0; v < x.nv; ++v)
+    for (int q = 0; q < x.nm; ++q) out[v * x.nm + q] = C[v][q];
+  return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1177,6 +1406,10 @@ int orc_cfl_dt(const orc_config *c, const double *U, double *dt) {
 /* Third-order TVD (SSP) Runge-Kutta with the limiter after every stage.     */
 /* ------------------------------------------------------------------------ */
 
+/* Boundary data are taken at the time each stage's input approximates:
+ * t^n for the first residual, t^n + dt for the limiter after the first stage
+ * and the second residual, t^n + dt/2 for the limiter after the second stage
+ * and the third residual, t^n + dt after the last stage (c->time = t^n). */
 int orc_step(const orc_config *c, double *U, double dt) {
   orc_ctx x;
   int rc = make_ctx(c, &x);
@@ -1190,18 +1423,29 @@ int orc_step(const orc_config *c, double *U, double dt) {
   }
   int bad = 0;
   int lim = c->limiter != ORC_LIM_NONE;
+  double tn = c->time;
+  orc_config cs = *c;
+  orc_ctx xs = x;
+  xs.c = &cs;
   /* stage 1: u1 = u + dt L(u) */
-  if (orc_residual(c, U, L)) bad = 1;
+  cs.time = tn;
+  if (orc_residual(&cs, U, L)) bad = 1;
   for (size_t k = 0; k < n; ++k) U1[k] = U[k] + dt * L[k];
-  if (lim) limit_state(&x, U1, W, NULL, NULL, NULL);
+  cs.time = xs.time = tn + dt;
+  if (lim) limit_state(&xs, U1, W, NULL, NULL, NULL);
+  if (c->positivity && positivity_state(&xs, U1, NULL)) bad = 1;
   /* stage 2: u2 = 3/4 u + 1/4 (u1 + dt L(u1)) */
-  if (orc_residual(c, U1, L)) bad = 1;
+  if (orc_residual(&cs, U1, L)) bad = 1;
   for (size_t k = 0; k < n; ++k) U2[k] = 0.75 * U[k] + 0.25 * (U1[k] + dt * L[k]);
-  if (lim) limit_state(&x, U2, W, NULL, NULL, NULL);
+  cs.time = xs.time = tn + 0.5 * dt;
+  if (lim) limit_state(&xs, U2, W, NULL, NULL, NULL);
+  if (c->positivity && positivity_state(&xs, U2, NULL)) bad = 1;
   /* stage 3: u = 1/3 u + 2/3 (u2 + dt L(u2)) */
-  if (orc_residual(c, U2, L)) bad = 1;
+  if (orc_residual(&cs, U2, L)) bad = 1;
   for (size_t k = 0; k < n; ++k) U[k] = U[k] / 3.0 + 2.0 * (U2[k] + dt * L[k]) / 3.0;
-  if (lim) limit_state(&x, U, W, NULL, NULL, NULL);
+  cs.time = xs.time = tn + dt;
+  if (lim) limit_state(&xs, U, W, NULL, NULL, NULL);
+  if (c->positivity && positivity_state(&xs, U, NULL)) bad = 1;
   free(U1); free(U2); free(L); free(W);
   return bad ? ORC_ERR_NONPHYSICAL : ORC_OK;
 }
@@ -1222,7 +1466,9 @@ int orc_run(const orc_config *c, double *U, double *t, double t_end, double dt_f
       dt = t_end - *t;
       last = 1;
     }
-    rc = orc_step(c, U, dt);
+    orc_config cs = *c;
+    cs.time = *t;
+    rc = orc_step(&cs, U, dt);
     if (dt_log && s < dt_log_len) dt_log[s] = dt;
     ++s;
     *t = last ? t_end : *t + dt;

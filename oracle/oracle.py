@@ -23,7 +23,7 @@ _SRC = os.path.join(_HERE, "dg_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 BURGERS, EULER = 0, 1
-PERIODIC, TRANSMISSIVE = 0, 1
+PERIODIC, TRANSMISSIVE, REFLECTIVE, INFLOW = 0, 1, 2, 3
 LIM_NONE, LIM_CSWENO, LIM_CSWENO_CHAR = 0, 1, 2
 IND_TVB, IND_ALL, IND_KXRCF = 0, 1, 3
 NEGW_SPLIT, NEGW_RAW = 0, 1
@@ -49,6 +49,12 @@ class OrcConfig(ctypes.Structure):
         ("tvb_M", ctypes.c_double),
         ("weno_eps", ctypes.c_double),
         ("cfl", ctypes.c_double),
+        ("positivity", ctypes.c_int32),
+        ("bc_beyond", ctypes.c_int32 * 4),
+        ("pad_", ctypes.c_int32),
+        ("bc_switch", (ctypes.c_double * 2) * 4),
+        ("bc_state", ((ctypes.c_double * 4) * 2) * 4),
+        ("time", ctypes.c_double),
     ]
 
 
@@ -90,6 +96,8 @@ def lib():
             "orc_basis": [ctypes.c_int, d, P(d), P(d)],
             "orc_num_threads": [],
             "orc_char_eig": [cfgp, P(d), ctypes.c_int, P(d), P(d)],
+            "orc_positivity": [cfgp, P(d), P(d)],
+            "orc_ghost": [cfgp, P(d), i32, i32, P(d)],
         }
         for name, args in sig.items():
             fn = getattr(_lib, name)
@@ -137,6 +145,14 @@ class Problem:
     tvb_M: float = 1.0
     weno_eps: float = 1e-6
     cfl: float = 0.1
+    positivity: int = 0
+    # south/north sides may switch kind along x at a + b t: bc_beyond[s] = kind
+    # beyond the switch (-1: none), bc_switch[s] = (a, b)
+    bc_beyond: tuple = (-1, -1, -1, -1)
+    bc_switch: tuple = ((0.0, 0.0),) * 4
+    # conserved inflow ghost states [side][before, beyond][var]
+    bc_state: object = None
+    time: float = 0.0
     _c: OrcConfig = field(default=None, repr=False)
 
     def __post_init__(self):
@@ -149,7 +165,21 @@ class Problem:
         c.limiter, c.indicator, c.negw_mode = self.limiter, self.indicator_mode, self.negw_mode
         c.gamma, c.x0, c.x1, c.y0, c.y1 = self.gamma, self.x0, self.x1, self.y0, self.y1
         c.tvb_M, c.weno_eps, c.cfl = self.tvb_M, self.weno_eps, self.cfl
+        c.positivity = int(self.positivity)
+        st = np.zeros((4, 2, 4)) if self.bc_state is None else np.asarray(self.bc_state, dtype=np.float64)
+        for k in range(4):
+            c.bc_beyond[k] = int(self.bc_beyond[k])
+            for a in range(2):
+                c.bc_switch[k][a] = float(self.bc_switch[k][a])
+                for v in range(4):
+                    c.bc_state[k][a][v] = float(st[k, a, v])
+        c.time = float(self.time)
         self._c = c
+
+    def at_time(self, t):
+        """The same problem with boundary data taken at time t."""
+        import dataclasses
+        return dataclasses.replace(self, time=float(t), _c=None)
 
     # -- shapes ---------------------------------------------------------
     @property
@@ -196,6 +226,22 @@ class Problem:
         R = np.zeros((nv, nv))
         self._chk(lib().orc_char_eig(ctypes.byref(self._c), _dp(w), int(direction), _dp(L), _dp(R)), "char_eig")
         return L, R
+
+    def positivity_scale(self, U):
+        """Positivity-preserving scaling of every cell.  Returns (state, theta)
+        with theta[0] / theta[1] the density / pressure factors per cell."""
+        out = np.array(U, dtype=np.float64, copy=True, order="C")
+        th = np.empty((2, self.ny, self.nx), dtype=np.float64)
+        self._chk(lib().orc_positivity(ctypes.byref(self._c), _dp(out), _dp(th)), "positivity")
+        return out, th
+
+    def ghost(self, U, i, j=0):
+        """Modes [nv][nm] of cell (i, j), i in [-1, nx], j in [-1, ny], as the
+        boundary conditions give it at the problem's time."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        out = np.zeros((self.nv, self.nm))
+        self._chk(lib().orc_ghost(ctypes.byref(self._c), _dp(U), int(i), int(j), _dp(out)), "ghost")
+        return out
 
     def indicator(self, U):
         U = np.ascontiguousarray(U, dtype=np.float64)

@@ -25,6 +25,15 @@ Workloads (names are what the problem is, with its sizes):
   t = 0.25.
 * ``riemann2d_batch256``  -- 256 such problems, side n uniform in
   [64,512], order uniform in {1,2,3}.
+* ``double_mach_960x240_q2`` -- the paper's Example 11: 2D Euler on
+  [0,4]x[0,1], a Mach 10 shock through (1/6, 0) at 60 degrees to the x-axis
+  moving right into (rho,u,v,p) = (1.4,0,0,1); behind it (8, 8.25 cos 30deg,
+  -8.25 sin 30deg, 116.5).  Inflow of the post-shock state on the west side
+  and on the south side for x < 1/6, a reflective wall on the rest of the
+  south side, transmissive east side, and on the north side the exact
+  motion of the shock (post-shock state for x < 1/6 + (1 + 20 t)/sqrt(3),
+  pre-shock beyond); positivity-preserving scaling on; t = 0.2; 960x240 and
+  1920x480 cells, Q2 and Q3.
 * ``sod``, ``lax``, ``density_wave``, ``isentropic_vortex`` -- the paper's
   Examples 7, 8, 3 and 4, used by the tests.
 """
@@ -36,7 +45,7 @@ from typing import Callable, Optional
 import numpy as np
 
 BURGERS, EULER = 0, 1
-PERIODIC, TRANSMISSIVE = 0, 1
+PERIODIC, TRANSMISSIVE, REFLECTIVE, INFLOW = 0, 1, 2, 3
 GAMMA = 1.4
 
 # quadrant order used when drawing four-state Riemann data
@@ -62,6 +71,9 @@ class Workload:
     gamma: float = GAMMA
     seed: Optional[int] = None
     extra: dict = field(default_factory=dict)
+    # boundary switches, inflow states and positivity scaling, as keyword
+    # arguments of a problem (bc_beyond, bc_switch, bc_state, positivity)
+    bc_extra: dict = field(default_factory=dict)
 
     @property
     def nv(self):
@@ -87,6 +99,7 @@ class Workload:
         d = dict(dim=self.dim, equation=self.equation, order=self.order, nx=self.nx, ny=self.ny,
                  x0=self.x0, x1=self.x1, y0=self.y0, y1=self.y1, bc=tuple(self.bc), gamma=self.gamma,
                  cfl=self.cfl)
+        d.update(self.bc_extra)
         d.update(over)
         return d
 
@@ -334,5 +347,43 @@ def by_name(name):
         "shu_osher_k4000_p3": lambda: shu_osher(),
         "burgers2d_1024_q2": lambda: burgers2d(),
         "riemann2d_2048_q2": lambda: riemann2d(),
+        "double_mach_960x240_q2": lambda: double_mach(960),
+        "double_mach_1920x480_q2": lambda: double_mach(1920),
     }
     return table[name]()
+
+
+# ---------------------------------------------------------------------------
+# double Mach reflection (the paper's Example 11)
+# ---------------------------------------------------------------------------
+
+DMR_PRE = (1.4, 0.0, 0.0, 1.0)
+DMR_POST = (8.0, 8.25 * np.cos(np.pi / 6.0), -8.25 * np.sin(np.pi / 6.0), 116.5)
+DMR_X0 = 1.0 / 6.0
+DMR_SHOCK_SPEED = 10.0
+
+
+def double_mach(nx=960, ny=None, order=2, t_end=0.2, cfl=None):
+    ny = ny or nx // 4
+    cfl = cfl if cfl is not None else (0.05 if order == 3 else 0.1)
+    s3 = np.sqrt(3.0)
+
+    def ic(X, Y):
+        behind = X < DMR_X0 + Y / s3
+        prim = [np.where(behind, a, b) for a, b in zip(DMR_POST, DMR_PRE)]
+        return euler2d_conserved(*prim)
+
+    post = [float(c) for c in euler2d_conserved(*DMR_POST)]
+    pre = [float(c) for c in euler2d_conserved(*DMR_PRE)]
+    state = np.zeros((4, 2, 4))
+    state[0, 0] = post  # west: inflow
+    state[2, 0] = post  # south, x < 1/6: inflow
+    state[3, 0] = post  # north, behind the shock
+    state[3, 1] = pre   # north, ahead of it
+    # the shock meets y = 1 at 1/6 + (1 + 20 t)/sqrt(3): normal speed 10 over sin 60deg
+    extra = dict(bc_beyond=(-1, -1, REFLECTIVE, INFLOW),
+                 bc_switch=((0.0, 0.0), (0.0, 0.0), (DMR_X0, 0.0),
+                            (DMR_X0 + 1.0 / s3, DMR_SHOCK_SPEED / np.sin(np.pi / 3.0))),
+                 bc_state=state, positivity=1)
+    return Workload(f"double_mach_{nx}x{ny}_q{order}", 2, EULER, order, nx, ny, 0.0, 4.0, 0.0, 1.0,
+                    (INFLOW, TRANSMISSIVE, INFLOW, INFLOW), cfl, t_end, ic, bc_extra=extra)

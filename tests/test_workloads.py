@@ -23,3 +23,49 @@ def test_batch_composition_is_seeded():
     assert [(w.nx, w.order, w.seed) for w in a] == [(w.nx, w.order, w.seed) for w in b]
     assert all(64 <= w.nx <= 512 and w.nx == w.ny and w.order in (1, 2, 3) for w in a)
     assert len({w.order for w in W.riemann2d_batch(count=64)}) == 3
+
+
+def test_double_mach_states_satisfy_rankine_hugoniot():
+    """The post-shock state is the one a Mach 10 shock moving at speed 10
+    along its normal (cos -30deg, sin -30deg) leaves behind in (1.4, 0, 0, 1):
+    mass, normal and tangential momentum and energy fluxes balance in the
+    shock frame, exactly for these rounded values."""
+    g = W.GAMMA
+    n = np.array([np.cos(-np.pi / 6.0), np.sin(-np.pi / 6.0)])
+    s = W.DMR_SHOCK_SPEED
+
+    def fluxes(prim):
+        rho, u, v, p = prim
+        vel = np.array([u, v])
+        un = vel @ n
+        E = p / (g - 1.0) + 0.5 * rho * (vel @ vel)
+        rel = un - s
+        return np.array([rho * rel, rho * un * rel + p, rho * (vel @ np.array([-n[1], n[0]])) * rel,
+                         E * rel + p * un])
+
+    np.testing.assert_allclose(fluxes(W.DMR_POST), fluxes(W.DMR_PRE), rtol=0, atol=1e-12)
+    # the pre-shock sound speed is 1, so the shock Mach number is the speed
+    assert np.sqrt(g * W.DMR_PRE[3] / W.DMR_PRE[0]) == 1.0
+
+
+def test_double_mach_boundary_geometry():
+    wl = W.double_mach(960)
+    assert (wl.nx, wl.ny, wl.x1, wl.y1, wl.t_end) == (960, 240, 4.0, 1.0, 0.2)
+    n = np.array([np.cos(-np.pi / 6.0), np.sin(-np.pi / 6.0)])
+    x0 = np.array([W.DMR_X0, 0.0])
+    # the initial shock line passes through (1/6, 0) at 60 degrees
+    for y in (0.0, 0.5, 1.0):
+        x = W.DMR_X0 + y / np.sqrt(3.0)
+        assert abs(n @ (np.array([x, y]) - x0)) < 1e-15
+    # the north switch point lies on the shock line at every time
+    a, b = wl.bc_extra["bc_switch"][3]
+    for t in (0.0, 0.1, 0.2):
+        assert abs(n @ (np.array([a + b * t, 1.0]) - x0) - W.DMR_SHOCK_SPEED * t) < 1e-13
+    # the south side is inflow up to the shock foot, a wall beyond it
+    assert wl.bc_extra["bc_switch"][2] == (W.DMR_X0, 0.0)
+    assert wl.bc[2] == W.INFLOW and wl.bc_extra["bc_beyond"][2] == W.REFLECTIVE
+    # initial data: post-shock state behind the line, pre-shock ahead
+    X = np.array([[0.1, 1.0]])
+    Y = np.array([[0.5, 0.5]])
+    rho = wl.ic(X, Y)[0]
+    assert rho[0, 0] == W.DMR_POST[0] and rho[0, 1] == W.DMR_PRE[0]
