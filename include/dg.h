@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define DG_ABI_VERSION 1
+#define DG_ABI_VERSION 2
 
 enum {
   DG_OK = 0,
@@ -56,7 +56,7 @@ enum {
 };
 
 enum { DG_EQ_BURGERS = 0, DG_EQ_EULER = 1 };
-enum { DG_BC_PERIODIC = 0, DG_BC_TRANSMISSIVE = 1 };
+enum { DG_BC_PERIODIC = 0, DG_BC_TRANSMISSIVE = 1, DG_BC_REFLECTIVE = 2, DG_BC_INFLOW = 3 };
 enum { DG_LIM_NONE = 0, DG_LIM_CSWENO = 1, DG_LIM_CSWENO_CHAR = 2 };
 enum { DG_IND_TVB = 0, DG_IND_ALL = 1, DG_IND_LEARNED = 2, DG_IND_KXRCF = 3 };
 enum { DG_NEGW_SPLIT = 0, DG_NEGW_RAW = 1 };
@@ -67,9 +67,16 @@ typedef struct dg_config {
   int32_t equation;    /* DG_EQ_BURGERS or DG_EQ_EULER */
   int32_t order;       /* N in 1..3: P^N in 1D, Q^N in 2D */
   int32_t nx, ny;      /* cells per direction; ny must be 1 in 1D */
-  int32_t bc[4];       /* west, east, south, north: DG_BC_PERIODIC or DG_BC_TRANSMISSIVE
-                          (transmissive = even reflection of the adjacent cell;
-                          periodic sides must come in pairs) */
+  int32_t bc[4];       /* west, east, south, north; the ghost cell beyond a side is:
+                          DG_BC_PERIODIC   the periodic image (sides come in pairs);
+                          DG_BC_TRANSMISSIVE the even reflection of the adjacent cell
+                                           (odd modes in the normal direction change sign);
+                          DG_BC_REFLECTIVE that reflection with the normal momentum
+                                           negated as well (a wall; Euler only);
+                          DG_BC_INFLOW     the constant state bc_state[side][0].
+                          A corner ghost beyond an inflow west/east side is that
+                          inflow state; otherwise the south/north rule applies to the
+                          column the west/east rule mapped to. */
   int32_t limiter;     /* DG_LIM_NONE, DG_LIM_CSWENO (componentwise), or DG_LIM_CSWENO_CHAR
                           (Euler: each WENO sweep in the local characteristic fields of its
                           direction, eigenvectors of the flux Jacobian at the troubled
@@ -84,12 +91,32 @@ typedef struct dg_config {
                           variables u or density and energy; margin min(|I-1|, |v_x|, |v_y|)) */
   int32_t negw_mode;   /* P3 points with a negative linear weight: DG_NEGW_SPLIT
                           (positive/negative split, theta = 3) or DG_NEGW_RAW */
-  int32_t reserved;    /* must be 0 */
+  int32_t positivity;  /* 1: positivity-preserving scaling of Zhang and Shu after the
+                          limiter of every stage (Example 11 adds it; Euler only): per
+                          cell the density, then the whole state, scaled towards the
+                          cell mean by the largest factors that keep density and
+                          pressure >= eps = min(1e-10, mean density, mean pressure) at
+                          the tensor points of the face Gauss rule with the 3-point
+                          (Q1: 2-point) Gauss-Lobatto rule in both orders and at the
+                          volume Gauss points.  0: off */
   double gamma;        /* ratio of specific heats (Euler), 1.4 */
   double x0, x1, y0, y1;
   double tvb_M;        /* TVB constant M; threshold M h^2 per direction */
   double weno_eps;     /* epsilon of the nonlinear weights (Section 3, Step 5), 1e-6 */
   double cfl;          /* CFL number used when dg_step is given dt <= 0 */
+  /* A south or north side may switch kind along x: kind bc[s] for ghost
+   * cells whose centre x < bc_switch[s][0] + bc_switch[s][1] t, kind
+   * bc_beyond[s] (DG_BC_TRANSMISSIVE, DG_BC_REFLECTIVE or DG_BC_INFLOW with
+   * state bc_state[s][1]) from there on; -1: no switch.  West and east sides
+   * never switch (-1).  t is the time the data of a stage stand for: dg_step
+   * takes t^n for the first residual, t^n + dt for the limiter after the
+   * first stage and the second residual, t^n + dt/2 for the limiter after the
+   * second stage and the third residual, t^n + dt after the last stage;
+   * dg_residual and dg_limit take the time of dg_set_time (0 initially). */
+  int32_t bc_beyond[4];
+  int32_t pad;              /* must be 0 */
+  double bc_switch[4][2];
+  double bc_state[4][2][4]; /* conserved inflow states [side][before, beyond][variable] */
 } dg_config;
 
 typedef struct dg_problem dg_problem;
@@ -139,7 +166,8 @@ int dg_residual(dg_problem *p, const double *state, double *out);
  * indicator and, for DG_IND_TVB, a lower bound on the change of the tested
  * quantities that would alter the decision; either may be NULL.
  * flags_override (device uint8[ny][nx], non-zero = troubled) replaces the
- * indicator when not NULL.  n_troubled (host) receives the count; may be NULL. */
+ * indicator when not NULL.  n_troubled (host) receives the count; may be NULL.
+ * With positivity on, every cell is then scaled as dg_config.positivity says. */
 int dg_limit(dg_problem *p, double *state, uint8_t *flags, double *margin, const uint8_t *flags_override,
              int32_t *n_troubled);
 
@@ -158,6 +186,10 @@ int dg_cfl_dt(dg_problem *p, const double *state, double *dt);
  * graph per state pointer and replayed. */
 int dg_step(dg_problem *p, double *state, double *t, double t_end, double dt, int32_t max_steps,
             int32_t *steps_taken);
+
+/* Time at which dg_residual and dg_limit evaluate time-dependent boundary
+ * data (switching sides).  Enqueued on the problem's stream. */
+int dg_set_time(dg_problem *p, double t);
 
 /* Status word of the problem: DG_OK or DG_ERR_NONPHYSICAL (sticky until read;
  * reading clears it).  Synchronises the stream. */

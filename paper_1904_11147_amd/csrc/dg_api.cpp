@@ -48,15 +48,42 @@ int num_modes(const dg_config *c) { return c->dim == 1 ? c->order + 1 : (c->orde
 
 int validate_config(const dg_config *c) {
   if (!c) return DG_ERR_INVALID_ARG;
-  if (c->abi_version != DG_ABI_VERSION || c->reserved != 0) return DG_ERR_INVALID_ARG;
+  if (c->abi_version != DG_ABI_VERSION || c->pad != 0) return DG_ERR_INVALID_ARG;
   if (c->dim != 1 && c->dim != 2) return DG_ERR_UNSUPPORTED;
   if (c->equation != DG_EQ_BURGERS && c->equation != DG_EQ_EULER) return DG_ERR_UNSUPPORTED;
   if (c->order < 1 || c->order > dg::kMaxN) return DG_ERR_UNSUPPORTED;
   if (c->nx < 1 || c->ny < 1 || (c->dim == 1 && c->ny != 1)) return DG_ERR_INVALID_ARG;
-  for (int k = 0; k < 4; ++k)
-    if (c->bc[k] != DG_BC_PERIODIC && c->bc[k] != DG_BC_TRANSMISSIVE) return DG_ERR_INVALID_ARG;
+  const int sides = c->dim == 1 ? 2 : 4;
+  for (int k = 0; k < sides; ++k) {
+    const int kind = c->bc[k], beyond = c->bc_beyond[k];
+    if (kind < DG_BC_PERIODIC || kind > DG_BC_INFLOW) return DG_ERR_INVALID_ARG;
+    if (beyond != -1) {
+      if (k < 2 || kind == DG_BC_PERIODIC || beyond < DG_BC_TRANSMISSIVE || beyond > DG_BC_INFLOW)
+        return DG_ERR_INVALID_ARG;
+      if (!std::isfinite(c->bc_switch[k][0]) || !std::isfinite(c->bc_switch[k][1])) return DG_ERR_INVALID_ARG;
+    }
+    for (int part = 0; part < 2; ++part) {
+      const int kk = part == 0 ? kind : beyond;
+      if (kk == DG_BC_REFLECTIVE && c->equation != DG_EQ_EULER) return DG_ERR_UNSUPPORTED;
+      if (kk == DG_BC_INFLOW) {  // an admissible state
+        const double *w = c->bc_state[k][part];
+        const int nv = num_vars(c);
+        for (int v = 0; v < nv; ++v)
+          if (!std::isfinite(w[v])) return DG_ERR_INVALID_ARG;
+        if (c->equation == DG_EQ_EULER) {
+          double ke = 0.0;
+          for (int d = 1; d <= c->dim; ++d) ke += w[d] * w[d];
+          if (!(w[0] > 0.0) || !(w[nv - 1] - 0.5 * ke / w[0] > 0.0)) return DG_ERR_INVALID_ARG;
+        }
+      }
+    }
+  }
+  for (int k = sides; k < 4; ++k)
+    if (c->bc_beyond[k] != -1) return DG_ERR_INVALID_ARG;
   if ((c->bc[0] == DG_BC_PERIODIC) != (c->bc[1] == DG_BC_PERIODIC)) return DG_ERR_INVALID_ARG;
   if (c->dim == 2 && (c->bc[2] == DG_BC_PERIODIC) != (c->bc[3] == DG_BC_PERIODIC)) return DG_ERR_INVALID_ARG;
+  if (c->positivity != 0 && c->positivity != 1) return DG_ERR_INVALID_ARG;
+  if (c->positivity && c->equation != DG_EQ_EULER) return DG_ERR_UNSUPPORTED;
   if (c->limiter != DG_LIM_NONE && c->limiter != DG_LIM_CSWENO && c->limiter != DG_LIM_CSWENO_CHAR)
     return DG_ERR_INVALID_ARG;
   if (c->indicator != DG_IND_TVB && c->indicator != DG_IND_ALL && c->indicator != DG_IND_LEARNED &&
@@ -110,6 +137,17 @@ void fill_geometry(const dg_config *cfg, Geometry *g) {
   g->pad = 0;
   const double rad = cfg->dim == 1 ? 0.5 * g->hx : 0.5 * std::sqrt(g->hx * g->hx + g->hy * g->hy);
   g->kx_scale = 1.0 / std::pow(rad, 0.5 * (cfg->order + 1));
+  g->x0 = cfg->x0;
+  // an inflow ghost holds only the lowest mode: mean / psi_0^dim, psi_0 = 1/sqrt(2)
+  const double p0 = std::sqrt(0.5), k0 = cfg->dim == 1 ? p0 : p0 * p0;
+  for (int k = 0; k < 4; ++k) {
+    g->bcb[k] = cfg->dim == 1 && k >= 2 ? -1 : cfg->bc_beyond[k];
+    g->bsw[k][0] = cfg->bc_switch[k][0];
+    g->bsw[k][1] = cfg->bc_switch[k][1];
+    for (int part = 0; part < 2; ++part)
+      for (int v = 0; v < 4; ++v) g->bst[2 * k + part][v] = cfg->bc_state[k][part][v] / k0;
+  }
+  g->tb = nullptr;
 }
 
 }  // namespace dg
@@ -189,17 +227,28 @@ void harvest(dg_problem *p) {
 }
 
 // One SSP-RK3 step with the limiter after every stage (enqueue only).
+// Boundary data of a stage stand for the time its input approximates: t^n
+// for the first residual (decide_dt sets it), t^n + dt for the limiter after
+// stage 1 and the second residual, t^n + dt/2 for the limiter after stage 2
+// and the third residual, t^n + dt after stage 3.
 int enqueue_step(dg_problem *p, double *state, bool cfl_mode) {
   LaunchCtx &c = p->ctx;
-  const bool lim = p->cfg.limiter != DG_LIM_NONE;
+  const bool lim = p->cfg.limiter != DG_LIM_NONE, pos = p->cfg.positivity != 0, timed = c.timed_bc != 0;
   int rc;
+  auto limit = [&](double *u, double *side, int slot, double frac) {
+    int r = DG_OK;
+    if (timed) r = dg::launch_set_tb(c, frac, 0.0);
+    if (!r && lim) { Timed t(p, DG_PROF_LIMITER); r = dg::launch_limit(c, u, side, slot, c.flags, nullptr, nullptr); }
+    if (!r && pos) { Timed t(p, DG_PROF_LIMITER); r = dg::launch_positivity(c, u, 1); }
+    return r;
+  };
   { Timed t(p, DG_PROF_DT); rc = dg::launch_dt_finalize(c); }
   if (!rc) { Timed t(p, DG_PROF_STAGE1); rc = dg::launch_stage(c, 1, state, nullptr, c.bufA, false); }
-  if (!rc && lim) { Timed t(p, DG_PROF_LIMITER); rc = dg::launch_limit(c, c.bufA, c.bufB, 0, c.flags, nullptr, nullptr); }
+  if (!rc) rc = limit(c.bufA, c.bufB, 0, 1.0);
   if (!rc) { Timed t(p, DG_PROF_STAGE23); rc = dg::launch_stage(c, 2, c.bufA, state, c.bufB, false); }
-  if (!rc && lim) { Timed t(p, DG_PROF_LIMITER); rc = dg::launch_limit(c, c.bufB, c.bufA, 1, c.flags, nullptr, nullptr); }
+  if (!rc) rc = limit(c.bufB, c.bufA, 1, 0.5);
   if (!rc) { Timed t(p, DG_PROF_STAGE23); rc = dg::launch_stage(c, 3, c.bufB, state, state, cfl_mode); }
-  if (!rc && lim) { Timed t(p, DG_PROF_LIMITER); rc = dg::launch_limit(c, state, c.bufA, 2, c.flags, nullptr, nullptr); }
+  if (!rc) rc = limit(state, c.bufA, 2, 1.0);
   return rc;
 }
 
@@ -284,6 +333,11 @@ int dg_init(const dg_config *cfg, void *workspace, size_t workspace_bytes, void 
   c.cfl = cfg->cfl;
   c.limiter = cfg->limiter;
   c.indicator = cfg->indicator;
+  c.positivity = cfg->positivity;
+  c.timed_bc = 0;
+  for (int k = 2; k < 4; ++k)
+    if (c.geo.bcb[k] >= 0 && c.geo.bsw[k][1] != 0.0) c.timed_bc = 1;
+  c.geo.tb = &c.sc->tb;
   c.grid_cap = 2048;
   c.use_march = 1;
   c.rows = 0;
@@ -346,11 +400,17 @@ int dg_limit(dg_problem *p, double *state, uint8_t *flags, double *margin, const
   if (rc) return rc;
   const LaunchCtx &c = p->ctx;  // with DG_LIM_NONE only the indicator runs
   rc = dg::launch_limit(c, state, c.bufA, 3, flags, margin, flags_override);
+  if (!rc && p->cfg.positivity) rc = dg::launch_positivity(c, state, 0);
   if (rc) return rc;
   DevScalars h;
   rc = sync_status(p, &h);
   if (n_troubled) *n_troubled = h.count[3];
   return rc;
+}
+
+int dg_set_time(dg_problem *p, double t) {
+  if (!p || !std::isfinite(t)) return DG_ERR_INVALID_ARG;
+  return dg::launch_set_tb(p->ctx, -1.0, t);
 }
 
 int dg_cfl_dt(dg_problem *p, const double *state, double *dt) {

@@ -42,6 +42,8 @@ int validate_batch(const dg_config *cfgs, int32_t n) {
     if (rc) return rc;
     if (cfgs[i].dim != 2 || cfgs[i].equation != DG_EQ_EULER) return DG_ERR_UNSUPPORTED;
     if (cfgs[i].limiter != cfgs[0].limiter || cfgs[i].indicator != cfgs[0].indicator) return DG_ERR_INVALID_ARG;
+    // per-instance boundary switches and positivity scaling run on single meshes only
+    if (cfgs[i].positivity || cfgs[i].bc_beyond[2] >= 0 || cfgs[i].bc_beyond[3] >= 0) return DG_ERR_UNSUPPORTED;
     cells += (long long)cfgs[i].nx * cfgs[i].ny;
   }
   if (cells > (1ll << 31) - 1) return DG_ERR_UNSUPPORTED;

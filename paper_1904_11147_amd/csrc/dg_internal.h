@@ -54,6 +54,8 @@ struct DevScalars {
   int32_t count[4];  // troubled-cell counts: stage 1..3, standalone limiter
   unsigned long long troubled_total;  // all troubled cells flagged since the last reset
   int32_t pad[4];
+  double tn;  // start time of the current step
+  double tb;  // time of the boundary data of the kernels running now
 };
 
 struct Geometry {
@@ -67,6 +69,11 @@ struct Geometry {
   int32_t negw_raw;
   int32_t pad;
   double kx_scale;  // KXRCF: 1 / h^((N+1)/2), h the cell's circumscribed radius
+  double x0;        // west end of the mesh
+  int32_t bcb[4];   // south/north: kind beyond the switch point, -1 none
+  double bsw[4][2]; // switch at bsw[s][0] + bsw[s][1] * t (x along the side)
+  double bst[8][4]; // inflow ghost modes: [2 side + part][variable], the lowest mode only
+  const double *tb; // device: time of the boundary data (DevScalars::tb)
 };
 
 struct Kernels;  // launch helpers live in the kernel TU
@@ -83,6 +90,8 @@ struct LaunchCtx {
   int32_t *list;         // device [cells]
   double cfl;
   int limiter, indicator;
+  int positivity;        // Zhang-Shu scaling after every limiter pass
+  int timed_bc;          // a side switches at a moving point: keep DevScalars::tb current
   int grid_cap;          // blocks for list-driven kernels
   int use_march;         // 2D: marching stage kernel where registers allow
   int rows;              // 2D marching kernels: rows per tile (0: a rule from the mesh size)
@@ -164,6 +173,11 @@ int launch_limit(const LaunchCtx &c, double *u, double *side, int count_slot, ui
                  const uint8_t *flags_override);
 int launch_speed(const LaunchCtx &c, const double *u);
 int launch_dt_finalize(const LaunchCtx &c);
+// Positivity scaling of every cell of u (Euler); check_done: skip once the
+// step loop is done (calls inside dg_step).
+int launch_positivity(const LaunchCtx &c, double *u, int check_done);
+// DevScalars::tb = tn + frac * dt (frac < 0: = value).
+int launch_set_tb(const LaunchCtx &c, double frac, double value);
 int launch_reset_counts(const LaunchCtx &c);
 int launch_project(const LaunchCtx &c, const double *pv, int j0, int nrows, double *u);
 int launch_mlp_features(const LaunchCtx &c, const double *u, float *f32, uint16_t *bf, int KP);

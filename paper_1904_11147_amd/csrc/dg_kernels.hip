@@ -114,42 +114,80 @@ __device__ inline void llf(const double *a, const double *b, double *F, double g
 }
 
 // ---------------------------------------------------------------------------
-// Cell access with boundary conditions: periodic wrap, or an even reflection
-// of the adjacent cell (odd modes in the normal direction change sign).
+// Cell access with boundary conditions.  Beyond a side the ghost cell is the
+// periodic image, the even reflection of the adjacent cell (odd modes in the
+// normal direction change sign), that reflection with the normal momentum
+// negated (wall), or a constant inflow state.  The west/east rule is applied
+// first; a corner beyond an inflow west/east side is that inflow state.
+// South/north sides may switch kind at x = a + b t (t: DevScalars::tb).
 // ---------------------------------------------------------------------------
 struct CellIdx {
-  long idx;
-  bool fx, fy;
+  long idx;      // a cell inside the mesh (also for inflow ghosts, so loads stay in bounds)
+  bool fx, fy;   // odd modes in x / y change sign
+  uint8_t neg;   // bit v: variable v changes sign
+  int8_t gs;     // >= 0: inflow ghost with lowest mode Geometry::bst[gs]
 };
 
 __device__ inline CellIdx map_cell(const Geometry &g, int i, int j) {
   CellIdx c;
   c.fx = c.fy = false;
-  if (i < 0) {
-    if (g.bc[0] == DG_BC_PERIODIC) i += g.nx; else { i = 0; c.fx = true; }
-  } else if (i >= g.nx) {
-    if (g.bc[1] == DG_BC_PERIODIC) i -= g.nx; else { i = g.nx - 1; c.fx = true; }
+  c.neg = 0;
+  c.gs = -1;
+  if (i < 0 || i >= g.nx) {
+    const int s = i < 0 ? 0 : 1, k = g.bc[s];
+    if (k == DG_BC_PERIODIC) {
+      i += s ? -g.nx : g.nx;
+    } else {
+      i = s ? g.nx - 1 : 0;
+      c.fx = true;
+      if (k == DG_BC_REFLECTIVE) c.neg = 2;
+      if (k == DG_BC_INFLOW) c.gs = (int8_t)(2 * s);
+    }
   }
-  if (j < 0) {
-    if (g.bc[2] == DG_BC_PERIODIC) j += g.ny; else { j = 0; c.fy = true; }
-  } else if (j >= g.ny) {
-    if (g.bc[3] == DG_BC_PERIODIC) j -= g.ny; else { j = g.ny - 1; c.fy = true; }
+  if (j < 0 || j >= g.ny) {
+    const int s = j < 0 ? 2 : 3;
+    int k = g.bc[s], part = 0;
+    if (g.bcb[s] >= 0) {  // rounded like a plain product and sum, without contraction
+      const double xc = __dadd_rn(g.x0, __dmul_rn(i + 0.5, g.hx));
+      if (!(xc < __dadd_rn(g.bsw[s][0], __dmul_rn(g.bsw[s][1], *g.tb)))) {
+        part = 1;
+        k = g.bcb[s];
+      }
+    }
+    if (k == DG_BC_PERIODIC) {
+      j += s == 3 ? -g.ny : g.ny;
+    } else {
+      j = s == 3 ? g.ny - 1 : 0;
+      if (c.gs < 0) {
+        c.fy = true;
+        if (k == DG_BC_REFLECTIVE) c.neg |= 4;
+        if (k == DG_BC_INFLOW) c.gs = (int8_t)(2 * s + part);
+      }
+    }
   }
   c.idx = (long)j * g.nx + i;
   return c;
 }
 
+// Mode q (= m + NP n) of variable v of the cell or ghost c.
+template <int NP, int NM, int DIM>
+__device__ __forceinline__ double cell_mode(const double *__restrict__ u, long plane, const Geometry &g,
+                                            const CellIdx &c, int v, int q) {
+  const int m = q % NP, n = q / NP;
+  double s = u[(long)(v * NM + q) * plane + c.idx];
+  const bool flip = ((c.fx && (m & 1)) != (DIM == 2 && c.fy && (n & 1))) != (((c.neg >> v) & 1) != 0);
+  s = flip ? -s : s;
+  if (c.gs >= 0) s = q == 0 ? g.bst[c.gs][v] : 0.0;
+  return s;
+}
+
 template <int NP, int NM, int NV, int DIM>
-__device__ inline void load_cell(const double *__restrict__ u, long plane, const CellIdx &c, double C[NV][NM]) {
+__device__ inline void load_cell(const double *__restrict__ u, long plane, const Geometry &g, const CellIdx &c,
+                                 double C[NV][NM]) {
 #pragma unroll
   for (int v = 0; v < NV; ++v)
 #pragma unroll
-    for (int q = 0; q < NM; ++q) {
-      int m = q % NP, n = q / NP;
-      double s = u[(long)(v * NM + q) * plane + c.idx];
-      bool flip = (c.fx && (m & 1)) != (DIM == 2 && c.fy && (n & 1));
-      C[v][q] = flip ? -s : s;
-    }
+    for (int q = 0; q < NM; ++q) C[v][q] = cell_mode<NP, NM, DIM>(u, plane, g, c, v, q);
 }
 
 // ---------------------------------------------------------------------------
@@ -178,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_1d(StageArgs a) {
   double spd = 0.0;
   if (i < g.nx) {
     double C[NV][NP], Nb[NV][NP], L[NV][NP];
-    load_cell<NP, NP, NV, 1>(a.u, plane, map_cell(g, i, 0), C);
+    load_cell<NP, NP, NV, 1>(a.u, plane, g, map_cell(g, i, 0), C);
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -204,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_1d(StageArgs a) {
     }
     // faces
     double a_[NV], b_[NV], F[NV];
-    load_cell<NP, NP, NV, 1>(a.u, plane, map_cell(g, i + 1, 0), Nb);
+    load_cell<NP, NP, NV, 1>(a.u, plane, g, map_cell(g, i + 1, 0), Nb);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       double s0 = 0.0, s1 = 0.0;
@@ -221,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_1d(StageArgs a) {
     for (int v = 0; v < NV; ++v)
 #pragma unroll
       for (int n = 0; n < NP; ++n) L[v][n] -= g.rhx * F[v] * T.bp[n];
-    load_cell<NP, NP, NV, 1>(a.u, plane, map_cell(g, i - 1, 0), Nb);
+    load_cell<NP, NP, NV, 1>(a.u, plane, g, map_cell(g, i - 1, 0), Nb);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       double s0 = 0.0, s1 = 0.0;
@@ -278,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_2d(StageArgs a) {
   double spx = 0.0, spy = 0.0;
   if (i < g.nx && j < g.ny) {
     double C[NV][NM], L[NV][NM];
-    load_cell<NP, NM, NV, 2>(a.u, plane, map_cell(g, i, j), C);
+    load_cell<NP, NM, NV, 2>(a.u, plane, g, map_cell(g, i, j), C);
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -340,7 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_2d(StageArgs a) {
       const int di = face == 0 ? 1 : (face == 1 ? -1 : 0);
       const int dj = face == 2 ? 1 : (face == 3 ? -1 : 0);
       double Nb[NV][NM];
-      load_cell<NP, NM, NV, 2>(a.u, plane, map_cell(g, i + di, j + dj), Nb);
+      load_cell<NP, NM, NV, 2>(a.u, plane, g, map_cell(g, i + di, j + dj), Nb);
       // own and neighbour 1D trace coefficients along the face: c[v][k]
       double co[NV][NP], cn[NV][NP];
       const double *bo = (face == 0 || face == 2) ? T.bp : T.bm;  // own side
@@ -553,17 +591,13 @@ __device__ inline void lift(const OrderTables &T, const double (&F)[NV][N + 1], 
 // variable at a time so that no full cell state stays live.
 template <int N, int NV>
 __device__ inline void south_trace_streamed(const OrderTables &T, const double *__restrict__ u, long plane,
-                                            const CellIdx &c, double (&ts)[NV][N + 1]) {
+                                            const Geometry &g, const CellIdx &c, double (&ts)[NV][N + 1]) {
   constexpr int NP = N + 1, NM = NP * NP;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     double m9[NM];
 #pragma unroll
-    for (int q = 0; q < NM; ++q) {
-      const int m = q % NP, n = q / NP;
-      const double s = u[(long)(v * NM + q) * plane + c.idx];
-      m9[q] = ((c.fx && (m & 1)) != (c.fy && (n & 1))) ? -s : s;
-    }
+    for (int q = 0; q < NM; ++q) m9[q] = cell_mode<NP, NM, 2>(u, plane, g, c, v, q);
 #pragma unroll
     for (int e = 0; e < NP; ++e) {
       double acc = 0.0;
@@ -601,9 +635,9 @@ __global__ __launch_bounds__(64) void k_stage_2d_march(StageArgs a, int rows_per
   double FS[NV][NP];
   {
     double Ub[NV][NM], tn[NV][NP], ts[NV][NP];
-    load_cell<NP, NM, NV, 2>(a.u, plane, map_cell(g, col, j0 - 1), Ub);
+    load_cell<NP, NM, NV, 2>(a.u, plane, g, map_cell(g, col, j0 - 1), Ub);
     trace_y<N, NV, +1>(T, Ub, tn);
-    south_trace_streamed<N, NV>(T, a.u, plane, map_cell(g, col, j0), ts);
+    south_trace_streamed<N, NV>(T, a.u, plane, g, map_cell(g, col, j0), ts);
     face_flux<EQ, N, NV, 1>(tn, ts, FS, g.gamma, bad);
   }
   for (int j = j0; j < j1; ++j) {
@@ -618,7 +652,7 @@ __global__ __launch_bounds__(64) void k_stage_2d_march(StageArgs a, int rows_per
     double tn[NV][NP];
     {
       double U[NV][NM];
-      load_cell<NP, NM, NV, 2>(a.u, plane, me, U);
+      load_cell<NP, NM, NV, 2>(a.u, plane, g, me, U);
 #pragma unroll
       for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -693,7 +727,7 @@ __global__ __launch_bounds__(64) void k_stage_2d_march(StageArgs a, int rows_per
     // row's north trace and the next row's south trace
     {
       double ts[NV][NP], FN[NV][NP];
-      south_trace_streamed<N, NV>(T, a.u, plane, map_cell(g, col, j + 1), ts);
+      south_trace_streamed<N, NV>(T, a.u, plane, g, map_cell(g, col, j + 1), ts);
       face_flux<EQ, N, NV, 1>(tn, ts, FN, g.gamma, bad);
       lift<N, NV, 1, -1>(T, FS, g.rhy, L);
       lift<N, NV, 1, +1>(T, FN, g.rhy, L);
@@ -895,6 +929,18 @@ __device__ __forceinline__ void euler_tile(const StageArgs &a, int bx, int by, i
         }
         U[k][q] = s;
       }
+    if (c.neg != 0 || c.gs >= 0) {  // wall and inflow ghosts: boundary cells only
+#pragma unroll
+      for (int k = 0; k < VPL; ++k) {
+        const int v = v0 + k;
+#pragma unroll
+        for (int q = 0; q < NM; ++q) {
+          double s = ((c.neg >> v) & 1) ? -U[k][q] : U[k][q];
+          if (c.gs >= 0) s = q == 0 ? g.bst[c.gs][v] : 0.0;
+          U[k][q] = s;
+        }
+      }
+    }
   };
   auto rd = [&](int k, int q) -> double { return row[(k * NM + q) * 64 + lane]; };
   // trace of the two own variables on a face (dirf 0: x-face, 1: y-face)
@@ -1220,6 +1266,8 @@ __device__ inline void decide_dt(DevScalars *sc, int dim, double cfl, double hx,
     last = true;
   }
   sc->dt = dt;
+  sc->tn = sc->t;
+  sc->tb = sc->t;
   sc->t = last ? sc->t_end : sc->t + dt;
   sc->steps += 1;
   sc->smax[0] = 0ull;
@@ -1231,6 +1279,14 @@ __global__ void k_dt_finalize(DevScalars *sc, int dim, double cfl, double hx, do
   if (threadIdx.x == 0) decide_dt(sc, dim, cfl, hx, hy);
 }
 
+// Time of the boundary data: tn + frac dt during a step (frac >= 0), or the
+// given value (frac < 0).  Nothing once the run is done.
+__global__ void k_set_tb(DevScalars *sc, double frac, double value) {
+  if (threadIdx.x != 0) return;
+  if (frac < 0.0) sc->tb = value;
+  else if (!sc->done) sc->tb = sc->tn + frac * sc->dt;
+}
+
 __global__ void k_reset(DevScalars *sc, int what) {
   if (threadIdx.x != 0) return;
   if (what == 0) {  // standalone limiter count
@@ -1239,6 +1295,140 @@ __global__ void k_reset(DevScalars *sc, int what) {
     sc->smax[0] = 0ull;
     sc->smax[1] = 0ull;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Positivity-preserving scaling of Zhang and Shu on every cell (Euler), one
+// thread per cell.  Points: the face Gauss rule G (the residual's N+1 nodes)
+// crossed with the Gauss-Lobatto rule S (end points, and the centre for
+// N >= 2) in both orders, and the volume points G x G; 1D: S and G.  Density
+// is scaled towards the mean by theta1 so that it is >= eps at every point,
+// then the whole state by theta2 so that the pressure is, eps = min(1e-10,
+// mean density, mean pressure).  A cell that needs neither keeps its modes
+// untouched; a cell whose mean is not admissible sets the status word.
+// ---------------------------------------------------------------------------
+constexpr double kPosEps = 1e-10;
+
+template <int DIM>
+__device__ inline double pos_pressure(const double *w, double gam) {
+  double ke = w[1] * w[1];
+  if (DIM == 2) ke += w[2] * w[2];
+  return (gam - 1.0) * (w[DIM + 1] - 0.5 * ke / w[0]);
+}
+
+// The t in [0,1] where the pressure along wb + t (wq - wb) reaches eps, for
+// p(wb) >= eps > p(wq): the decreasing root of rho (p - eps) / (gamma - 1),
+// a quadratic A t^2 + B t + C, in the form without cancellation.
+template <int DIM>
+__device__ inline double pos_root(const double *wb, const double *wq, double eps, double gam) {
+  constexpr int E = DIM + 1;
+  const double ee = eps / (gam - 1.0);
+  const double dr = wq[0] - wb[0], dE = wq[E] - wb[E];
+  double mm = 0.0, md = 0.0, dd = 0.0;
+#pragma unroll
+  for (int d = 1; d <= DIM; ++d) {
+    const double dm = wq[d] - wb[d];
+    mm += wb[d] * wb[d];
+    md += wb[d] * dm;
+    dd += dm * dm;
+  }
+  const double A = dE * dr - 0.5 * dd;
+  const double B = wb[E] * dr + wb[0] * dE - md - ee * dr;
+  const double C = wb[E] * wb[0] - 0.5 * mm - ee * wb[0];
+  if (!(C > 0.0)) return 0.0;
+  double D = B * B - 4.0 * A * C;
+  if (D < 0.0) D = 0.0;
+  const double t = B <= 0.0 ? 2.0 * C / (sqrt(D) - B) : (-B - sqrt(D)) / (2.0 * A);
+  return fmin(fmax(t, 0.0), 1.0);
+}
+
+template <int N, int DIM>
+__global__ __launch_bounds__(kBlock) void k_positivity(double *__restrict__ u, DevScalars *sc, Geometry g,
+                                                       int check_done) {
+  constexpr int NP = N + 1, NM = DIM == 1 ? NP : NP * NP, NV = DIM + 2, NL = N == 1 ? 2 : 3;
+  const OrderTables &T = c_tab[N];
+  if (check_done && sc->done) return;
+  const long plane = (long)g.nx * g.ny;
+  const double k0 = DIM == 1 ? T.b0[0] : T.b0[0] * T.b0[0];
+  // basis rows of the Gauss-Lobatto points
+  auto lob = [&](int a, int n) { return a == 0 ? T.bm[n] : (a == NL - 1 ? T.bp[n] : T.b0[n]); };
+  bool bad = false;
+  for (long cell = blockIdx.x * (long)blockDim.x + threadIdx.x; cell < plane; cell += (long)gridDim.x * blockDim.x) {
+    double C[NV][NM], wb[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+      for (int q = 0; q < NM; ++q) C[v][q] = u[(long)(v * NM + q) * plane + cell];
+      wb[v] = C[v][0] * k0;
+    }
+    const double pb = pos_pressure<DIM>(wb, g.gamma);
+    if (!(wb[0] > 0.0 && pb > 0.0)) {
+      bad = true;
+      continue;
+    }
+    const double eps = fmin(kPosEps, fmin(wb[0], pb));
+    // visit(f): f(point values of the requested variables) at every point
+    auto visit = [&](auto nvars, auto f) {
+      constexpr int K = decltype(nvars)::value;
+      if (DIM == 1) {
+        for (int a = 0; a < NL + NP; ++a) {
+          double w[NV];
+#pragma unroll
+          for (int v = 0; v < K; ++v) {
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m < NP; ++m) acc += C[v][m] * (a < NL ? lob(a, m) : T.bq[m][a - NL]);
+            w[v] = acc;
+          }
+          f(w);
+        }
+      } else {
+        // rows s: Gauss-Lobatto rows take the Gauss columns, Gauss rows take both
+        for (int b = 0; b < NL + NP; ++b) {
+          double cr[K][NP];  // partial sums over the y-degree at this row
+#pragma unroll
+          for (int v = 0; v < K; ++v)
+#pragma unroll
+            for (int m = 0; m < NP; ++m) {
+              double acc = 0.0;
+#pragma unroll
+              for (int n = 0; n < NP; ++n) acc += C[v][m + NP * n] * (b < NL ? lob(b, n) : T.bq[n][b - NL]);
+              cr[v][m] = acc;
+            }
+          const int a0 = b < NL ? NL : 0;
+          for (int a = a0; a < NL + NP; ++a) {
+            double w[NV];
+#pragma unroll
+            for (int v = 0; v < K; ++v) {
+              double acc = 0.0;
+#pragma unroll
+              for (int m = 0; m < NP; ++m) acc += cr[v][m] * (a < NL ? lob(a, m) : T.bq[m][a - NL]);
+              w[v] = acc;
+            }
+            f(w);
+          }
+        }
+      }
+    };
+    double rmin = INFINITY;
+    visit(std::integral_constant<int, 1>{}, [&](const double *w) { rmin = fmin(rmin, w[0]); });
+    double th1 = 1.0, th2 = 1.0;
+    if (rmin < eps) {
+      th1 = (wb[0] - eps) / (wb[0] - rmin);
+#pragma unroll
+      for (int q = 1; q < NM; ++q) C[0][q] *= th1;
+    }
+    visit(std::integral_constant<int, NV>{}, [&](const double *w) {
+      if (pos_pressure<DIM>(w, g.gamma) < eps) th2 = fmin(th2, pos_root<DIM>(wb, w, eps, g.gamma));
+    });
+    if (th1 < 1.0 || th2 < 1.0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int q = 1; q < NM; ++q) u[(long)(v * NM + q) * plane + cell] = th2 < 1.0 ? C[v][q] * th2 : C[v][q];
+    }
+  }
+  if (bad) atomicOr(&sc->status, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1285,7 +1475,7 @@ __device__ inline bool tvb_cell(const double *__restrict__ u, const Geometry &g,
   const double k0 = DIM == 1 ? T.b0[0] : T.b0[0] * T.b0[0];
   bool flag = false;
   double C[NV][NM];
-  load_cell<NP, NM, NV, DIM>(u, plane, map_cell(g, i, j), C);
+  load_cell<NP, NM, NV, DIM>(u, plane, g, map_cell(g, i, j), C);
 #pragma unroll
   for (int dir = 0; dir < DIM; ++dir) {
     const double Mh2 = dir == 0 ? g.tvb_Mx : g.tvb_My;
@@ -1294,8 +1484,8 @@ __device__ inline bool tvb_cell(const double *__restrict__ u, const Geometry &g,
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       double mean = C[v][0] * k0;
-      double mp = u[(long)(v * NM) * plane + cp.idx] * k0;
-      double mm = u[(long)(v * NM) * plane + cm.idx] * k0;
+      double mp = cell_mode<NP, NM, DIM>(u, plane, g, cp, v, 0) * k0;
+      double mm = cell_mode<NP, NM, DIM>(u, plane, g, cm, v, 0) * k0;
       double up = 0.0, um = 0.0;
 #pragma unroll
       for (int q = 0; q < NM; ++q) {
@@ -1336,7 +1526,7 @@ __device__ inline bool kxrcf_cell(const double *__restrict__ u, const Geometry &
   const long plane = (long)g.nx * g.ny;
   const double k0 = DIM == 1 ? T.b0[0] : T.b0[0] * T.b0[0];
   double C[NV][NM];
-  load_cell<NP, NM, NV, DIM>(u, plane, map_cell(g, i, j), C);
+  load_cell<NP, NM, NV, DIM>(u, plane, g, map_cell(g, i, j), C);
   double vel[2] = {0.0, 0.0};
   if (EQ == 0) {
     vel[0] = vel[1] = C[0][0] * k0;
@@ -1363,11 +1553,7 @@ __device__ inline bool kxrcf_cell(const double *__restrict__ u, const Geometry &
       const int v = k == 0 ? 0 : DIM + 1;
       double Nb[NM];
 #pragma unroll
-      for (int q = 0; q < NM; ++q) {
-        const int m = q % NP, n = q / NP;
-        const double s = u[(long)(v * NM + q) * plane + cn.idx];
-        Nb[q] = ((cn.fx && (m & 1)) != (DIM == 2 && cn.fy && (n & 1))) ? -s : s;
-      }
+      for (int q = 0; q < NM; ++q) Nb[q] = cell_mode<NP, NM, DIM>(u, plane, g, cn, v, q);
       if (DIM == 1) {
         double a = 0.0, b = 0.0;
 #pragma unroll
@@ -1551,10 +1737,7 @@ __device__ inline void csweno_cell(const double *__restrict__ u, double *__restr
       CellIdx ci = map_cell(g, i + c - 1, 0);
       double md[NP];
 #pragma unroll
-      for (int n = 0; n < NP; ++n) {
-        double s = u[(long)(v * NM + n) * plane + ci.idx];
-        md[n] = (ci.fx && (n & 1)) ? -s : s;
-      }
+      for (int n = 0; n < NP; ++n) md[n] = cell_mode<NP, NM, 1>(u, plane, g, ci, v, n);
       const int k0 = c == 0 ? 0 : (c == 1 ? N : N + 1), k1 = c == 0 ? N : (c == 1 ? N + 1 : NS);
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
@@ -1584,12 +1767,7 @@ __device__ inline void csweno_cell(const double *__restrict__ u, double *__restr
         CellIdx ci = map_cell(g, i + cx - 1, j + cy - 1);
         double md[NM];
 #pragma unroll
-        for (int q = 0; q < NM; ++q) {
-          int m = q % NP, n = q / NP;
-          double s = u[(long)(v * NM + q) * plane + ci.idx];
-          bool flip = (ci.fx && (m & 1)) != (ci.fy && (n & 1));
-          md[q] = flip ? -s : s;
-        }
+        for (int q = 0; q < NM; ++q) md[q] = cell_mode<NP, NM, 2>(u, plane, g, ci, v, q);
         const int x0 = cx == 0 ? 0 : (cx == 1 ? N : N + 1), x1 = cx == 0 ? N : (cx == 1 ? N + 1 : NS);
         const int y0 = cy == 0 ? 0 : (cy == 1 ? N : N + 1), y1 = cy == 0 ? N : (cy == 1 ? N + 1 : NS);
 #pragma unroll
@@ -1712,13 +1890,10 @@ __device__ inline void char_eig(double gam, int dir, const double (&w)[DIM + 2],
 
 // Modes of variable v of cell (i, j) with the boundary reflections applied.
 template <int NP, int NM, int DIM>
-__device__ inline void load_var(const double *__restrict__ u, long plane, const CellIdx &c, int v, double (&md)[NM]) {
+__device__ inline void load_var(const double *__restrict__ u, long plane, const Geometry &g, const CellIdx &c, int v,
+                                double (&md)[NM]) {
 #pragma unroll
-  for (int q = 0; q < NM; ++q) {
-    const int m = q % NP, n = q / NP;
-    const double s = u[(long)(v * NM + q) * plane + c.idx];
-    md[q] = ((c.fx && (m & 1)) != (DIM == 2 && c.fy && (n & 1))) ? -s : s;
-  }
+  for (int q = 0; q < NM; ++q) md[q] = cell_mode<NP, NM, DIM>(u, plane, g, c, v, q);
 }
 
 template <int N, int DIM>
@@ -1744,7 +1919,7 @@ __device__ inline void csweno_char_cell(const double *__restrict__ u, double *__
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         double md[NM];
-        load_var<NP, NM, 1>(u, plane, ci, v, md);
+        load_var<NP, NM, 1>(u, plane, g, ci, v, md);
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
           if (k < k0c || k >= k1c) continue;
@@ -1798,7 +1973,7 @@ __device__ inline void csweno_char_cell(const double *__restrict__ u, double *__
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           double md[NM];
-          load_var<NP, NM, 2>(u, plane, ci, v, md);
+          load_var<NP, NM, 2>(u, plane, g, ci, v, md);
 #pragma unroll
           for (int ix = 0; ix < NS; ++ix) {
             if (ix < x0 || ix >= x1) continue;
@@ -2078,6 +2253,30 @@ int launch_speed(const LaunchCtx &c, const double *u) {
     hipLaunchKernelGGL((k_speed<decltype(NN)::value, decltype(E)::value, decltype(D)::value>), grid, dim3(kBlock),
                        0, S(c), u, c.sc, c.geo);
   });
+}
+
+int launch_positivity(const LaunchCtx &c, double *u, int check_done) {
+  if (c.eq != 1) return DG_ERR_UNSUPPORTED;
+  const long cells = (long)c.geo.nx * c.geo.ny;
+  dim3 grid((unsigned)std::max<long>(1, std::min<long>((cells + kBlock - 1) / kBlock, 4096)));
+  auto go = [&](auto NN, auto D) {
+    hipLaunchKernelGGL((k_positivity<decltype(NN)::value, decltype(D)::value>), grid, dim3(kBlock), 0, S(c), u, c.sc,
+                       c.geo, check_done);
+  };
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I3 = std::integral_constant<int, 3>;
+  if (c.dim == 1) {
+    if (c.N == 1) go(I1{}, I1{}); else if (c.N == 2) go(I2{}, I1{}); else go(I3{}, I1{});
+  } else {
+    if (c.N == 1) go(I1{}, I2{}); else if (c.N == 2) go(I2{}, I2{}); else go(I3{}, I2{});
+  }
+  return check_launch();
+}
+
+int launch_set_tb(const LaunchCtx &c, double frac, double value) {
+  hipLaunchKernelGGL(k_set_tb, dim3(1), dim3(64), 0, S(c), c.sc, frac, value);
+  return check_launch();
 }
 
 int launch_dt_finalize(const LaunchCtx &c) {

@@ -144,11 +144,7 @@ __device__ inline void cell_features(const double *__restrict__ u, const Geometr
   for (int c = 0; c < 5; ++c) {
     const CellIdx ci = map_cell(g, i + di[c], j + dj[c]);
 #pragma unroll
-    for (int q = 0; q < NM; ++q) {
-      const int m = q % NP, n = q / NP;
-      const double s = u[(long)(v * NM + q) * plane + ci.idx];
-      f[c * NM + q] = ((ci.fx && (m & 1)) != (ci.fy && (n & 1))) ? -s : s;
-    }
+    for (int q = 0; q < NM; ++q) f[c * NM + q] = cell_mode<NP, NM, 2>(u, plane, g, ci, v, q);
   }
   const double c0 = f[0];
   double mx = g.tvb_Mx;
@@ -495,17 +491,12 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
   if (col > g.nx) col = g.nx;
   const bool owner = r >= 1 && r <= kLmStrip && col < g.nx;
   const long plane = (long)g.nx * g.ny;
-  const double *__restrict__ up = u + (long)gv * NM * plane;
   const float *par = reinterpret_cast<const float *>(wl + S::W1 + S::W2);  // b1 | b2 | w3 | b3
   auto loadrow = [&](int jj, double (&R)[NM]) {
     if (jj > g.ny) jj = g.ny;
     const CellIdx ci = map_cell(g, col, jj);
 #pragma unroll
-    for (int q = 0; q < NM; ++q) {
-      const int m = q % NP, n = q / NP;
-      const double v = up[(long)q * plane + ci.idx];
-      R[q] = ((ci.fx && (m & 1)) != (ci.fy && (n & 1))) ? -v : v;
-    }
+    for (int q = 0; q < NM; ++q) R[q] = cell_mode<NP, NM, 2>(u, plane, g, ci, gv, q);
   };
   double Sv[NM], Cv[NM], Nv[NM];
   loadrow(j0 - 1, Sv);

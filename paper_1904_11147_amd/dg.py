@@ -12,15 +12,16 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdg.so")
 
-DG_ABI_VERSION = 1
+DG_ABI_VERSION = 2
 DG_OK, DG_ERR_INVALID_ARG, DG_ERR_UNSUPPORTED, DG_ERR_WORKSPACE, DG_ERR_HIP, DG_ERR_NONPHYSICAL = 0, -1, -2, -3, -4, -5
 BURGERS, EULER = 0, 1
-PERIODIC, TRANSMISSIVE = 0, 1
+PERIODIC, TRANSMISSIVE, REFLECTIVE, INFLOW = 0, 1, 2, 3
 LIM_NONE, LIM_CSWENO, LIM_CSWENO_CHAR = 0, 1, 2
 IND_TVB, IND_ALL, IND_LEARNED, IND_KXRCF = 0, 1, 2, 3
 NEGW_SPLIT, NEGW_RAW = 0, 1
@@ -30,7 +31,7 @@ EXPORTS = ("dg_workspace_bytes", "dg_init", "dg_destroy", "dg_proj_nodes", "dg_p
            "dg_limit", "dg_cfl_dt", "dg_step", "dg_status", "dg_strerror", "dg_profile_enable", "dg_profile_read",
            "dg_autotune", "dg_mlp_layout", "dg_mlp_features", "dg_mlp_forward", "dg_mlp_gradient", "dg_mlp_adam", "dg_set_learned",
            "dg_batch_workspace_bytes", "dg_batch_init", "dg_batch_destroy", "dg_batch_autotune", "dg_batch_set_tiles",
-           "dg_batch_step", "dg_batch_set_learned")
+           "dg_batch_step", "dg_batch_set_learned", "dg_set_time")
 PROF_KINDS = ("stage1", "stage23", "limiter", "dt")
 
 
@@ -56,7 +57,7 @@ class Config(ctypes.Structure):
         ("limiter", ctypes.c_int32),
         ("indicator", ctypes.c_int32),
         ("negw_mode", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("positivity", ctypes.c_int32),
         ("gamma", ctypes.c_double),
         ("x0", ctypes.c_double),
         ("x1", ctypes.c_double),
@@ -65,6 +66,10 @@ class Config(ctypes.Structure):
         ("tvb_M", ctypes.c_double),
         ("weno_eps", ctypes.c_double),
         ("cfl", ctypes.c_double),
+        ("bc_beyond", ctypes.c_int32 * 4),
+        ("pad", ctypes.c_int32),
+        ("bc_switch", (ctypes.c_double * 2) * 4),
+        ("bc_state", ((ctypes.c_double * 4) * 2) * 4),
     ]
 
 
@@ -107,6 +112,7 @@ def lib():
             "dg_batch_set_tiles": [vp, i32, i32],
             "dg_batch_step": [vp, vp, P(ctypes.c_int64), P(d), P(d), i32, P(i32), P(i32), P(ctypes.c_int64)],
             "dg_batch_set_learned": [vp, i32, vp, vp, d, d],
+            "dg_set_time": [vp, d],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -127,16 +133,25 @@ def strerror(code):
 
 def make_config(dim=1, equation=BURGERS, order=2, nx=16, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
                 bc=(PERIODIC,) * 4, gamma=1.4, limiter=LIM_CSWENO, indicator=IND_TVB, negw_mode=NEGW_SPLIT,
-                tvb_M=1.0, weno_eps=1e-6, cfl=0.1):
+                tvb_M=1.0, weno_eps=1e-6, cfl=0.1, positivity=0, bc_beyond=(-1, -1, -1, -1),
+                bc_switch=((0.0, 0.0),) * 4, bc_state=None):
     c = Config()
     c.abi_version = DG_ABI_VERSION
     c.dim, c.equation, c.order = dim, equation, order
     c.nx, c.ny = nx, (1 if dim == 1 else ny)
     for k in range(4):
         c.bc[k] = bc[k]
-    c.limiter, c.indicator, c.negw_mode, c.reserved = limiter, indicator, negw_mode, 0
+    c.limiter, c.indicator, c.negw_mode, c.positivity = limiter, indicator, negw_mode, int(positivity)
     c.gamma, c.x0, c.x1, c.y0, c.y1 = gamma, x0, x1, y0, y1
     c.tvb_M, c.weno_eps, c.cfl = tvb_M, weno_eps, cfl
+    st = np.zeros((4, 2, 4)) if bc_state is None else np.asarray(bc_state, dtype=np.float64)
+    c.pad = 0
+    for k in range(4):
+        c.bc_beyond[k] = int(bc_beyond[k])
+        for a in range(2):
+            c.bc_switch[k][a] = float(bc_switch[k][a])
+            for v in range(4):
+                c.bc_state[k][a][v] = float(st[k, a, v])
     return c
 
 
@@ -244,6 +259,10 @@ class Problem:
         self._rc(rc, "dg_limit", allow_nonphysical)
         return flags, margin, n.value
 
+    def set_time(self, t):
+        """Time of the boundary data for residual() and limit()."""
+        self._rc(lib().dg_set_time(self._h, float(t)), "dg_set_time")
+
     def cfl_dt(self, state):
         self._check_state(state)
         dt = ctypes.c_double()
@@ -286,6 +305,7 @@ class Problem:
 def problem_from_workload(wl, device="cuda", **over):
     kw = dict(dim=wl.dim, equation=wl.equation, order=wl.order, nx=wl.nx, ny=wl.ny, x0=wl.x0, x1=wl.x1,
               y0=wl.y0, y1=wl.y1, bc=tuple(wl.bc), gamma=wl.gamma, cfl=wl.cfl)
+    kw.update(wl.bc_extra)
     kw.update(over)
     return Problem(device=device, **kw)
 
@@ -429,6 +449,7 @@ def batch_from_workloads(wls, device="cuda", limit=True, **over):
     for wl in wls:
         kw = dict(dim=2, equation=wl.equation, order=wl.order, nx=wl.nx, ny=wl.ny, x0=wl.x0, x1=wl.x1,
                   y0=wl.y0, y1=wl.y1, bc=tuple(wl.bc), gamma=wl.gamma, cfl=wl.cfl)
+        kw.update(wl.bc_extra)
         kw.update(over)
         cfgs.append(kw)
     b = Batch(cfgs, device=device)

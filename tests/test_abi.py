@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -101,3 +102,39 @@ def test_batch_workspace_and_validation(dg):
     h = ctypes.c_void_p()
     one = arr(dict(e2, order=2, nx=8, ny=8))
     assert dg.lib().dg_batch_init(one, 1, None, 0, None, ctypes.byref(h)) == dg.DG_ERR_WORKSPACE
+
+
+def test_boundary_and_positivity_validation(dg):
+    """Wall, inflow and switching sides and the positivity flag are checked on
+    the host: a wall or positivity needs the Euler equations, west/east sides
+    never switch, inflow states must be admissible."""
+    from paper_1904_11147_amd import workloads as W
+    wl = W.double_mach(64)
+    ok = dg.make_config(**{k: v for k, v in wl.config().items()})
+    assert dg.workspace_bytes(ok) > 0
+    bad = []
+    bad.append(dict(wl.config(), bc_beyond=(2, -1, 2, 3)))           # a west side that switches
+    bad.append(dict(wl.config(), bc_beyond=(-1, -1, 0, 3)))          # periodic beyond a switch
+    st = np.array(wl.bc_extra["bc_state"])
+    st[0, 0, 0] = -1.0
+    bad.append(dict(wl.config(), bc_state=st))                        # negative inflow density
+    st = np.array(wl.bc_extra["bc_state"])
+    st[3, 1, 3] = 0.0
+    bad.append(dict(wl.config(), bc_state=st))                        # zero pressure beyond the switch
+    bad.append(dict(dim=1, equation=dg.BURGERS, order=1, nx=8, bc=(dg.REFLECTIVE, 1, 0, 0)))
+    bad.append(dict(dim=1, equation=dg.BURGERS, order=1, nx=8, bc=(1, 1, 0, 0), positivity=1))
+    bad.append(dict(dim=1, equation=dg.EULER, order=1, nx=8, bc=(1, 1, 0, 0), positivity=2))
+    for kw in bad:
+        with pytest.raises(dg.DGError):
+            dg.workspace_bytes(dg.make_config(**kw))
+    c = dg.make_config(**wl.config())
+    c.pad = 1
+    with pytest.raises(dg.DGError):
+        dg.workspace_bytes(c)
+    # batches take walls and inflow sides, not switches or the positivity scaling
+    n = ctypes.c_size_t()
+    e2 = dict(dim=2, equation=dg.EULER, order=2, nx=8, ny=8)
+    cf = (dg.Config * 1)(dg.make_config(**dict(e2, bc=(dg.REFLECTIVE, 1, dg.REFLECTIVE, 1))))
+    assert dg.lib().dg_batch_workspace_bytes(cf, 1, ctypes.byref(n)) == 0
+    cf = (dg.Config * 1)(dg.make_config(**dict(e2, bc=(1, 1, 1, 1), positivity=1)))
+    assert dg.lib().dg_batch_workspace_bytes(cf, 1, ctypes.byref(n)) == dg.DG_ERR_UNSUPPORTED

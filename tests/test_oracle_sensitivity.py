@@ -43,3 +43,25 @@ def test_kxrcf_on_a_flow_from_rest_is_sensitive_tvb_is_not(oracle):
         B = op.run(U1, 0.0, wl.t_end)[0]
         out[mode] = np.abs(A - B)[:, 0].mean()
     assert out[0] < 1e-12 and out[3] > 1e-8, out
+
+
+def test_double_mach_q3_amplifies_q2_does_not(oracle):
+    """The double Mach reflection (Mach 10, positivity scaling on): a 1e-15
+    relative perturbation of the initial state stays near 1e-13 in L1 after
+    20 Q2 steps, while Q3 reaches ~1e-9 after 20 steps (and ~5e-2 after 49 on
+    this mesh), so Q3 final-time GPU/oracle comparisons of this problem stop
+    after 5 steps."""
+    from paper_1904_11147_amd import workloads as W
+    from tests.dgutil import oracle_initial_state, oracle_problem
+    from tests.test_gpu_runs import _l1_diff
+    out = {}
+    for order in (2, 3):
+        wl = W.double_mach(48, order=order)
+        op = oracle_problem(oracle, wl)
+        op, U0 = oracle_initial_state(oracle, wl, op, limit=True)
+        ref, _, s1, _ = op.run(U0, 0.0, 1.0, max_steps=20)
+        U1 = U0 * (1 + 1e-15 * np.random.default_rng(1).standard_normal(U0.shape))
+        got, _, s2, _ = op.run(U1, 0.0, 1.0, max_steps=20)
+        assert s1 == s2 == 20
+        out[order] = _l1_diff(got, ref, 2, order).max()
+    assert out[2] < 1e-11 and out[3] > 1e-10, out
