@@ -100,6 +100,47 @@ def indicator_leg(wl, state0, t0, steps, warmup, indicator=0, net=None, limiter=
             "troubled_fraction": troubled / max(1, 3 * wl.cells * n)}
 
 
+def double_mach_leg(steps, warmup, n=1920, order=2, to_end=False):
+    """The paper's Example 11 on its finest mesh: double Mach reflection,
+    n x n/4 cells, walls, inflow and the moving shock on the north side,
+    positivity scaling after every limiter pass.  Optionally the whole run to
+    t = 0.2 as well."""
+    import torch
+    from paper_1904_11147_amd import dg, workloads as W
+    wl = W.double_mach(n, order=order)
+    prob = dg.problem_from_workload(wl, device="cuda:0")
+    state = dg.initial_state(prob, wl, limit=True)
+    rows, _ = prob.autotune(state)
+    t, _ = prob.step(state, 0.0, wl.t_end, max_steps=warmup)
+    prob.profile(True)
+    prob.profile_read(reset=True)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    t, k = prob.step(state, t, wl.t_end, max_steps=steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - a
+    prof, troubled = prob.profile_read(reset=True)
+    prob.profile(False)
+    res = {"workload": f"{wl.name}: 2D Euler, Mach 10 shock at 60 degrees on [0,4]x[0,1], {wl.nx}x{wl.ny} cells, "
+                       f"Q{order}, TVB M=1 + CSWENO + positivity scaling, CFL {wl.cfl}",
+           "value": wl.dofs * k / el, "unit": "cell-DOF updates/s", "ms_per_step": 1e3 * el / k, "steps": k,
+           "troubled_fraction": troubled / max(1, 3 * wl.cells * k), "autotuned_rows": rows,
+           "kernels_ms_per_step": {kk: v[0] / k for kk, v in prof.items()}}
+    if to_end:
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        try:
+            t, k2 = prob.step(state, t, wl.t_end)
+            status = "ok"
+        except dg.DGError as e:
+            k2, status = 0, str(e)
+        torch.cuda.synchronize()
+        res["to_t_end"] = {"t": t, "steps_total": warmup + k + k2, "seconds_rest": time.perf_counter() - a,
+                           "status": status}
+    prob.close()
+    return res
+
+
 def batched_leg(steps, warmup, count=256, nets=None):
     """256 mixed four-state Riemann problems (side uniform in [64,512], order
     uniform in {1,2,3}, one seed each): every instance advanced alone through
@@ -186,6 +227,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-instance batched comparison")
     ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--no-double-mach", action="store_true", help="skip the double Mach reflection leg")
+    ap.add_argument("--double-mach-only", action="store_true",
+                    help="run only the double Mach reflection leg and print its record (for profiling)")
+    ap.add_argument("--double-mach-to-end", action="store_true",
+                    help="also run the double Mach reflection to t = 0.2 (about a minute)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run a plain 1 GiB device copy kernel three times "
                          "(the known-size reference for rocprofv3 FETCH_SIZE/WRITE_SIZE)")
@@ -198,6 +244,10 @@ def main():
     import torch
     from paper_1904_11147_amd import dg, workloads as W
 
+    if args.double_mach_only:
+        print(json.dumps({"double_mach": double_mach_leg(args.steps, args.warmup, to_end=args.double_mach_to_end)}),
+              flush=True)
+        return
     wl = W.riemann2d(n=args.n, order=2, seed=args.seed)
     prob = dg.problem_from_workload(wl, device="cuda:0")
     state = dg.initial_state(prob, wl, limit=True)
@@ -290,6 +340,9 @@ def main():
     prob.close()
     del state
     torch.cuda.empty_cache()
+    if not args.no_double_mach:
+        out["double_mach"] = double_mach_leg(args.steps, 2, to_end=args.double_mach_to_end)
+        torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = batched_leg(args.batched_steps, 2, nets=nets)
     if not args.no_cpu_baseline:

@@ -118,6 +118,12 @@ int ensure_tables(int device) {
   return DG_OK;
 }
 
+bool special_bc(const Geometry &g) {
+  for (int k = 0; k < 4; ++k)
+    if (g.bc[k] == DG_BC_REFLECTIVE || g.bc[k] == DG_BC_INFLOW || g.bcb[k] >= 0) return true;
+  return false;
+}
+
 void fill_geometry(const dg_config *cfg, Geometry *g) {
   g->nx = cfg->nx;
   g->ny = cfg->ny;
@@ -337,6 +343,7 @@ int dg_init(const dg_config *cfg, void *workspace, size_t workspace_bytes, void 
   c.timed_bc = 0;
   for (int k = 2; k < 4; ++k)
     if (c.geo.bcb[k] >= 0 && c.geo.bsw[k][1] != 0.0) c.timed_bc = 1;
+  c.special_bc = dg::special_bc(c.geo);
   c.geo.tb = &c.sc->tb;
   c.grid_cap = 2048;
   c.use_march = 1;

@@ -42,7 +42,9 @@ int validate_batch(const dg_config *cfgs, int32_t n) {
     if (rc) return rc;
     if (cfgs[i].dim != 2 || cfgs[i].equation != DG_EQ_EULER) return DG_ERR_UNSUPPORTED;
     if (cfgs[i].limiter != cfgs[0].limiter || cfgs[i].indicator != cfgs[0].indicator) return DG_ERR_INVALID_ARG;
-    // per-instance boundary switches and positivity scaling run on single meshes only
+    // walls, inflow and switching sides and the positivity scaling run on single meshes only
+    for (int k = 0; k < 4; ++k)
+      if (cfgs[i].bc[k] != DG_BC_PERIODIC && cfgs[i].bc[k] != DG_BC_TRANSMISSIVE) return DG_ERR_UNSUPPORTED;
     if (cfgs[i].positivity || cfgs[i].bc_beyond[2] >= 0 || cfgs[i].bc_beyond[3] >= 0) return DG_ERR_UNSUPPORTED;
     cells += (long long)cfgs[i].nx * cfgs[i].ny;
   }

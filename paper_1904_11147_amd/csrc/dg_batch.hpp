@@ -148,6 +148,7 @@ __global__ __launch_bounds__(64) void k_batch_speed(const BatchInst *__restrict_
 
 // SSP-RK3 stage over the queued tiles of one order.  Stage 1: u -> A, 2: (A,
 // u) -> B, 3: (B, u) -> u; stage 0 writes the residual of u into A.
+// Batches take periodic and transmissive sides only (checked on the host).
 template <int N, int STAGE>
 __global__ __launch_bounds__(64, 2) void k_batch_stage(const BatchInst *__restrict__ inst,
                                                        const BatchQueue *__restrict__ q) {
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(64, 2) void k_batch_stage(const BatchInst *__restri
   a.sc = I.sc;
   a.geo = I.geo;
   a.want_speed = 1;
-  euler_tile<N, STAGE>(a, local % I.tiles_x, local / I.tiles_x, I.rows, row);
+  euler_tile<N, STAGE, false>(a, local % I.tiles_x, local / I.tiles_x, I.rows, row);
 }
 
 // Buffers of the limiter pass after stage SLOT+1: the state it limits and the
@@ -209,8 +210,8 @@ __global__ __launch_bounds__(64) void k_batch_indicator(const BatchInst *__restr
     double mg = INFINITY;
     if (i < g.nx)
       flag = IND == DG_IND_ALL     ? true
-             : IND == DG_IND_KXRCF ? kxrcf_cell<N, 1, 2>(limit_target<SLOT>(I), g, i, s.j, mg)
-                                   : tvb_cell<N, 1, 2>(limit_target<SLOT>(I), g, i, s.j, mg);
+             : IND == DG_IND_KXRCF ? kxrcf_cell<N, 1, 2, false>(limit_target<SLOT>(I), g, i, s.j, mg)
+                                   : tvb_cell<N, 1, 2, false>(limit_target<SLOT>(I), g, i, s.j, mg);
     const long long cell = (long long)s.j * g.nx + i;
     append_batch(q, SLOT, list, I.sc, flag, ((long long)s.id << 32) | cell);
   }
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(64 * lm_waves(N), 2) void k_batch_learned(const Bat
     const int x0 = ((local % groups) * S::WAVES + wave) * kLmStrip;
     const int j0 = (local / groups) * kLmRows, j1 = min(j0 + kLmRows, g.ny);
     if (x0 >= g.nx) continue;  // no barrier in the loop
-    lm_strip<N>(limit_target<SLOT>(I), g, x0, j0, j1, L, lds, lds + S::FEAT0 + wave * S::FEAT,
+    lm_strip<N, false>(limit_target<SLOT>(I), g, x0, j0, j1, L, lds, lds + S::FEAT0 + wave * S::FEAT,
                 [&](bool active, bool flag, double, float, long cell) {
                   append_batch(q, SLOT, list, I.sc, active && flag, ((long long)id << 32) | cell);
                 });
@@ -252,7 +253,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_csweno(const BatchInst *__rest
   for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
     const long long e = list[t / 4];
     const BatchInst &I = inst[(int)(e >> 32)];
-    csweno_cell<N, 1, 2>(limit_target<SLOT>(I), limit_side<SLOT>(I), I.geo, (long)(e & 0xffffffffll), (int)(t % 4));
+    csweno_cell<N, 1, 2, false>(limit_target<SLOT>(I), limit_side<SLOT>(I), I.geo, (long)(e & 0xffffffffll),
+                                (int)(t % 4));
   }
 }
 
@@ -264,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_csweno_char(const BatchInst *_
   for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
     const long long e = list[t];
     const BatchInst &I = inst[(int)(e >> 32)];
-    csweno_char_cell<N, 2>(limit_target<SLOT>(I), limit_side<SLOT>(I), I.geo, (long)(e & 0xffffffffll));
+    csweno_char_cell<N, 2, false>(limit_target<SLOT>(I), limit_side<SLOT>(I), I.geo, (long)(e & 0xffffffffll));
   }
 }
 

@@ -92,6 +92,7 @@ struct LaunchCtx {
   int limiter, indicator;
   int positivity;        // Zhang-Shu scaling after every limiter pass
   int timed_bc;          // a side switches at a moving point: keep DevScalars::tb current
+  int special_bc;        // a wall, inflow or switching side (else periodic / transmissive only)
   int grid_cap;          // blocks for list-driven kernels
   int use_march;         // 2D: marching stage kernel where registers allow
   int rows;              // 2D marching kernels: rows per tile (0: a rule from the mesh size)
@@ -163,6 +164,7 @@ struct BatchCtx {
 int validate_config(const dg_config *c);
 int ensure_tables(int device);
 void fill_geometry(const dg_config *cfg, Geometry *g);
+bool special_bc(const Geometry &g);  // a wall, inflow or switching side
 int num_vars(const dg_config *c);
 int num_modes(const dg_config *c);
 

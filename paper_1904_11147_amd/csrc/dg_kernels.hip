@@ -128,11 +128,28 @@ struct CellIdx {
   int8_t gs;     // >= 0: inflow ghost with lowest mode Geometry::bst[gs]
 };
 
+// BND = false: only periodic and transmissive sides can occur (the launch
+// checked), which keeps the hot stage kernel free of the other cases.
+template <bool BND = true>
 __device__ inline CellIdx map_cell(const Geometry &g, int i, int j) {
   CellIdx c;
   c.fx = c.fy = false;
   c.neg = 0;
   c.gs = -1;
+  if constexpr (!BND) {
+    if (i < 0) {
+      if (g.bc[0] == DG_BC_PERIODIC) i += g.nx; else { i = 0; c.fx = true; }
+    } else if (i >= g.nx) {
+      if (g.bc[1] == DG_BC_PERIODIC) i -= g.nx; else { i = g.nx - 1; c.fx = true; }
+    }
+    if (j < 0) {
+      if (g.bc[2] == DG_BC_PERIODIC) j += g.ny; else { j = 0; c.fy = true; }
+    } else if (j >= g.ny) {
+      if (g.bc[3] == DG_BC_PERIODIC) j -= g.ny; else { j = g.ny - 1; c.fy = true; }
+    }
+    c.idx = (long)j * g.nx + i;
+    return c;
+  }
   if (i < 0 || i >= g.nx) {
     const int s = i < 0 ? 0 : 1, k = g.bc[s];
     if (k == DG_BC_PERIODIC) {
@@ -892,7 +909,7 @@ __host__ __device__ constexpr int euler_strip(int N) { return 64 * euler_vpl(N) 
 // row by row by one wavefront.  `row` is the wavefront's LDS staging area of
 // VPL (N+1)^2 64 doubles (the current row's modes of each lane's variables,
 // [k*NM+q][lane]).
-template <int N, int STAGE>
+template <int N, int STAGE, bool BND>
 __device__ __forceinline__ void euler_tile(const StageArgs &a, int bx, int by, int rows_per_block,
                                            double *__restrict__ row) {
   constexpr int NP = N + 1, NM = NP * NP, VPL = euler_vpl(N), LPC = 4 / VPL, STRIP = euler_strip(N);
@@ -929,7 +946,7 @@ __device__ __forceinline__ void euler_tile(const StageArgs &a, int bx, int by, i
         }
         U[k][q] = s;
       }
-    if (c.neg != 0 || c.gs >= 0) {  // wall and inflow ghosts: boundary cells only
+    if (BND && (c.neg != 0 || c.gs >= 0)) {  // wall and inflow ghosts: boundary cells only
 #pragma unroll
       for (int k = 0; k < VPL; ++k) {
         const int v = v0 + k;
@@ -991,9 +1008,9 @@ __device__ __forceinline__ void euler_tile(const StageArgs &a, int bx, int by, i
   double FS[VPL][NP];
   {
     double P[VPL][NM], tn[VPL][NP], ts[VPL][NP];
-    load2(map_cell(g, col, j0 - 1), P);
+    load2(map_cell<BND>(g, col, j0 - 1), P);
     trace2([&](int k, int q) { return P[k][q]; }, T.bp, 1, tn);
-    load2(map_cell(g, col, j0), P);
+    load2(map_cell<BND>(g, col, j0), P);
     trace2([&](int k, int q) { return P[k][q]; }, T.bm, 1, ts);
 #pragma unroll
     for (int e = 0; e < NP; ++e) {
@@ -1015,7 +1032,7 @@ __device__ __forceinline__ void euler_tile(const StageArgs &a, int bx, int by, i
   for (int j = j0; j < j1; ++j) {
     // next row in flight while this row is computed
     double P[VPL][NM];
-    load2(map_cell(g, col, j + 1), P);
+    load2(map_cell<BND>(g, col, j + 1), P);
     const long cellj = (long)j * g.nx + col;
     double L[VPL][NM];
 #pragma unroll
@@ -1186,12 +1203,12 @@ __device__ inline int xcd_tile(int L, int total) {
   return x * q + min(x, r) + L / kXcd;
 }
 
-template <int N, int STAGE>
+template <int N, int STAGE, bool BND>
 __global__ __launch_bounds__(64, 2) void k_stage_2d_euler(StageArgs a, int rows_per_block) {
   __shared__ double row[euler_vpl(N) * (N + 1) * (N + 1) * 64];
   const int tiles_x = gridDim.x;
   const int w = xcd_tile(blockIdx.x + blockIdx.y * tiles_x, tiles_x * gridDim.y);
-  euler_tile<N, STAGE>(a, w % tiles_x, w / tiles_x, rows_per_block, row);
+  euler_tile<N, STAGE, BND>(a, w % tiles_x, w / tiles_x, rows_per_block, row);
 }
 
 // ---------------------------------------------------------------------------
@@ -1467,7 +1484,7 @@ struct LimitArgs {
 
 // TVB-modified minmod decision of cell (i, j) from the state u; mg receives
 // the decision margin.
-template <int N, int EQ, int DIM>
+template <int N, int EQ, int DIM, bool BND = true>
 __device__ inline bool tvb_cell(const double *__restrict__ u, const Geometry &g, int i, int j, double &mg) {
   constexpr int NP = N + 1, NM = DIM == 1 ? NP : NP * NP, NV = Phys<EQ, DIM>::NV;
   const OrderTables &T = c_tab[N];
@@ -1475,12 +1492,12 @@ __device__ inline bool tvb_cell(const double *__restrict__ u, const Geometry &g,
   const double k0 = DIM == 1 ? T.b0[0] : T.b0[0] * T.b0[0];
   bool flag = false;
   double C[NV][NM];
-  load_cell<NP, NM, NV, DIM>(u, plane, g, map_cell(g, i, j), C);
+  load_cell<NP, NM, NV, DIM>(u, plane, g, map_cell<BND>(g, i, j), C);
 #pragma unroll
   for (int dir = 0; dir < DIM; ++dir) {
     const double Mh2 = dir == 0 ? g.tvb_Mx : g.tvb_My;
-    const CellIdx cp = map_cell(g, i + (dir == 0), j + (dir == 1));
-    const CellIdx cm = map_cell(g, i - (dir == 0), j - (dir == 1));
+    const CellIdx cp = map_cell<BND>(g, i + (dir == 0), j + (dir == 1));
+    const CellIdx cm = map_cell<BND>(g, i - (dir == 0), j - (dir == 1));
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       double mean = C[v][0] * k0;
@@ -1518,7 +1535,7 @@ __device__ inline bool tvb_cell(const double *__restrict__ u, const Geometry &g,
 // divided by h^((N+1)/2) (g.kx_scale), the inflow boundary's measure and the
 // maximum of |u| over the volume quadrature points; troubled above 1.  mg
 // receives min(|I - 1|, |v_x|, |v_y|).
-template <int N, int EQ, int DIM>
+template <int N, int EQ, int DIM, bool BND = true>
 __device__ inline bool kxrcf_cell(const double *__restrict__ u, const Geometry &g, int i, int j, double &mg) {
   constexpr int NP = N + 1, NM = DIM == 1 ? NP : NP * NP, NV = Phys<EQ, DIM>::NV;
   constexpr int NVAR = EQ == 0 ? 1 : 2;
@@ -1526,7 +1543,7 @@ __device__ inline bool kxrcf_cell(const double *__restrict__ u, const Geometry &
   const long plane = (long)g.nx * g.ny;
   const double k0 = DIM == 1 ? T.b0[0] : T.b0[0] * T.b0[0];
   double C[NV][NM];
-  load_cell<NP, NM, NV, DIM>(u, plane, g, map_cell(g, i, j), C);
+  load_cell<NP, NM, NV, DIM>(u, plane, g, map_cell<BND>(g, i, j), C);
   double vel[2] = {0.0, 0.0};
   if (EQ == 0) {
     vel[0] = vel[1] = C[0][0] * k0;
@@ -1545,7 +1562,7 @@ __device__ inline bool kxrcf_cell(const double *__restrict__ u, const Geometry &
     if (vel[dir] == 0.0) continue;
     const bool minus = vel[dir] > 0.0;  // inflow through the west / south face
     const int d = minus ? -1 : 1;
-    const CellIdx cn = map_cell(g, i + (dir == 0 ? d : 0), j + (dir == 1 ? d : 0));
+    const CellIdx cn = map_cell<BND>(g, i + (dir == 0 ? d : 0), j + (dir == 1 ? d : 0));
     const double *own = minus ? T.bm : T.bp, *nbr = minus ? T.bp : T.bm;
     const double flen = DIM == 1 ? 1.0 : (dir == 0 ? g.hy : g.hx);
 #pragma unroll
@@ -1623,7 +1640,7 @@ __device__ inline void append_troubled(const LimitArgs &a, bool flag, long cell)
   }
 }
 
-template <int N, int EQ, int DIM>
+template <int N, int EQ, int DIM, bool BND>
 __global__ __launch_bounds__(kBlock) void k_indicator(LimitArgs a) {
   const Geometry &g = a.geo;
   if (a.check_done && a.sc->done) return;
@@ -1639,9 +1656,9 @@ __global__ __launch_bounds__(kBlock) void k_indicator(LimitArgs a) {
     } else if (a.mode == DG_IND_ALL) {
       flag = true;
     } else if (a.mode == DG_IND_KXRCF) {
-      flag = kxrcf_cell<N, EQ, DIM>(a.u, g, i, j, mg);
+      flag = kxrcf_cell<N, EQ, DIM, BND>(a.u, g, i, j, mg);
     } else {
-      flag = tvb_cell<N, EQ, DIM>(a.u, g, i, j, mg);
+      flag = tvb_cell<N, EQ, DIM, BND>(a.u, g, i, j, mg);
     }
     if (a.flags) a.flags[cell] = flag ? 1 : 0;
     if (a.margin) a.margin[cell] = mg;
@@ -1721,7 +1738,7 @@ __device__ inline double interval_mean(const OrderTables &T, int k, int n) {
 
 // Reconstruction of variable v of the troubled cell `cell` from the
 // pre-limit state u; the non-mean modes are written to `side`.
-template <int N, int EQ, int DIM>
+template <int N, int EQ, int DIM, bool BND = true>
 __device__ inline void csweno_cell(const double *__restrict__ u, double *__restrict__ side, const Geometry &g,
                                    long cell, int v) {
   constexpr int NP = N + 1, NM = DIM == 1 ? NP : NP * NP;
@@ -1734,7 +1751,7 @@ __device__ inline void csweno_cell(const double *__restrict__ u, double *__restr
     double st[NS];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      CellIdx ci = map_cell(g, i + c - 1, 0);
+      CellIdx ci = map_cell<BND>(g, i + c - 1, 0);
       double md[NP];
 #pragma unroll
       for (int n = 0; n < NP; ++n) md[n] = cell_mode<NP, NM, 1>(u, plane, g, ci, v, n);
@@ -1764,7 +1781,7 @@ __device__ inline void csweno_cell(const double *__restrict__ u, double *__restr
     for (int cy = 0; cy < 3; ++cy)
 #pragma unroll
       for (int cx = 0; cx < 3; ++cx) {
-        CellIdx ci = map_cell(g, i + cx - 1, j + cy - 1);
+        CellIdx ci = map_cell<BND>(g, i + cx - 1, j + cy - 1);
         double md[NM];
 #pragma unroll
         for (int q = 0; q < NM; ++q) md[q] = cell_mode<NP, NM, 2>(u, plane, g, ci, v, q);
@@ -1825,13 +1842,13 @@ __device__ inline void csweno_cell(const double *__restrict__ u, double *__restr
   }
 }
 
-template <int N, int EQ, int DIM>
+template <int N, int EQ, int DIM, bool BND>
 __global__ __launch_bounds__(kBlock) void k_csweno(LimitArgs a) {
   constexpr int NV = Phys<EQ, DIM>::NV;
   if (a.check_done && a.sc->done) return;
   const long total = (long)(*a.count) * NV;
   for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x)
-    csweno_cell<N, EQ, DIM>(a.u, a.side, a.geo, a.list[t / NV], (int)(t % NV));
+    csweno_cell<N, EQ, DIM, BND>(a.u, a.side, a.geo, a.list[t / NV], (int)(t % NV));
 }
 
 // ---------------------------------------------------------------------------
@@ -1896,7 +1913,7 @@ __device__ inline void load_var(const double *__restrict__ u, long plane, const 
   for (int q = 0; q < NM; ++q) md[q] = cell_mode<NP, NM, DIM>(u, plane, g, c, v, q);
 }
 
-template <int N, int DIM>
+template <int N, int DIM, bool BND = true>
 __device__ inline void csweno_char_cell(const double *__restrict__ u, double *__restrict__ side, const Geometry &g,
                                         long cell) {
   constexpr int NP = N + 1, NM = DIM == 1 ? NP : NP * NP, NV = DIM + 2;
@@ -1914,7 +1931,7 @@ __device__ inline void csweno_char_cell(const double *__restrict__ u, double *__
     double a[NV][NS];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const CellIdx ci = map_cell(g, i + c - 1, 0);
+      const CellIdx ci = map_cell<BND>(g, i + c - 1, 0);
       const int k0c = c == 0 ? 0 : (c == 1 ? N : N + 1), k1c = c == 0 ? N : (c == 1 ? N + 1 : NS);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -1968,7 +1985,7 @@ __device__ inline void csweno_char_cell(const double *__restrict__ u, double *__
       double a[NV][NS];
 #pragma unroll
       for (int cx = 0; cx < 3; ++cx) {
-        const CellIdx ci = map_cell(g, i + cx - 1, j + cy - 1);
+        const CellIdx ci = map_cell<BND>(g, i + cx - 1, j + cy - 1);
         const int x0 = cx == 0 ? 0 : (cx == 1 ? N : N + 1), x1 = cx == 0 ? N : (cx == 1 ? N + 1 : NS);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -2057,12 +2074,12 @@ __device__ inline void csweno_char_cell(const double *__restrict__ u, double *__
   }
 }
 
-template <int N, int DIM>
+template <int N, int DIM, bool BND>
 __global__ __launch_bounds__(kBlock) void k_csweno_char(LimitArgs a) {
   if (a.check_done && a.sc->done) return;
   const long total = *a.count;
   for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x)
-    csweno_char_cell<N, DIM>(a.u, a.side, a.geo, a.list[t]);
+    csweno_char_cell<N, DIM, BND>(a.u, a.side, a.geo, a.list[t]);
 }
 
 template <int NM, int NV>
@@ -2166,7 +2183,8 @@ void stage_launch(const LaunchCtx &c, const StageArgs &a) {
     constexpr int strip = euler_strip(NN);
     const int rows = march_rows(c, strip);
     dim3 grid((c.geo.nx + strip - 1) / strip, (c.geo.ny + rows - 1) / rows, 1);
-    hipLaunchKernelGGL((k_stage_2d_euler<NN, STAGE>), grid, dim3(64), 0, S(c), a, rows);
+    if (c.special_bc) hipLaunchKernelGGL((k_stage_2d_euler<NN, STAGE, true>), grid, dim3(64), 0, S(c), a, rows);
+    else hipLaunchKernelGGL((k_stage_2d_euler<NN, STAGE, false>), grid, dim3(64), 0, S(c), a, rows);
     return;
   }
   if (D == 2 && march && c.use_march) {
@@ -2213,8 +2231,9 @@ int launch_limit(const LaunchCtx &c, double *u, double *side, int count_slot, ui
   a.geo = c.geo;
   a.mode = c.indicator;
   a.check_done = count_slot < 3 ? 1 : 0;
-  return dispatch(c, [&](auto D, auto E, auto NN) {
+  auto body = [&](auto D, auto E, auto NN, auto B) {
     constexpr int d = decltype(D)::value, e = decltype(E)::value, n = decltype(NN)::value;
+    constexpr bool bnd = decltype(B)::value;
     constexpr int NM = d == 1 ? n + 1 : (n + 1) * (n + 1);
     constexpr int NV = Phys<e, d>::NV;
     dim3 block, grid = cell_grid(c, block);
@@ -2225,23 +2244,29 @@ int launch_limit(const LaunchCtx &c, double *u, double *side, int count_slot, ui
                       (float)c.band_hi, c.mlp_prob};
         constexpr int waves = lm_waves(n);
         const int groups = ((c.geo.nx + kLmStrip - 1) / kLmStrip + waves - 1) / waves;
-        hipLaunchKernelGGL((k_indicator_learned<n, e>), dim3(groups, (c.geo.ny + kLmRows - 1) / kLmRows),
+        hipLaunchKernelGGL((k_indicator_learned<n, e, bnd>), dim3(groups, (c.geo.ny + kLmRows - 1) / kLmRows),
                            dim3(64 * waves), 0, S(c), a, L, kLmRows);
         learned = true;
       }
     }
-    if (!learned) hipLaunchKernelGGL((k_indicator<n, e, d>), grid, block, 0, S(c), a);
+    if (!learned) hipLaunchKernelGGL((k_indicator<n, e, d, bnd>), grid, block, 0, S(c), a);
     if (c.limiter != DG_LIM_NONE) {
       bool chr = false;
       if constexpr (e == DG_EQ_EULER) {
         if (c.limiter == DG_LIM_CSWENO_CHAR) {
-          hipLaunchKernelGGL((k_csweno_char<n, d>), dim3(c.grid_cap), dim3(kBlock), 0, S(c), a);
+          hipLaunchKernelGGL((k_csweno_char<n, d, bnd>), dim3(c.grid_cap), dim3(kBlock), 0, S(c), a);
           chr = true;
         }
       }
-      if (!chr) hipLaunchKernelGGL((k_csweno<n, e, d>), dim3(c.grid_cap), dim3(kBlock), 0, S(c), a);
+      if (!chr) hipLaunchKernelGGL((k_csweno<n, e, d, bnd>), dim3(c.grid_cap), dim3(kBlock), 0, S(c), a);
       hipLaunchKernelGGL((k_scatter<NM, NV>), dim3(c.grid_cap), dim3(kBlock), 0, S(c), a, u);
     }
+  };
+  // walls, inflow and switching sides get their own instantiations, so that
+  // problems with periodic and transmissive sides only carry none of that code
+  return dispatch(c, [&](auto D, auto E, auto NN) {
+    if (c.special_bc) body(D, E, NN, std::true_type{});
+    else body(D, E, NN, std::false_type{});
   });
 }
 

@@ -479,7 +479,7 @@ __device__ inline void lm_load_weights(const LearnedArgs &L, uint16_t *wl) {
 // One wavefront's strip: columns x0-1 .. x0+14 (owned x0 .. x0+13), rows
 // j0 .. j1-1.  emit(active, flag, margin, p, cell) is called by every lane
 // once per row (active: an owned cell, from lane group 0).
-template <int N, typename Emit>
+template <int N, bool BND, typename Emit>
 __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g, int x0, int j0, int j1,
                                 const LearnedArgs &L, const uint16_t *__restrict__ wl, uint16_t *__restrict__ feat,
                                 Emit &&emit) {
@@ -492,11 +492,20 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
   const bool owner = r >= 1 && r <= kLmStrip && col < g.nx;
   const long plane = (long)g.nx * g.ny;
   const float *par = reinterpret_cast<const float *>(wl + S::W1 + S::W2);  // b1 | b2 | w3 | b3
+  const double *__restrict__ up = u + (long)gv * NM * plane;
   auto loadrow = [&](int jj, double (&R)[NM]) {
     if (jj > g.ny) jj = g.ny;
-    const CellIdx ci = map_cell(g, col, jj);
+    const CellIdx ci = map_cell<BND>(g, col, jj);
 #pragma unroll
-    for (int q = 0; q < NM; ++q) R[q] = cell_mode<NP, NM, 2>(u, plane, g, ci, gv, q);
+    for (int q = 0; q < NM; ++q) {
+      if constexpr (BND) {
+        R[q] = cell_mode<NP, NM, 2>(u, plane, g, ci, gv, q);
+      } else {  // periodic and transmissive sides: parity flips only
+        const int m = q % NP, n = q / NP;
+        const double v = up[(long)q * plane + ci.idx];
+        R[q] = ((ci.fx && (m & 1)) != (ci.fy && (n & 1))) ? -v : v;
+      }
+    }
   };
   double Sv[NM], Cv[NM], Nv[NM];
   loadrow(j0 - 1, Sv);
@@ -625,7 +634,7 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
 }
 
 // Single mesh: grid (strip groups, row chunks); block = lm_waves(N) wavefronts.
-template <int N, int EQ>
+template <int N, int EQ, bool BND>
 __global__ __launch_bounds__(64 * lm_waves(N), 2) void k_indicator_learned(LimitArgs a, LearnedArgs L, int rows) {
   static_assert(EQ == 1, "learned indicator: 2D Euler");
   using S = LmShape<N>;
@@ -637,7 +646,7 @@ __global__ __launch_bounds__(64 * lm_waves(N), 2) void k_indicator_learned(Limit
   const int x0 = (blockIdx.x * S::WAVES + wave) * kLmStrip;
   if (x0 >= g.nx) return;  // no barrier follows
   const int j0 = blockIdx.y * rows, j1 = min(j0 + rows, g.ny);
-  lm_strip<N>(a.u, g, x0, j0, j1, L, lds, lds + S::FEAT0 + wave * S::FEAT,
+  lm_strip<N, BND>(a.u, g, x0, j0, j1, L, lds, lds + S::FEAT0 + wave * S::FEAT,
               [&](bool active, bool flag, double mg, float p, long cell) {
                 if (active) {
                   if (L.prob) L.prob[cell] = p;

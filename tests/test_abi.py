@@ -131,10 +131,10 @@ def test_boundary_and_positivity_validation(dg):
     c.pad = 1
     with pytest.raises(dg.DGError):
         dg.workspace_bytes(c)
-    # batches take walls and inflow sides, not switches or the positivity scaling
+    # batches take periodic and transmissive sides only, without the scaling
     n = ctypes.c_size_t()
     e2 = dict(dim=2, equation=dg.EULER, order=2, nx=8, ny=8)
     cf = (dg.Config * 1)(dg.make_config(**dict(e2, bc=(dg.REFLECTIVE, 1, dg.REFLECTIVE, 1))))
-    assert dg.lib().dg_batch_workspace_bytes(cf, 1, ctypes.byref(n)) == 0
+    assert dg.lib().dg_batch_workspace_bytes(cf, 1, ctypes.byref(n)) == dg.DG_ERR_UNSUPPORTED
     cf = (dg.Config * 1)(dg.make_config(**dict(e2, bc=(1, 1, 1, 1), positivity=1)))
     assert dg.lib().dg_batch_workspace_bytes(cf, 1, ctypes.byref(n)) == dg.DG_ERR_UNSUPPORTED

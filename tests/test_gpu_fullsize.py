@@ -5,9 +5,10 @@ benchmark (dg_step replaying its captured step after dg_autotune):
 * 1D Euler shock/entropy-wave interaction, 4000 cells, P3;
 * 2D Burgers, 1024^2 cells, Q2, periodic.
 
-The GPU takes one SSP-RK3 step (CFL time step) of the whole mesh; sampled
-windows are then recomputed by the oracle from the same initial data and the
-GPU's time step.  One step with limiting after each stage reads at most six
+The initial state is the oracle's (projection in bands of rows, then one
+limiter pass over the whole mesh); the GPU takes one SSP-RK3 step (CFL time
+step) of the whole mesh from it; sampled windows are then recomputed by the
+oracle from the same initial data and the GPU's time step.  One step with limiting after each stage reads at most six
 cells in each direction (per stage: one for the residual, one for the
 limiter), so each window carries a six-cell halo (the true boundary condition
 where it meets the domain boundary, wrapped data on periodic domains) and
@@ -23,10 +24,27 @@ pytestmark = pytest.mark.gpu
 HALO = 6
 
 
-def _gpu_one_step(wl):
+def _oracle_initial_state(O, wl, band=128):
+    """Projection of the initial data by the oracle, band by band of rows
+    (each band a problem of its own: the projection is cell by cell), then
+    the limiter once on the whole mesh."""
+    from tests.dgutil import oracle_problem
+    full = oracle_problem(O, wl)
+    if wl.dim == 1:
+        return full.limit(full.project(wl.point_values(full.proj_nodes()[0])))[0]
+    U = full.zeros()
+    hy = (wl.y1 - wl.y0) / wl.ny
+    for j0 in range(0, wl.ny, band):
+        nr = min(band, wl.ny - j0)
+        sub = oracle_problem(O, wl, ny=nr, y0=wl.y0 + j0 * hy, y1=wl.y0 + (j0 + nr) * hy)
+        U[..., j0:j0 + nr, :] = sub.project(wl.point_values(sub.proj_nodes()[0], j0, nr))
+    return full.limit(U)[0]
+
+
+def _gpu_one_step(wl, O):
     from paper_1904_11147_amd import dg
     p = dg.problem_from_workload(wl)
-    u0 = dg.initial_state(p, wl, limit=True)
+    u0 = torch.from_numpy(_oracle_initial_state(O, wl)).cuda()
     p.autotune(u0)
     u1 = u0.clone()
     t, n = p.step(u1, 0.0, wl.t_end, max_steps=1)
@@ -80,7 +98,7 @@ def _window_2d(O, wl, u0, u1, dt, ja, ia, w):
 def test_riemann2d_2048_q2_full_size(oracle):
     from paper_1904_11147_amd import workloads as W
     wl = W.riemann2d(n=2048, order=2, seed=12345)
-    u0, u1, dt = _gpu_one_step(wl)
+    u0, u1, dt = _gpu_one_step(wl, oracle)
     rng = np.random.default_rng(7)
     wins = [(1024 - 12, 1024 - 12), (0, 0), (2048 - 24, 2048 - 24), (0, 1500), (1017, 0)]
     wins += [tuple(int(v) for v in rng.integers(0, 2048 - 24, size=2)) for _ in range(3)]
@@ -91,7 +109,7 @@ def test_riemann2d_2048_q2_full_size(oracle):
 def test_shu_osher_k4000_p3_full_size(oracle):
     from paper_1904_11147_amd import workloads as W
     wl = W.shu_osher()
-    u0, u1, dt = _gpu_one_step(wl)
+    u0, u1, dt = _gpu_one_step(wl, oracle)
     for a in (0, 90, 100, 1700, 3960):  # the shock sits near cell 100 (x = -4)
         _window_1d(oracle, wl, u0, u1, dt, a, a + 40)
 
@@ -99,6 +117,44 @@ def test_shu_osher_k4000_p3_full_size(oracle):
 def test_burgers2d_1024_q2_full_size(oracle):
     from paper_1904_11147_amd import workloads as W
     wl = W.burgers2d()
-    u0, u1, dt = _gpu_one_step(wl)
+    u0, u1, dt = _gpu_one_step(wl, oracle)
     for ja, ia in ((0, 0), (1024 - 20, 1024 - 20), (500, 3), (7, 800), (333, 666)):
         _window_2d(oracle, wl, u0, u1, dt, ja, ia, 20)
+
+
+def _window_dmr(O, wl, u0, u1, dt, ja, ia, w):
+    """Window of the double Mach reflection: sides on the domain boundary keep
+    their true kinds (inflow, wall, moving switch), inner sides are
+    transmissive (contaminated halo)."""
+    ny, nx = wl.ny, wl.nx
+    hx, hy = (wl.x1 - wl.x0) / nx, (wl.y1 - wl.y0) / ny
+    ilo, ihi = max(ia - HALO, 0), min(ia + w + HALO, nx)
+    jlo, jhi = max(ja - HALO, 0), min(ja + w + HALO, ny)
+    cfg = wl.config()
+    at_edge = (ilo == 0, ihi == nx, jlo == 0, jhi == ny)
+    bc = [wl.bc[k] if at_edge[k] else 1 for k in range(4)]
+    beyond = [cfg["bc_beyond"][k] if at_edge[k] else -1 for k in range(4)]
+    cfg.update(nx=ihi - ilo, ny=jhi - jlo, x0=wl.x0 + ilo * hx, x1=wl.x0 + ihi * hx, y0=wl.y0 + jlo * hy,
+               y1=wl.y0 + jhi * hy, bc=tuple(bc), bc_beyond=tuple(beyond))
+    op = O.Problem(**cfg)
+    U = np.ascontiguousarray(u0[..., jlo:jhi, ilo:ihi].cpu().numpy())
+    ref = op.step(U, dt)
+    oi, oj = ia - ilo, ja - jlo
+    got = u1[..., ja:ja + w, ia:ia + w].cpu().numpy()
+    assert_close(got, ref[..., oj:oj + w, oi:oi + w], what=f"{wl.name} window ({ja},{ia}) size {w}")
+
+
+def test_double_mach_1920x480_q2_full_size(oracle):
+    """The paper's finest double Mach mesh, one step from t = 0: windows on
+    the inflow west side, on both sides of the wall's start at x = 1/6, where
+    the shock meets the north side, and inside."""
+    from paper_1904_11147_amd import workloads as W
+    wl = W.double_mach(1920, order=2)
+    u0, u1, dt = _gpu_one_step(wl, oracle)
+    w = 24
+    foot = int(round(W.DMR_X0 * 480))  # the south side switches at column 80
+    top = int((W.DMR_X0 + 1.0 / np.sqrt(3.0)) * 480)  # the shock meets y = 1 near column 357
+    wins = [(0, 0), (0, foot - 12), (0, foot + 30), (480 - w, top - 12), (480 - w, 1920 - w), (200, 1000),
+            (100, 300), (480 - w, 0)]
+    for ja, ia in wins:
+        _window_dmr(oracle, wl, u0, u1, dt, ja, ia, w)
