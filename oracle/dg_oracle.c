@@ -21,7 +21,9 @@
  * invariants are pinned by tests/test_oracle_*.py; the reflective wall,
  * inflow and switching boundary sides by mirror images, periodic images and
  * stage-time checks (test_oracle_boundary.py); the positivity scaling by
- * bisection on its defining property (test_oracle_positivity.py).  The P3 treatment of the
+ * bisection on its defining property (test_oracle_positivity.py); the
+ * non-uniform mesh tables, residual, limiter and design order
+ * (test_oracle_nonuniform.py).  The P3 treatment of the
  * negative linear weights is "parity unpinned" (the paper does not say what
  * it does with them; see orc_weno_point).
  */
@@ -64,6 +66,9 @@ typedef struct {
   double bc_switch[4][2];   /* [side] {a, b} */
   double bc_state[4][2][4]; /* conserved ghost state of an inflow part [side][before, beyond][var] */
   double time;              /* time of the boundary data (orc_step: the step's start time) */
+  /* Non-uniform tensor-product meshes: node coordinates x_0 < ... < x_nx
+   * (and y_0 < ... < y_ny in 2D), or NULL for the uniform mesh on [x0,x1]. */
+  const double *xn, *yn;
 } orc_config;
 
 /* ------------------------------------------------------------------------ */
@@ -199,8 +204,9 @@ typedef struct {
 static orc_tables g_tab[ORC_MAXN + 1];
 static int g_tab_ready[ORC_MAXN + 1];
 
-static int build_tables(int N) {
-  orc_tables *T = &g_tab[N];
+/* Tables of order N for a troubled cell whose left and right neighbours are
+ * rl and rr times as wide as itself (1, 1 on a uniform mesh). */
+static int build_tables_into(orc_tables *T, int N, double rl, double rr) {
   memset(T, 0, sizeof(*T));
   T->N = N;
   T->np = N + 1;
@@ -224,10 +230,10 @@ static int build_tables(int N) {
    * Cells are numbered left to right. */
   int ns = 2 * N + 1;
   for (int k = 0; k < N; ++k) {
-    T->cl[k] = -1.5 + (double)k / N;
-    T->cr[k] = -1.5 + (double)(k + 1) / N;
-    T->cl[N + 1 + k] = 0.5 + (double)k / N;
-    T->cr[N + 1 + k] = 0.5 + (double)(k + 1) / N;
+    T->cl[k] = (-0.5 - rl) + k * rl / N;
+    T->cr[k] = (-0.5 - rl) + (k + 1) * rl / N;
+    T->cl[N + 1 + k] = 0.5 + k * rr / N;
+    T->cr[N + 1 + k] = 0.5 + (k + 1) * rr / N;
   }
   T->cl[N] = -0.5;
   T->cr[N] = 0.5;
@@ -335,8 +341,13 @@ static int build_tables(int N) {
     for (int G = 0; G < T->ng; ++G) T->bg[n][G] = psi(n, T->rg[G]);
     for (int a = 0; a < T->npq; ++a) T->bpq[n][a] = psi(n, T->rpq[a]);
   }
-  g_tab_ready[N] = 1;
   return ORC_OK;
+}
+
+static int build_tables(int N) {
+  int rc = build_tables_into(&g_tab[N], N, 1.0, 1.0);
+  if (rc == ORC_OK) g_tab_ready[N] = 1;
+  return rc;
 }
 
 static const orc_tables *tables(int N) {
@@ -444,6 +455,7 @@ typedef struct {
   double hx, hy;
   double kx_scale; /* KXRCF: 1 / h^((N+1)/2), h the radius of the cell's circumscribed circle */
   double time;     /* time of the boundary data */
+  const orc_tables *tx, *ty; /* non-uniform meshes: tables per column and per row (limiter only) */
 } orc_ctx;
 
 static int make_ctx(const orc_config *c, orc_ctx *x) {
@@ -459,6 +471,16 @@ static int make_ctx(const orc_config *c, orc_ctx *x) {
     if ((k == ORC_BC_REFLECTIVE || kb == ORC_BC_REFLECTIVE) && c->equation != ORC_EULER) return ORC_ERR_ARG;
   }
   if (c->positivity && c->equation != ORC_EULER) return ORC_ERR_ARG;
+  if (c->xn || c->yn) { /* tensor-product meshes: nodes increasing, no moving switches */
+    if (!c->xn || (c->dim == 2) != (c->yn != NULL)) return ORC_ERR_ARG;
+    for (int i = 0; i < c->nx; ++i)
+      if (!(c->xn[i + 1] > c->xn[i])) return ORC_ERR_ARG;
+    if (c->dim == 2)
+      for (int j = 0; j < c->ny; ++j)
+        if (!(c->yn[j + 1] > c->yn[j])) return ORC_ERR_ARG;
+    if (c->bc_beyond[2] >= 0 || c->bc_beyond[3] >= 0) return ORC_ERR_ARG;
+  }
+  x->tx = x->ty = NULL;
   x->c = c;
   x->time = c->time;
   x->T = tables(c->order);
@@ -476,6 +498,30 @@ static int make_ctx(const orc_config *c, orc_ctx *x) {
     x->kx_scale = 1.0 / pow(rad, 0.5 * (c->order + 1));
   }
   return ORC_OK;
+}
+
+/* Width of column i (i in [-1, nx]: a ghost column has the width of the cell
+ * it images, the periodic one or the mirrored adjacent one) and of row j. */
+static double cell_hx(const orc_ctx *x, int i) {
+  if (!x->c->xn) return x->hx;
+  if (i < 0) i = x->c->bc[0] == ORC_BC_PERIODIC ? i + x->nx : -1 - i;
+  else if (i >= x->nx) i = x->c->bc[1] == ORC_BC_PERIODIC ? i - x->nx : 2 * x->nx - 1 - i;
+  return x->c->xn[i + 1] - x->c->xn[i];
+}
+
+static double cell_hy(const orc_ctx *x, int j) {
+  if (!x->c->yn) return x->hy;
+  if (j < 0) j = x->c->bc[2] == ORC_BC_PERIODIC ? j + x->ny : -1 - j;
+  else if (j >= x->ny) j = x->c->bc[3] == ORC_BC_PERIODIC ? j - x->ny : 2 * x->ny - 1 - j;
+  return x->c->yn[j + 1] - x->c->yn[j];
+}
+
+/* KXRCF scale 1 / h^((N+1)/2) of cell (i, j), h its circumscribed radius. */
+static double cell_kx_scale(const orc_ctx *x, int i, int j) {
+  if (!x->c->xn) return x->kx_scale;
+  double hx = cell_hx(x, i), hy = cell_hy(x, j);
+  double rad = x->c->dim == 1 ? 0.5 * hx : 0.5 * sqrt(hx * hx + hy * hy);
+  return 1.0 / pow(rad, 0.5 * (x->c->order + 1));
 }
 
 static size_t at(const orc_ctx *x, int v, int q, int j, int i) {
@@ -630,7 +676,7 @@ static int residual_cell(const orc_ctx *x, const double *U, int i, int j, double
     for (int q = 0; q < x->nm; ++q) L[v][q] = 0.0;
 
   if (x->c->dim == 1) {
-    double sx = 2.0 / x->hx;
+    double sx = 2.0 / cell_hx(x, i);
     for (int q = 0; q < np; ++q) { /* volume term: sum_q w_q f(u_q) psi_n'(r_q) */
       for (int n = 0; n < np; ++n) br[n] = T->bq[n][q];
       point_value(x, C, br, NULL, a);
@@ -655,7 +701,7 @@ static int residual_cell(const orc_ctx *x, const double *U, int i, int j, double
     return bad;
   }
 
-  double sx = 2.0 / x->hx, sy = 2.0 / x->hy;
+  double sx = 2.0 / cell_hx(x, i), sy = 2.0 / cell_hy(x, j);
   for (int qx = 0; qx < np; ++qx)
     for (int qy = 0; qy < np; ++qy) {
       double w = T->wq[qx] * T->wq[qy];
@@ -760,7 +806,7 @@ static int indicator_cell(const orc_ctx *x, const double *U, int i, int j, doubl
   for (int v = 0; v < x->nv; ++v) mean[v] = C[v][0] * k0;
   int ndir = x->c->dim;
   for (int dir = 0; dir < ndir; ++dir) {
-    double h = dir == 0 ? x->hx : x->hy, Mh2 = x->c->tvb_M * h * h;
+    double h = dir == 0 ? cell_hx(x, i) : cell_hy(x, j), Mh2 = x->c->tvb_M * h * h;
     /* traces at the face midpoints of this direction */
     if (dir == 0) {
       point_value(x, C, x->T->bp, x->T->b0, up);
@@ -843,7 +889,7 @@ static int kxrcf_cell(const orc_ctx *x, const double *U, int i, int j, double *m
         J += a[v] - b[v];
         len += 1.0;
       } else {
-        const double flen = dir == 0 ? x->hy : x->hx;
+        const double flen = dir == 0 ? cell_hy(x, j) : cell_hx(x, i);
         double integral = 0.0;
         for (int e = 0; e < np; ++e) {
           double bs[ORC_MAXP], a[ORC_MAXV], b[ORC_MAXV];
@@ -873,7 +919,7 @@ static int kxrcf_cell(const orc_ctx *x, const double *U, int i, int j, double *m
         point_value(x, C, bx, by, a);
         norm = fmax(norm, fabs(a[v]));
       }
-    const double I = (len > 0.0 && norm > 0.0) ? fabs(J) * x->kx_scale / (len * norm) : 0.0;
+    const double I = (len > 0.0 && norm > 0.0) ? fabs(J) * cell_kx_scale(x, i, j) / (len * norm) : 0.0;
     flag |= I > 1.0;
     mg = fmin(mg, fabs(I - 1.0));
   }
@@ -983,8 +1029,12 @@ int orc_char_eig(const orc_config *c, const double *w, int dir, double *L, doubl
  * characteristic fields with L of that sweep's direction, evaluated at the
  * troubled cell's mean state, reconstructs every field with the same WENO
  * and maps the point values back with R. */
+/* Tables of the x-sweeps of column i and of the y-sweeps of row j. */
+static const orc_tables *col_tables(const orc_ctx *x, int i) { return x->tx ? &x->tx[i] : x->T; }
+static const orc_tables *row_tables(const orc_ctx *x, int j) { return x->ty ? &x->ty[j] : x->T; }
+
 static void limit_cell_char(const orc_ctx *x, const double *Uin, int i, int j, double *Uout) {
-  const orc_tables *T = x->T;
+  const orc_tables *T = col_tables(x, i), *Ty = row_tables(x, j);
   const int N = x->N, np = x->np, ns = 2 * N + 1, ng = T->ng, nv = x->nv;
   const double eps = x->c->weno_eps, k0 = cell_mean_factor(x);
   const int negw = x->c->negw_mode;
@@ -1074,7 +1124,7 @@ static void limit_cell_char(const orc_ctx *x, const double *Uin, int i, int j, d
         ch[f][iy] = s;
       }
     for (int f = 0; f < nv; ++f)
-      for (int H = 0; H < ng; ++H) cH[f][H] = orc_weno_point(T, H, ch[f], eps, negw);
+      for (int H = 0; H < ng; ++H) cH[f][H] = orc_weno_point(Ty, H, ch[f], eps, negw);
     for (int v = 0; v < nv; ++v)
       for (int H = 0; H < ng; ++H) {
         double s = 0.0;
@@ -1097,7 +1147,7 @@ static void limit_cell(const orc_ctx *x, const double *Uin, int i, int j, double
     limit_cell_char(x, Uin, i, j, Uout);
     return;
   }
-  const orc_tables *T = x->T;
+  const orc_tables *T = col_tables(x, i), *Ty = row_tables(x, j);
   int N = x->N, np = x->np, ns = 2 * N + 1, ng = T->ng;
   double eps = x->c->weno_eps;
   int negw = x->c->negw_mode;
@@ -1149,7 +1199,7 @@ static void limit_cell(const orc_ctx *x, const double *Uin, int i, int j, double
     for (int G = 0; G < ng; ++G) {
       double col[ORC_MAXS];
       for (int iy = 0; iy < ns; ++iy) col[iy] = vy[iy][G];
-      for (int H = 0; H < ng; ++H) u[G][H] = orc_weno_point(T, H, col, eps, negw);
+      for (int H = 0; H < ng; ++H) u[G][H] = orc_weno_point(Ty, H, col, eps, negw);
     }
     for (int q = 1; q < x->nm; ++q) {
       int m = q % np, n = q / np;
@@ -1165,8 +1215,32 @@ static int positivity_state(const orc_ctx *x, double *U, double *theta);
 
 /* Indicator + CSWENO with Jacobi semantics: every decision and every
  * reconstruction reads the state as it was before this call. */
-static int limit_state(const orc_ctx *x, double *U, double *work, uint8_t *flags_out, double *margin_out,
+static int limit_state(const orc_ctx *x0, double *U, double *work, uint8_t *flags_out, double *margin_out,
                        const uint8_t *flags_in) {
+  orc_ctx xl = *x0, *x = &xl;
+  orc_tables *tx = NULL, *ty = NULL;
+  if (x->c->xn && x->c->limiter != ORC_LIM_NONE) {
+    /* non-uniform mesh: the tables of every column and row, from the widths
+     * of the cell and of its two neighbours (Steps 2-3 on that stencil) */
+    tx = (orc_tables *)malloc(sizeof(orc_tables) * x->nx);
+    ty = x->c->dim == 2 ? (orc_tables *)malloc(sizeof(orc_tables) * x->ny) : NULL;
+    int bad = !tx || (x->c->dim == 2 && !ty);
+    for (int i = 0; !bad && i < x->nx; ++i) {
+      double h = cell_hx(x, i);
+      bad = build_tables_into(&tx[i], x->N, cell_hx(x, i - 1) / h, cell_hx(x, i + 1) / h) != ORC_OK;
+    }
+    for (int j = 0; !bad && x->c->dim == 2 && j < x->ny; ++j) {
+      double h = cell_hy(x, j);
+      bad = build_tables_into(&ty[j], x->N, cell_hy(x, j - 1) / h, cell_hy(x, j + 1) / h) != ORC_OK;
+    }
+    if (bad) {
+      free(tx);
+      free(ty);
+      return ORC_ERR_TABLE;
+    }
+    xl.tx = tx;
+    xl.ty = ty;
+  }
   size_t n = (size_t)x->nv * x->nm * x->ny * x->nx;
   memcpy(work, U, n * sizeof(double));
 #pragma omp parallel for schedule(dynamic, 4)
@@ -1182,6 +1256,8 @@ static int limit_state(const orc_ctx *x, double *U, double *work, uint8_t *flags
       if (margin_out) margin_out[k] = m;
       if (f && x->c->limiter != ORC_LIM_NONE) limit_cell(x, work, i, j, U);
     }
+  free(tx);
+  free(ty);
   return ORC_OK;
 }
 
@@ -1388,6 +1464,24 @@ int orc_max_speed(const orc_config *c, const double *U, double *sx, double *sy) 
 }
 
 int orc_cfl_dt(const orc_config *c, const double *U, double *dt) {
+  if (c->xn) { /* non-uniform: the largest spectral radius over width per direction */
+    orc_ctx x;
+    int rc = make_ctx(c, &x);
+    if (rc) return rc;
+    double k0 = cell_mean_factor(&x), mx = 0.0, my = 0.0;
+    int bad = 0;
+    for (int j = 0; j < x.ny; ++j)
+      for (int i = 0; i < x.nx; ++i) {
+        double u[ORC_MAXV];
+        for (int v = 0; v < x.nv; ++v) u[v] = U[at(&x, v, 0, j, i)] * k0;
+        mx = fmax(mx, spectral_radius(&x, 0, u, &bad) / cell_hx(&x, i));
+        if (c->dim == 2) my = fmax(my, spectral_radius(&x, 1, u, &bad) / cell_hy(&x, j));
+      }
+    if (bad) return ORC_ERR_NONPHYSICAL;
+    double den = mx + my;
+    *dt = den > 0.0 ? c->cfl / den : INFINITY;
+    return ORC_OK;
+  }
   double sx, sy;
   int rc = orc_max_speed(c, U, &sx, &sy);
   if (rc) return rc;
@@ -1527,9 +1621,8 @@ int orc_project(const orc_config *c, const double *pv, double *U) {
 /* Reconstruction rule, linear weights, the rows T_i[k] giving p_i(x_G) from
  * the stencil means, and the smoothness quadratic forms B_i (beta_i = a^T B_i a
  * over the cells of S_i), evaluated through the oracle's own routines. */
-int orc_weno_tables(int order, int32_t *ng, double *rg, double *wg, double *gam, double *rows, double *bmat,
-                    int32_t *split, double *gam_resid) {
-  const orc_tables *T = tables(order);
+static int weno_tables_of(const orc_tables *T, int order, int32_t *ng, double *rg, double *wg, double *gam,
+                          double *rows, double *bmat, int32_t *split, double *gam_resid) {
   if (!T) return ORC_ERR_ARG;
   int N = order, ns = 2 * N + 1;
   *ng = T->ng;
@@ -1574,6 +1667,30 @@ int orc_weno_tables(int order, int32_t *ng, double *rg, double *wg, double *gam,
         bmat[(i * (N + 1) + k) * (N + 1) + l] = v;
       }
   return ORC_OK;
+}
+
+int orc_weno_tables(int order, int32_t *ng, double *rg, double *wg, double *gam, double *rows, double *bmat,
+                    int32_t *split, double *gam_resid) {
+  return weno_tables_of(tables(order), order, ng, rg, wg, gam, rows, bmat, split, gam_resid);
+}
+
+/* The same for a troubled cell whose neighbours are rl and rr times as wide
+ * (non-uniform meshes); the stencil cells in units of the cell's width are
+ * returned in cl, cr (2N+1 each). */
+int orc_weno_tables_nu(int order, double rl, double rr, int32_t *ng, double *rg, double *wg, double *gam,
+                       double *rows, double *bmat, int32_t *split, double *gam_resid, double *cl, double *cr) {
+  if (order < 1 || order > ORC_MAXN || !(rl > 0.0) || !(rr > 0.0)) return ORC_ERR_ARG;
+  orc_tables *T = (orc_tables *)malloc(sizeof(orc_tables));
+  if (!T) return ORC_ERR_ARG;
+  int rc = build_tables_into(T, order, rl, rr);
+  if (!rc) rc = weno_tables_of(T, order, ng, rg, wg, gam, rows, bmat, split, gam_resid);
+  if (!rc)
+    for (int k = 0; k < 2 * order + 1; ++k) {
+      cl[k] = T->cl[k];
+      cr[k] = T->cr[k];
+    }
+  free(T);
+  return rc;
 }
 
 /* One WENO reconstruction through the oracle's own routine (pin tests). */

@@ -55,6 +55,8 @@ class OrcConfig(ctypes.Structure):
         ("bc_switch", (ctypes.c_double * 2) * 4),
         ("bc_state", ((ctypes.c_double * 4) * 2) * 4),
         ("time", ctypes.c_double),
+        ("xn", ctypes.POINTER(ctypes.c_double)),
+        ("yn", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -91,6 +93,8 @@ def lib():
             "orc_project": [cfgp, P(d), P(d)],
             "orc_weno_tables": [ctypes.c_int, P(i32), P(d), P(d), P(d), P(d), P(d), P(i32), P(d)],
             "orc_weno_eval": [ctypes.c_int, ctypes.c_int, P(d), d, ctypes.c_int, P(d)],
+            "orc_weno_tables_nu": [ctypes.c_int, d, d, P(i32), P(d), P(d), P(d), P(d), P(d), P(i32), P(d), P(d),
+                                   P(d)],
             "orc_subcell_means": [ctypes.c_int, P(d)],
             "orc_quadrature": [ctypes.c_int, ctypes.c_int, P(d), P(d)],
             "orc_basis": [ctypes.c_int, d, P(d), P(d)],
@@ -153,6 +157,9 @@ class Problem:
     # conserved inflow ghost states [side][before, beyond][var]
     bc_state: object = None
     time: float = 0.0
+    # non-uniform tensor-product mesh: node coordinates (nx+1, ny+1), or None
+    xn: object = None
+    yn: object = None
     _c: OrcConfig = field(default=None, repr=False)
 
     def __post_init__(self):
@@ -174,6 +181,15 @@ class Problem:
                 for v in range(4):
                     c.bc_state[k][a][v] = float(st[k, a, v])
         c.time = float(self.time)
+        self._nodes = []
+        for name, n in (("xn", self.nx), ("yn", self.ny)):
+            arr = getattr(self, name)
+            if arr is None:
+                continue
+            arr = np.ascontiguousarray(arr, dtype=np.float64)
+            assert arr.shape == (n + 1,), (name, arr.shape)
+            self._nodes.append(arr)  # keeps the memory alive with the config
+            setattr(c, name, _dp(arr))
         self._c = c
 
     def at_time(self, t):
@@ -299,12 +315,20 @@ class Problem:
     def node_coords(self):
         """Physical coordinates of the projection nodes: (X[qx, i], Y[qy, j])."""
         r, _ = self.proj_nodes()
-        i = np.arange(self.nx)
-        X = self.x0 + (i[None, :] + 0.5 * (1.0 + r[:, None])) * self.hx
+        if self.xn is not None:
+            xn = np.asarray(self.xn)
+            X = xn[None, :-1] + 0.5 * (1.0 + r[:, None]) * np.diff(xn)[None, :]
+        else:
+            i = np.arange(self.nx)
+            X = self.x0 + (i[None, :] + 0.5 * (1.0 + r[:, None])) * self.hx
         if self.dim == 1:
             return X, None
-        j = np.arange(self.ny)
-        Y = self.y0 + (j[None, :] + 0.5 * (1.0 + r[:, None])) * self.hy
+        if self.yn is not None:
+            yn = np.asarray(self.yn)
+            Y = yn[None, :-1] + 0.5 * (1.0 + r[:, None]) * np.diff(yn)[None, :]
+        else:
+            j = np.arange(self.ny)
+            Y = self.y0 + (j[None, :] + 0.5 * (1.0 + r[:, None])) * self.hy
         return X, Y
 
     def project(self, pv):
@@ -317,7 +341,11 @@ class Problem:
 
 # -- table introspection (pin tests) -----------------------------------------
 
-def weno_tables(order):
+def weno_tables(order, rl=None, rr=None):
+    """Linear weights, rows p_i(x_G) over the stencil means and the beta
+    quadratic forms; with rl, rr the stencil of a cell whose left / right
+    neighbours are rl / rr times as wide (non-uniform meshes), which also
+    returns the stencil cells (in units of the cell's width)."""
     N = order
     ns = 2 * N + 1
     ng = ctypes.c_int32()
@@ -327,12 +355,19 @@ def weno_tables(order):
     bmat = np.zeros((N + 1) ** 3)
     split = np.zeros(4, dtype=np.int32)
     resid = ctypes.c_double()
-    rc = lib().orc_weno_tables(order, ctypes.byref(ng), _dp(rg), _dp(wg), _dp(gam), _dp(rows), _dp(bmat),
-                               split.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(resid))
+    cl, cr = np.zeros(7), np.zeros(7)
+    if rl is None:
+        rc = lib().orc_weno_tables(order, ctypes.byref(ng), _dp(rg), _dp(wg), _dp(gam), _dp(rows), _dp(bmat),
+                                   split.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(resid))
+    else:
+        rc = lib().orc_weno_tables_nu(order, float(rl), float(rr), ctypes.byref(ng), _dp(rg), _dp(wg), _dp(gam),
+                                      _dp(rows), _dp(bmat), split.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      ctypes.byref(resid), _dp(cl), _dp(cr))
     if rc:
         raise OracleError(rc, "weno_tables")
     G = ng.value
     return dict(
+        cells=np.stack([cl[:ns], cr[:ns]], axis=1).copy(),
         rg=rg[:G].copy(), wg=wg[:G].copy(),
         gamma=gam[: G * (N + 1)].reshape(G, N + 1).copy(),
         rows=rows[: G * (N + 1) * ns].reshape(G, N + 1, ns).copy(),

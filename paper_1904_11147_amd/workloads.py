@@ -74,6 +74,8 @@ class Workload:
     # boundary switches, inflow states and positivity scaling, as keyword
     # arguments of a problem (bc_beyond, bc_switch, bc_state, positivity)
     bc_extra: dict = field(default_factory=dict)
+    # non-uniform tensor-product mesh: {"xn": nodes (nx+1), "yn": nodes (ny+1)}
+    mesh: dict = field(default_factory=dict)
 
     @property
     def nv(self):
@@ -100,8 +102,30 @@ class Workload:
                  x0=self.x0, x1=self.x1, y0=self.y0, y1=self.y1, bc=tuple(self.bc), gamma=self.gamma,
                  cfl=self.cfl)
         d.update(self.bc_extra)
+        d.update(self.mesh)
         d.update(over)
         return d
+
+    def nonuniform(self, seed, frac=0.1):
+        """The same problem on a mesh whose interior nodes are moved by up to
+        frac of the uniform width, uniformly at random (the paper's accuracy
+        tests use 10%); the end nodes stay on the domain boundary."""
+        mesh = {"xn": perturbed_nodes(self.nx, self.x0, self.x1, seed, frac)}
+        if self.dim == 2:
+            mesh["yn"] = perturbed_nodes(self.ny, self.y0, self.y1, seed + 1, frac)
+        return replace(self, name=f"{self.name}_nu{seed}", mesh=mesh)
+
+    def _nodes(self, r, axis, j0=0, nrows=None):
+        """Physical coordinates [q, cell] of the reference nodes r in every
+        column (axis 0) or in rows j0.. (axis 1)."""
+        key, lo, hi, n = ("xn", self.x0, self.x1, self.nx) if axis == 0 else ("yn", self.y0, self.y1, self.ny)
+        idx = np.arange(n) if axis == 0 else np.arange(j0, j0 + nrows)
+        if key in self.mesh:
+            nodes = np.asarray(self.mesh[key], dtype=np.float64)
+            left, width = nodes[idx], nodes[idx + 1] - nodes[idx]
+            return left[None, :] + 0.5 * (1.0 + r[:, None]) * width[None, :]
+        h = (hi - lo) / n
+        return lo + (idx[None, :] + 0.5 * (1.0 + r[:, None])) * h
 
     def point_values(self, r_nodes, j0=0, nrows=None):
         """Initial data at the projection nodes r_nodes (reference coordinate in
@@ -109,17 +133,13 @@ class Workload:
 
         Returns an array [nv][nq_y][nq_x][nrows][nx] (1D: [nv][nq][1][nx])."""
         r = np.asarray(r_nodes, dtype=np.float64)
-        hx = (self.x1 - self.x0) / self.nx
-        i = np.arange(self.nx)
-        X = self.x0 + (i[None, :] + 0.5 * (1.0 + r[:, None])) * hx  # [q, i]
+        X = self._nodes(r, 0)  # [q, i]
         if self.dim == 1:
             vals = self.ic(X, None)
             return np.ascontiguousarray(np.stack([np.asarray(v, dtype=np.float64) for v in vals])[:, :, None, :])
         if nrows is None:
             nrows = self.ny - j0
-        hy = (self.y1 - self.y0) / self.ny
-        j = np.arange(j0, j0 + nrows)
-        Y = self.y0 + (j[None, :] + 0.5 * (1.0 + r[:, None])) * hy  # [q, j]
+        Y = self._nodes(r, 1, j0, nrows)  # [q, j]
         XX = X[None, :, None, :]  # [qy, qx, j, i]
         YY = Y[:, None, :, None]
         XX, YY = np.broadcast_arrays(XX, YY)
@@ -132,7 +152,7 @@ class Workload:
         data (whose quadrant test separates into an x and a y part); None for
         other workloads.  Each node's conserved values are the same numbers
         point_values gives."""
-        if "states" not in self.extra or self.dim != 2:
+        if "states" not in self.extra or self.dim != 2 or self.mesh:
             return None
         import torch
         st = self.extra["states"]
@@ -149,6 +169,16 @@ class Workload:
                 for q in QUADRANTS}
         return torch.where(north, torch.where(east, cons["NE"], cons["NW"]),
                            torch.where(east, cons["SE"], cons["SW"])).contiguous()
+
+
+def perturbed_nodes(n, x0, x1, seed, frac=0.1):
+    """Nodes of [x0, x1] in n cells, the n-1 interior ones moved by a uniform
+    random fraction in [-frac, frac] of the uniform width (seeded)."""
+    h = (x1 - x0) / n
+    nodes = x0 + h * np.arange(n + 1, dtype=np.float64)
+    nodes[1:-1] += frac * h * np.random.default_rng(seed).uniform(-1.0, 1.0, n - 1)
+    nodes[0], nodes[-1] = x0, x1
+    return nodes
 
 
 # ---------------------------------------------------------------------------

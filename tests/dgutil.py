@@ -63,6 +63,7 @@ def oracle_problem(O, wl, **over):
     kw = dict(dim=wl.dim, equation=wl.equation, order=wl.order, nx=wl.nx, ny=wl.ny, x0=wl.x0, x1=wl.x1,
               y0=wl.y0, y1=wl.y1, bc=tuple(wl.bc), gamma=wl.gamma, cfl=wl.cfl)
     kw.update(wl.bc_extra)
+    kw.update(wl.mesh)
     kw.update(over)
     return O.Problem(**kw)
 
