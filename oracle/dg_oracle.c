@@ -169,6 +169,40 @@ static int solve_dense(int n, double *A, double *b) { /* A row-major n x n, b ov
   return 0;
 }
 
+static int solve_dense_ld(int n, long double *A, long double *b) { /* as solve_dense, in long double */
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (fabsl(A[r * n + c]) > fabsl(A[p * n + c])) p = r;
+    if (A[p * n + c] == 0.0L) return -1;
+    if (p != c) {
+      for (int k = 0; k < n; ++k) {
+        long double t = A[c * n + k];
+        A[c * n + k] = A[p * n + k];
+        A[p * n + k] = t;
+      }
+      long double t = b[c];
+      b[c] = b[p];
+      b[p] = t;
+    }
+    for (int r = c + 1; r < n; ++r) {
+      long double f = A[r * n + c] / A[c * n + c];
+      for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    long double s = b[r];
+    for (int k = r + 1; k < n; ++k) s -= A[r * n + k] * b[k];
+    b[r] = s / A[r * n + r];
+  }
+  return 0;
+}
+
+static long double mono_mean_ld(int d, long double a, long double b) {
+  return (powl(b, d + 1) - powl(a, d + 1)) / ((d + 1.0L) * (b - a));
+}
+
 /* Mean of xi^d over [a,b]. */
 static double mono_mean(int d, double a, double b) {
   return (pow(b, d + 1) - pow(a, d + 1)) / ((d + 1.0) * (b - a));
@@ -239,66 +273,73 @@ static int build_tables_into(orc_tables *T, int N, double rl, double rr) {
   T->cr[N] = 0.5;
 
   /* Step 2: p_i of degree N whose means on the N+1 cells of S_i = cells
-   * i..i+N equal the data, and Q of degree 2N on all 2N+1 cells. */
+   * i..i+N equal the data, and Q of degree 2N on all 2N+1 cells.  The small
+   * systems are solved in long double (the moment matrices of the 7-cell P3
+   * stencil lose about three digits), the results rounded once. */
+  long double Ainv[ORC_MAXP][ORC_MAXP][ORC_MAXP];
   for (int i = 0; i <= N; ++i) {
     for (int k = 0; k <= N; ++k) {
-      double A[ORC_MAXP * ORC_MAXP], e[ORC_MAXP];
+      long double A[ORC_MAXP * ORC_MAXP], e[ORC_MAXP];
       for (int r = 0; r <= N; ++r)
-        for (int d = 0; d <= N; ++d) A[r * (N + 1) + d] = mono_mean(d, T->cl[i + r], T->cr[i + r]);
-      for (int r = 0; r <= N; ++r) e[r] = (r == k) ? 1.0 : 0.0;
-      if (solve_dense(N + 1, A, e)) return ORC_ERR_TABLE;
-      for (int d = 0; d <= N; ++d) T->Ainv[i][d][k] = e[d];
+        for (int d = 0; d <= N; ++d) A[r * (N + 1) + d] = mono_mean_ld(d, T->cl[i + r], T->cr[i + r]);
+      for (int r = 0; r <= N; ++r) e[r] = (r == k) ? 1.0L : 0.0L;
+      if (solve_dense_ld(N + 1, A, e)) return ORC_ERR_TABLE;
+      for (int d = 0; d <= N; ++d) {
+        Ainv[i][d][k] = e[d];
+        T->Ainv[i][d][k] = (double)e[d];
+      }
     }
   }
-  double AQinv[ORC_MAXS][ORC_MAXS];
+  long double AQinv[ORC_MAXS][ORC_MAXS];
   for (int k = 0; k < ns; ++k) {
-    double A[ORC_MAXS * ORC_MAXS], e[ORC_MAXS];
+    long double A[ORC_MAXS * ORC_MAXS], e[ORC_MAXS];
     for (int r = 0; r < ns; ++r)
-      for (int d = 0; d < ns; ++d) A[r * ns + d] = mono_mean(d, T->cl[r], T->cr[r]);
-    for (int r = 0; r < ns; ++r) e[r] = (r == k) ? 1.0 : 0.0;
-    if (solve_dense(ns, A, e)) return ORC_ERR_TABLE;
+      for (int d = 0; d < ns; ++d) A[r * ns + d] = mono_mean_ld(d, T->cl[r], T->cr[r]);
+    for (int r = 0; r < ns; ++r) e[r] = (r == k) ? 1.0L : 0.0L;
+    if (solve_dense_ld(ns, A, e)) return ORC_ERR_TABLE;
     for (int d = 0; d < ns; ++d) AQinv[d][k] = e[d];
   }
 
   /* Step 3: linear weights with Q(x_G) = sum_i gamma_i p_i(x_G) for every
    * data vector, i.e. 2N+1 equations in N+1 unknowns, solved in the least
-   * squares sense; the residual is recorded and must vanish. */
+   * squares sense (normal equations, long double); the residual is recorded
+   * and must vanish. */
   T->gam_resid = 0.0;
   for (int G = 0; G < T->ng; ++G) {
-    double xi = 0.5 * T->rg[G];
-    double M[ORC_MAXS][ORC_MAXP], rhs[ORC_MAXS];
+    long double xi = 0.5L * T->rg[G];
+    long double M[ORC_MAXS][ORC_MAXP], rhs[ORC_MAXS];
     for (int k = 0; k < ns; ++k) {
-      double q = 0.0;
-      for (int d = 0; d < ns; ++d) q += AQinv[d][k] * pow(xi, d);
+      long double q = 0.0L;
+      for (int d = 0; d < ns; ++d) q += AQinv[d][k] * powl(xi, d);
       rhs[k] = q;
       for (int i = 0; i <= N; ++i) {
-        double t = 0.0;
+        long double t = 0.0L;
         if (k >= i && k <= i + N)
-          for (int d = 0; d <= N; ++d) t += T->Ainv[i][d][k - i] * pow(xi, d);
+          for (int d = 0; d <= N; ++d) t += Ainv[i][d][k - i] * powl(xi, d);
         M[k][i] = t;
       }
     }
-    double NtN[ORC_MAXP * ORC_MAXP], Ntb[ORC_MAXP];
+    long double NtN[ORC_MAXP * ORC_MAXP], Ntb[ORC_MAXP];
     for (int a = 0; a <= N; ++a) {
-      Ntb[a] = 0.0;
+      Ntb[a] = 0.0L;
       for (int k = 0; k < ns; ++k) Ntb[a] += M[k][a] * rhs[k];
       for (int b = 0; b <= N; ++b) {
-        double s = 0.0;
-        for (int k = 0; k < ns; ++k) s += M[k][a] * M[k][b];
-        NtN[a * (N + 1) + b] = s;
+        long double s2 = 0.0L;
+        for (int k = 0; k < ns; ++k) s2 += M[k][a] * M[k][b];
+        NtN[a * (N + 1) + b] = s2;
       }
     }
-    if (solve_dense(N + 1, NtN, Ntb)) return ORC_ERR_TABLE;
+    if (solve_dense_ld(N + 1, NtN, Ntb)) return ORC_ERR_TABLE;
     int neg = 0;
     for (int i = 0; i <= N; ++i) {
-      T->gam[G][i] = Ntb[i];
-      if (Ntb[i] < 0.0) neg = 1;
+      T->gam[G][i] = (double)Ntb[i];
+      if (Ntb[i] < 0.0L) neg = 1;
     }
     T->split[G] = neg;
     for (int k = 0; k < ns; ++k) {
-      double s = -rhs[k];
-      for (int i = 0; i <= N; ++i) s += M[k][i] * T->gam[G][i];
-      if (fabs(s) > T->gam_resid) T->gam_resid = fabs(s);
+      long double s2 = -rhs[k];
+      for (int i = 0; i <= N; ++i) s2 += M[k][i] * Ntb[i];
+      if (fabsl(s2) > T->gam_resid) T->gam_resid = (double)fabsl(s2);
     }
   }
   if (T->gam_resid > 1e-10) return ORC_ERR_TABLE;
