@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define DG_ABI_VERSION 2
+#define DG_ABI_VERSION 3
 
 enum {
   DG_OK = 0,
@@ -117,6 +117,18 @@ typedef struct dg_config {
   int32_t pad;              /* must be 0 */
   double bc_switch[4][2];
   double bc_state[4][2][4]; /* conserved inflow states [side][before, beyond][variable] */
+  /* Non-uniform tensor-product meshes (the accuracy tests of Sec. 4 move every
+   * node of the uniform mesh): host arrays of nx+1 (x_nodes) and ny+1
+   * (y_nodes, 2D) strictly increasing node coordinates, or NULL for the
+   * uniform mesh on [x0,x1] x [y0,y1].  Cells stay rectangles; each column
+   * and row has its own width, TVB threshold M h^2, KXRCF radius and CSWENO
+   * tables (Steps 2-4 on the stencil of the cell and its two neighbours; a
+   * ghost column has the width of the cell it images); the CFL rule becomes
+   * dt = cfl / (max S_x/h_x + max S_y/h_y) over the cells.  Read by
+   * dg_workspace_bytes and dg_init only (dg_init copies what it needs into the
+   * workspace).  Not with DG_IND_LEARNED, switching sides or batches. */
+  const double *x_nodes;
+  const double *y_nodes;
 } dg_config;
 
 typedef struct dg_problem dg_problem;

@@ -7,6 +7,7 @@
 #include <limits>
 #include <mutex>
 #include <new>
+#include <vector>
 
 #include "dg_internal.h"
 
@@ -83,6 +84,15 @@ int validate_config(const dg_config *c) {
   if ((c->bc[0] == DG_BC_PERIODIC) != (c->bc[1] == DG_BC_PERIODIC)) return DG_ERR_INVALID_ARG;
   if (c->dim == 2 && (c->bc[2] == DG_BC_PERIODIC) != (c->bc[3] == DG_BC_PERIODIC)) return DG_ERR_INVALID_ARG;
   if (c->positivity != 0 && c->positivity != 1) return DG_ERR_INVALID_ARG;
+  if (c->x_nodes || c->y_nodes) {  // non-uniform tensor-product mesh
+    if (!c->x_nodes || (c->dim == 2) != (c->y_nodes != nullptr)) return DG_ERR_INVALID_ARG;
+    for (int i = 0; i <= c->nx; ++i)
+      if (!std::isfinite(c->x_nodes[i]) || (i > 0 && !(c->x_nodes[i] > c->x_nodes[i - 1]))) return DG_ERR_INVALID_ARG;
+    if (c->dim == 2)
+      for (int j = 0; j <= c->ny; ++j)
+        if (!std::isfinite(c->y_nodes[j]) || (j > 0 && !(c->y_nodes[j] > c->y_nodes[j - 1]))) return DG_ERR_INVALID_ARG;
+    if (c->indicator == DG_IND_LEARNED || c->bc_beyond[2] >= 0 || c->bc_beyond[3] >= 0) return DG_ERR_UNSUPPORTED;
+  }
   if (c->positivity && c->equation != DG_EQ_EULER) return DG_ERR_UNSUPPORTED;
   if (c->limiter != DG_LIM_NONE && c->limiter != DG_LIM_CSWENO && c->limiter != DG_LIM_CSWENO_CHAR)
     return DG_ERR_INVALID_ARG;
@@ -119,6 +129,7 @@ int ensure_tables(int device) {
 }
 
 bool special_bc(const Geometry &g) {
+  if (g.hxa) return true;  // non-uniform mesh
   for (int k = 0; k < 4; ++k)
     if (g.bc[k] == DG_BC_REFLECTIVE || g.bc[k] == DG_BC_INFLOW || g.bcb[k] >= 0) return true;
   return false;
@@ -154,6 +165,9 @@ void fill_geometry(const dg_config *cfg, Geometry *g) {
       for (int v = 0; v < 4; ++v) g->bst[2 * k + part][v] = cfg->bc_state[k][part][v] / k0;
   }
   g->tb = nullptr;
+  g->tvb_M = cfg->tvb_M;
+  g->hxa = g->hya = g->rhxa = g->rhya = g->mhx = g->mhy = nullptr;
+  g->wtx = g->wty = nullptr;
 }
 
 }  // namespace dg
@@ -167,7 +181,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t scalars, bufA, bufB, flags, margin, list, total;
+  size_t scalars, bufA, bufB, flags, margin, list, mesh, total;
 };
 
 Layout layout(const dg_config *c) {
@@ -187,8 +201,60 @@ Layout layout(const dg_config *c) {
   off += align_up(cells * sizeof(double));
   L.list = off;
   off += align_up(cells * sizeof(int32_t));
+  L.mesh = off;  // non-uniform meshes: 3 arrays and the tables per column and per row
+  if (c->x_nodes) {
+    const size_t lines = (size_t)c->nx + (c->dim == 2 ? c->ny : 0);
+    off += align_up(3 * lines * sizeof(double)) + align_up(lines * sizeof(dg::WenoCoef));
+  }
   L.total = off;
   return L;
+}
+
+// Width of column i of nodes e[0..n] with the ghost rule of the boundary
+// sides lo/hi: the periodic image or the mirrored adjacent cell.
+double line_width(const double *e, int n, int i, int bc_lo, int bc_hi) {
+  if (i < 0) i = bc_lo == DG_BC_PERIODIC ? i + n : -1 - i;
+  else if (i >= n) i = bc_hi == DG_BC_PERIODIC ? i - n : 2 * n - 1 - i;
+  return e[i + 1] - e[i];
+}
+
+// Uploads widths, 2/width, M width^2 and the CSWENO tables of every column
+// (and row) into the workspace and points the geometry at them.
+int upload_mesh(const dg_config *c, char *ws, const Layout &L, hipStream_t st, dg::Geometry *g) {
+  const int lines_x = c->nx, lines_y = c->dim == 2 ? c->ny : 0, lines = lines_x + lines_y;
+  std::vector<double> arr(3 * (size_t)lines);
+  std::vector<dg::WenoCoef> tab(lines);
+  for (int d = 0; d < (c->dim == 2 ? 2 : 1); ++d) {
+    const double *e = d == 0 ? c->x_nodes : c->y_nodes;
+    const int n = d == 0 ? c->nx : c->ny, off = d == 0 ? 0 : lines_x;
+    const int lo = c->bc[2 * d], hi = c->bc[2 * d + 1];
+    for (int i = 0; i < n; ++i) {
+      const double h = e[i + 1] - e[i];
+      arr[off + i] = h;
+      arr[lines + off + i] = 2.0 / h;
+      arr[2 * lines + off + i] = c->tvb_M * h * h;
+      int rc = dg::build_weno_coef(c->order, line_width(e, n, i - 1, lo, hi) / h, line_width(e, n, i + 1, lo, hi) / h,
+                                   &tab[off + i]);
+      if (rc) return rc;
+    }
+  }
+  double *dv = (double *)(ws + L.mesh);
+  dg::WenoCoef *dt = (dg::WenoCoef *)(ws + L.mesh + align_up(3 * (size_t)lines * sizeof(double)));
+  if (hipMemcpyAsync(dv, arr.data(), arr.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(dt, tab.data(), tab.size() * sizeof(dg::WenoCoef), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return DG_ERR_HIP;
+  g->hxa = dv;
+  g->rhxa = dv + lines;
+  g->mhx = dv + 2 * lines;
+  g->wtx = dt;
+  if (lines_y) {
+    g->hya = dv + lines_x;
+    g->rhya = dv + lines + lines_x;
+    g->mhy = dv + 2 * lines + lines_x;
+    g->wty = dt + lines_x;
+  }
+  return DG_OK;
 }
 
 int hip_ok(hipError_t e) { return e == hipSuccess ? DG_OK : DG_ERR_HIP; }
@@ -317,6 +383,7 @@ int dg_init(const dg_config *cfg, void *workspace, size_t workspace_bytes, void 
   dg_problem *p = new (std::nothrow) dg_problem();
   if (!p) return DG_ERR_INVALID_ARG;
   p->cfg = *cfg;
+  p->cfg.x_nodes = p->cfg.y_nodes = nullptr;  // caller memory: read here only
   p->device = device;
   p->user_stream = (hipStream_t)stream;
   p->ws_bytes = workspace_bytes;
@@ -340,6 +407,13 @@ int dg_init(const dg_config *cfg, void *workspace, size_t workspace_bytes, void 
   c.limiter = cfg->limiter;
   c.indicator = cfg->indicator;
   c.positivity = cfg->positivity;
+  if (cfg->x_nodes) {
+    rc = upload_mesh(cfg, ws, L, p->user_stream, &c.geo);
+    if (rc) {
+      delete p;
+      return rc;
+    }
+  }
   c.timed_bc = 0;
   for (int k = 2; k < 4; ++k)
     if (c.geo.bcb[k] >= 0 && c.geo.bsw[k][1] != 0.0) c.timed_bc = 1;
@@ -430,10 +504,12 @@ int dg_cfl_dt(dg_problem *p, const double *state, double *dt) {
   std::memcpy(&sx, &h.smax[0], sizeof(double));
   std::memcpy(&sy, &h.smax[1], sizeof(double));
   const double inf = std::numeric_limits<double>::infinity();
+  const bool nu = p->ctx.geo.hxa != nullptr;  // speeds are already per width
+  const double hx = nu ? 1.0 : p->ctx.geo.hx, hy = nu ? 1.0 : p->ctx.geo.hy;
   if (p->cfg.dim == 1) {
-    *dt = sx > 0.0 ? p->cfg.cfl * p->ctx.geo.hx / sx : inf;
+    *dt = sx > 0.0 ? p->cfg.cfl * hx / sx : inf;
   } else {
-    double den = sx / p->ctx.geo.hx + sy / p->ctx.geo.hy;
+    double den = sx / hx + sy / hy;
     *dt = den > 0.0 ? p->cfg.cfl / den : inf;
   }
   return rc;

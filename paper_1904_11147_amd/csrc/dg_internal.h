@@ -37,6 +37,20 @@ struct OrderTables {
 // Builds the tables of order N (1..3) on the host.  Returns 0 or a DG_ERR code.
 int build_order_tables(int N, OrderTables *out);
 
+// The stencil-dependent part of the tables (members named as in
+// OrderTables) for a troubled cell whose left and right neighbours are rl and
+// rr times as wide as itself: non-uniform meshes keep one per column (x
+// sweeps) and one per row (y sweeps).
+struct WenoCoef {
+  double T[kMaxG][kMaxP][kMaxP];
+  double gam[kMaxG][kMaxP];
+  int32_t split[kMaxG];
+  double gpn[kMaxG][kMaxP], gmn[kMaxG][kMaxP];
+  double sp[kMaxG], sm[kMaxG];
+  double B[kMaxP][kMaxP][kMaxP];
+};
+int build_weno_coef(int N, double rl, double rr, WenoCoef *out);
+
 // Uploads tables of all orders to the current device (kernel TU).
 int upload_tables(const OrderTables *tabs /* [kMaxN+1], index N */);
 
@@ -69,6 +83,11 @@ struct Geometry {
   int32_t negw_raw;
   int32_t pad;
   double kx_scale;  // KXRCF: 1 / h^((N+1)/2), h the cell's circumscribed radius
+  double tvb_M;
+  // non-uniform tensor-product meshes (device, null on uniform meshes): per
+  // column / row width, 2 / width, M width^2 and the stencil tables
+  const double *hxa, *hya, *rhxa, *rhya, *mhx, *mhy;
+  const WenoCoef *wtx, *wty;
   double x0;        // west end of the mesh
   int32_t bcb[4];   // south/north: kind beyond the switch point, -1 none
   double bsw[4][2]; // switch at bsw[s][0] + bsw[s][1] * t (x along the side)

@@ -207,6 +207,18 @@ __device__ inline void load_cell(const double *__restrict__ u, long plane, const
     for (int q = 0; q < NM; ++q) C[v][q] = cell_mode<NP, NM, DIM>(u, plane, g, c, v, q);
 }
 
+// Per-column / per-row geometry of non-uniform meshes (uniform: the scalars).
+__device__ inline double rh_x(const Geometry &g, int i) {
+  return g.rhxa ? g.rhxa[min(max(i, 0), g.nx - 1)] : g.rhx;
+}
+__device__ inline double rh_y(const Geometry &g, int j) {
+  return g.rhya ? g.rhya[min(max(j, 0), g.ny - 1)] : g.rhy;
+}
+// A spectral radius over the cell width on non-uniform meshes, whose CFL rule
+// then takes unit widths; unchanged on uniform meshes.
+__device__ inline double per_wx(const Geometry &g, int i, double s) { return g.hxa ? s / g.hxa[i] : s; }
+__device__ inline double per_wy(const Geometry &g, int j, double s) { return g.hya ? s / g.hya[j] : s; }
+
 // ---------------------------------------------------------------------------
 // Residual + SSP-RK3 stage.  STAGE 0: out = L(u).  1: u + dt L.  2: 3/4 un +
 // 1/4 (u + dt L).  3: 1/3 un + 2/3 (u + dt L).
@@ -232,6 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_1d(StageArgs a) {
   bool bad = false;
   double spd = 0.0;
   if (i < g.nx) {
+    const double rx = rh_x(g, i);
     double C[NV][NP], Nb[NV][NP], L[NV][NP];
     load_cell<NP, NP, NV, 1>(a.u, plane, g, map_cell(g, i, 0), C);
 #pragma unroll
@@ -252,7 +265,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_1d(StageArgs a) {
       P::template flux<0>(uq, f, g.gamma, bad);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        double fw = g.rhx * T.wq[q] * f[v];
+        double fw = rx * T.wq[q] * f[v];
 #pragma unroll
         for (int n = 0; n < NP; ++n) L[v][n] += fw * T.dbq[n][q];
       }
@@ -275,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_1d(StageArgs a) {
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
-      for (int n = 0; n < NP; ++n) L[v][n] -= g.rhx * F[v] * T.bp[n];
+      for (int n = 0; n < NP; ++n) L[v][n] -= rx * F[v] * T.bp[n];
     load_cell<NP, NP, NV, 1>(a.u, plane, g, map_cell(g, i - 1, 0), Nb);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -292,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_1d(StageArgs a) {
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
-      for (int n = 0; n < NP; ++n) L[v][n] += g.rhx * F[v] * T.bm[n];
+      for (int n = 0; n < NP; ++n) L[v][n] += rx * F[v] * T.bm[n];
 
     const double dt = STAGE == 0 ? 0.0 : a.sc->dt;
     double mean[NV];
@@ -309,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_1d(StageArgs a) {
         a.out[k] = r;
         if (n == 0) mean[v] = r * T.b0[0];
       }
-    if (STAGE == 3 && a.want_speed) spd = P::template speed<0>(mean, g.gamma, bad);
+    if (STAGE == 3 && a.want_speed) spd = per_wx(g, i, P::template speed<0>(mean, g.gamma, bad));
   }
   if (bad) atomicOr(&a.sc->status, 1);
   if (STAGE == 3 && a.want_speed) {
@@ -370,8 +383,8 @@ __global__ __launch_bounds__(kBlock) void k_stage_2d(StageArgs a) {
         double w = T.wq[qx] * T.wq[qy];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          Fx[v][qx] = w * g.rhx * f[v];
-          Gy[v][qx] = w * g.rhy * gg[v];
+          Fx[v][qx] = w * rh_x(g, i) * f[v];
+          Gy[v][qx] = w * rh_y(g, j) * gg[v];
         }
       }
 #pragma unroll
@@ -445,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_2d(StageArgs a) {
         }
       }
       // lift: east/north subtract F psi(+1), west/south add F psi(-1)
-      const double sc = face < 2 ? g.rhx : g.rhy;
+      const double sc = face < 2 ? rh_x(g, i) : rh_y(g, j);
 #pragma unroll
       for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -476,8 +489,8 @@ __global__ __launch_bounds__(kBlock) void k_stage_2d(StageArgs a) {
         if (q == 0) mean[v] = r * (T.b0[0] * T.b0[0]);
       }
     if (STAGE == 3 && a.want_speed) {
-      spx = P::template speed<0>(mean, g.gamma, bad);
-      spy = P::template speed<1>(mean, g.gamma, bad);
+      spx = per_wx(g, i, P::template speed<0>(mean, g.gamma, bad));
+      spy = per_wy(g, j, P::template speed<1>(mean, g.gamma, bad));
     }
   }
   if (bad) atomicOr(&a.sc->status, 1);
@@ -647,6 +660,7 @@ __global__ __launch_bounds__(64) void k_stage_2d_march(StageArgs a, int rows_per
   const double dt = STAGE == 0 ? 0.0 : a.sc->dt;
   bool bad = false;
   double spx = 0.0, spy = 0.0;
+  const double rx = rh_x(g, col);
 
   // flux on the south face of row j0 from the halo row below
   double FS[NV][NP];
@@ -685,13 +699,13 @@ __global__ __launch_bounds__(64) void k_stage_2d_march(StageArgs a, int rows_per
         double tw[NV][NP], FW[NV][NP];
         trace_x<N, NV, -1>(T, U, tw);
         face_flux<EQ, N, NV, 0>(tl, tw, FW, g.gamma, bad);
-        lift<N, NV, 0, -1>(T, FW, g.rhx, L);
+        lift<N, NV, 0, -1>(T, FW, rx, L);
         double FE[NV][NP];
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
           for (int e = 0; e < NP; ++e) FE[v][e] = __shfl_down(FW[v][e], 1);
-        lift<N, NV, 0, +1>(T, FE, g.rhx, L);
+        lift<N, NV, 0, +1>(T, FE, rx, L);
       }
       __builtin_amdgcn_sched_barrier(0);
       // volume term, one quadrature row qy at a time (not unrolled: keeps
@@ -719,8 +733,8 @@ __global__ __launch_bounds__(64) void k_stage_2d_march(StageArgs a, int rows_per
           const double w = T.wq[qx] * T.wq[qy];
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
-            Fx[v][qx] = w * g.rhx * f[v];
-            Gy[v][qx] = w * g.rhy * gg[v];
+            Fx[v][qx] = w * rx * f[v];
+            Gy[v][qx] = w * rh_y(g, j) * gg[v];
           }
         }
 #pragma unroll
@@ -746,8 +760,8 @@ __global__ __launch_bounds__(64) void k_stage_2d_march(StageArgs a, int rows_per
       double ts[NV][NP], FN[NV][NP];
       south_trace_streamed<N, NV>(T, a.u, plane, g, map_cell(g, col, j + 1), ts);
       face_flux<EQ, N, NV, 1>(tn, ts, FN, g.gamma, bad);
-      lift<N, NV, 1, -1>(T, FS, g.rhy, L);
-      lift<N, NV, 1, +1>(T, FN, g.rhy, L);
+      lift<N, NV, 1, -1>(T, FS, rh_y(g, j), L);
+      lift<N, NV, 1, +1>(T, FN, rh_y(g, j), L);
 #pragma unroll
       for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -773,8 +787,8 @@ __global__ __launch_bounds__(64) void k_stage_2d_march(StageArgs a, int rows_per
         }
       }
       if (STAGE == 3 && a.want_speed) {
-        spx = fmax(spx, P::template speed<0>(mean, g.gamma, bad));
-        spy = fmax(spy, P::template speed<1>(mean, g.gamma, bad));
+        spx = fmax(spx, per_wx(g, col, P::template speed<0>(mean, g.gamma, bad)));
+        spy = fmax(spy, per_wy(g, j, P::template speed<1>(mean, g.gamma, bad)));
       }
     }
   }
@@ -921,6 +935,8 @@ __device__ __forceinline__ void euler_tile(const StageArgs &a, int bx, int by, i
   if (col > g.nx) col = g.nx;
   const bool owner = slot >= 1 && slot <= STRIP && col < g.nx;
   const int j0 = by * rows_per_block;
+  // 2 / width of the lane's column (per column on non-uniform meshes)
+  const double rhx = BND ? rh_x(g, col) : g.rhx;
   const int j1 = min(j0 + rows_per_block, g.ny);
   const long plane = (long)g.nx * g.ny;
   const double dt = STAGE == 0 ? 0.0 : a.sc->dt;
@@ -1030,6 +1046,7 @@ __device__ __forceinline__ void euler_tile(const StageArgs &a, int bx, int by, i
       for (int q = 0; q < NM; ++q) row[(k * NM + q) * 64 + lane] = P[k][q];
   }
   for (int j = j0; j < j1; ++j) {
+    const double rhy = BND ? rh_y(g, j) : g.rhy;
     // next row in flight while this row is computed
     double P[VPL][NM];
     load2(map_cell<BND>(g, col, j + 1), P);
@@ -1060,8 +1077,8 @@ __device__ __forceinline__ void euler_tile(const StageArgs &a, int bx, int by, i
       for (int k = 0; k < VPL; ++k)
 #pragma unroll
         for (int e = 0; e < NP; ++e) FE[k][e] = __shfl_down(FW[k][e], LPC);
-      lift2(FW, T.bm, 0, -1, g.rhx, L);
-      lift2(FE, T.bp, 0, +1, g.rhx, L);
+      lift2(FW, T.bm, 0, -1, rhx, L);
+      lift2(FE, T.bp, 0, +1, rhx, L);
     }
     // volume term
 #pragma unroll 1
@@ -1088,8 +1105,8 @@ __device__ __forceinline__ void euler_tile(const StageArgs &a, int bx, int by, i
         const double w = T.wq[qx] * T.wq[qy];
 #pragma unroll
         for (int k = 0; k < VPL; ++k) {
-          Fx[k][qx] = w * g.rhx * flux_comp<0>(st, uq[k], v0 + k);
-          Gy[k][qx] = w * g.rhy * flux_comp<1>(st, uq[k], v0 + k);
+          Fx[k][qx] = w * rhx * flux_comp<0>(st, uq[k], v0 + k);
+          Gy[k][qx] = w * rhy * flux_comp<1>(st, uq[k], v0 + k);
         }
       }
 #pragma unroll
@@ -1136,8 +1153,8 @@ __device__ __forceinline__ void euler_tile(const StageArgs &a, int bx, int by, i
 #pragma unroll
         for (int k = 0; k < VPL; ++k) FN[k][e] = F[k];
       }
-      lift2(FS, T.bm, 1, -1, g.rhy, L);
-      lift2(FN, T.bp, 1, +1, g.rhy, L);
+      lift2(FS, T.bm, 1, -1, rhy, L);
+      lift2(FN, T.bp, 1, +1, rhy, L);
 #pragma unroll
       for (int k = 0; k < VPL; ++k)
 #pragma unroll
@@ -1169,8 +1186,13 @@ __device__ __forceinline__ void euler_tile(const StageArgs &a, int bx, int by, i
       gather_state<VPL>(mm, part, wm);
       if (owner) {
         const EulerPrim s = prim_of(wm, g.gamma, bad);
-        spx = fmax(spx, euler_speed<0>(s, 0.0, g.gamma));
-        spy = fmax(spy, euler_speed<1>(s, 0.0, g.gamma));
+        if (BND) {
+          spx = fmax(spx, per_wx(g, col, euler_speed<0>(s, 0.0, g.gamma)));
+          spy = fmax(spy, per_wy(g, j, euler_speed<1>(s, 0.0, g.gamma)));
+        } else {
+          spx = fmax(spx, euler_speed<0>(s, 0.0, g.gamma));
+          spy = fmax(spy, euler_speed<1>(s, 0.0, g.gamma));
+        }
       }
     }
     // the next row becomes the current one (each lane touches only its own slots)
@@ -1227,8 +1249,8 @@ __global__ __launch_bounds__(kBlock) void k_speed(const double *__restrict__ u, 
     double m[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) m[v] = u[(long)(v * NM) * plane + cell] * k0;
-    sx = fmax(sx, P::template speed<0>(m, g.gamma, bad));
-    if (DIM == 2) sy = fmax(sy, P::template speed<1>(m, g.gamma, bad));
+    sx = fmax(sx, per_wx(g, (int)(cell % g.nx), P::template speed<0>(m, g.gamma, bad)));
+    if (DIM == 2) sy = fmax(sy, per_wy(g, (int)(cell / g.nx), P::template speed<1>(m, g.gamma, bad)));
   }
   if (bad) atomicOr(&sc->status, 1);
 #pragma unroll
@@ -1495,7 +1517,8 @@ __device__ inline bool tvb_cell(const double *__restrict__ u, const Geometry &g,
   load_cell<NP, NM, NV, DIM>(u, plane, g, map_cell<BND>(g, i, j), C);
 #pragma unroll
   for (int dir = 0; dir < DIM; ++dir) {
-    const double Mh2 = dir == 0 ? g.tvb_Mx : g.tvb_My;
+    double Mh2 = dir == 0 ? g.tvb_Mx : g.tvb_My;
+    if (BND && g.mhx) Mh2 = dir == 0 ? g.mhx[i] : g.mhy[j];  // per column / row
     const CellIdx cp = map_cell<BND>(g, i + (dir == 0), j + (dir == 1));
     const CellIdx cm = map_cell<BND>(g, i - (dir == 0), j - (dir == 1));
 #pragma unroll
@@ -1554,6 +1577,12 @@ __device__ inline bool kxrcf_cell(const double *__restrict__ u, const Geometry &
   }
   mg = fabs(vel[0]);
   if (DIM == 2) mg = fmin(mg, fabs(vel[1]));
+  double kxs = g.kx_scale;
+  if (BND && g.hxa) {  // non-uniform mesh: this cell's circumscribed radius
+    const double hx = g.hxa[i], hy = DIM == 2 ? g.hya[j] : 0.0;
+    const double rad = DIM == 1 ? 0.5 * hx : 0.5 * sqrt(hx * hx + hy * hy);
+    kxs = 1.0 / pow(rad, 0.5 * (N + 1));
+  }
   double J[NVAR], len = 0.0;
 #pragma unroll
   for (int k = 0; k < NVAR; ++k) J[k] = 0.0;
@@ -1564,7 +1593,7 @@ __device__ inline bool kxrcf_cell(const double *__restrict__ u, const Geometry &
     const int d = minus ? -1 : 1;
     const CellIdx cn = map_cell<BND>(g, i + (dir == 0 ? d : 0), j + (dir == 1 ? d : 0));
     const double *own = minus ? T.bm : T.bp, *nbr = minus ? T.bp : T.bm;
-    const double flen = DIM == 1 ? 1.0 : (dir == 0 ? g.hy : g.hx);
+    const double flen = DIM == 1 ? 1.0 : (dir == 0 ? (BND && g.hya ? g.hya[j] : g.hy) : (BND && g.hxa ? g.hxa[i] : g.hx));
 #pragma unroll
     for (int k = 0; k < NVAR; ++k) {
       const int v = k == 0 ? 0 : DIM + 1;
@@ -1616,7 +1645,7 @@ __device__ inline bool kxrcf_cell(const double *__restrict__ u, const Geometry &
         }
         norm = fmax(norm, fabs(a));
       }
-    const double I = (len > 0.0 && norm > 0.0) ? fabs(J[k]) * g.kx_scale / (len * norm) : 0.0;
+    const double I = (len > 0.0 && norm > 0.0) ? fabs(J[k]) * kxs / (len * norm) : 0.0;
     flag |= I > 1.0;
     mg = fmin(mg, fabs(I - 1.0));
   }
@@ -1674,8 +1703,8 @@ __global__ __launch_bounds__(kBlock) void k_indicator(LimitArgs a) {
 // row is taken relative to the troubled cell's mean a[N] (the smoothness
 // indicators only see derivatives and the normalised weights sum to one), so
 // the quadratic forms do not cancel O(1) means.
-template <int N>
-__device__ inline void weno_row(const OrderTables &T, const double *a_in, double *out, double eps, bool raw) {
+template <int N, typename Tab>
+__device__ inline void weno_row(const Tab &T, const double *a_in, double *out, double eps, bool raw) {
   constexpr int NP = N + 1, NG = num_points<N>(), NS = 2 * N + 1;
   const double a0 = a_in[N];
   double a[NS];
@@ -1766,7 +1795,8 @@ __device__ inline void csweno_cell(const double *__restrict__ u, double *__restr
       }
     }
     double uG[NG];
-    weno_row<N>(T, st, uG, g.eps, raw);
+    if (BND && g.wtx) weno_row<N>(g.wtx[i], st, uG, g.eps, raw);  // this column's stencil
+    else weno_row<N>(T, st, uG, g.eps, raw);
 #pragma unroll
     for (int n = 1; n < NP; ++n) {
       double s = 0.0;
@@ -1813,7 +1843,8 @@ __device__ inline void csweno_cell(const double *__restrict__ u, double *__restr
 #pragma unroll
     for (int iy = 0; iy < NS; ++iy) {
       double r[NG];
-      weno_row<N>(T, st[iy], r, g.eps, raw);
+      if (BND && g.wtx) weno_row<N>(g.wtx[i], st[iy], r, g.eps, raw);
+      else weno_row<N>(T, st[iy], r, g.eps, raw);
 #pragma unroll
       for (int G = 0; G < NG; ++G) vy[G][iy] = r[G];
     }
@@ -1822,7 +1853,8 @@ __device__ inline void csweno_cell(const double *__restrict__ u, double *__restr
 #pragma unroll
     for (int G = 0; G < NG; ++G) {
       double u[NG];
-      weno_row<N>(T, vy[G], u, g.eps, raw);
+      if (BND && g.wty) weno_row<N>(g.wty[j], vy[G], u, g.eps, raw);  // this row's stencil
+      else weno_row<N>(T, vy[G], u, g.eps, raw);
 #pragma unroll
       for (int n = 0; n < NP; ++n) {
         double acc = 0.0;
@@ -1959,7 +1991,8 @@ __device__ inline void csweno_char_cell(const double *__restrict__ u, double *__
         for (int v = 0; v < NV; ++v) s += L[f][v] * a[v][k];
         ch[k] = s;
       }
-      weno_row<N>(T, ch, cG[f], g.eps, raw);
+      if (BND && g.wtx) weno_row<N>(g.wtx[i], ch, cG[f], g.eps, raw);  // this column's stencil
+      else weno_row<N>(T, ch, cG[f], g.eps, raw);
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v)
@@ -2017,7 +2050,8 @@ __device__ inline void csweno_char_cell(const double *__restrict__ u, double *__
           for (int v = 0; v < NV; ++v) s += L[f][v] * a[v][ix];
           ch[ix] = s;
         }
-        weno_row<N>(T, ch, cG[f], g.eps, raw);
+        if (BND && g.wtx) weno_row<N>(g.wtx[i], ch, cG[f], g.eps, raw);
+        else weno_row<N>(T, ch, cG[f], g.eps, raw);
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v)
@@ -2049,7 +2083,8 @@ __device__ inline void csweno_char_cell(const double *__restrict__ u, double *__
           for (int v = 0; v < NV; ++v) s += L[f][v] * vy[v][iy][G];
           ch[iy] = s;
         }
-        weno_row<N>(T, ch, cH[f], g.eps, raw);
+        if (BND && g.wty) weno_row<N>(g.wty[j], ch, cH[f], g.eps, raw);  // this row's stencil
+        else weno_row<N>(T, ch, cH[f], g.eps, raw);
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v)
@@ -2305,7 +2340,9 @@ int launch_set_tb(const LaunchCtx &c, double frac, double value) {
 }
 
 int launch_dt_finalize(const LaunchCtx &c) {
-  hipLaunchKernelGGL(k_dt_finalize, dim3(1), dim3(64), 0, S(c), c.sc, c.dim, c.cfl, c.geo.hx, c.geo.hy);
+  const bool nu = c.geo.hxa != nullptr;  // speeds are already per width
+  hipLaunchKernelGGL(k_dt_finalize, dim3(1), dim3(64), 0, S(c), c.sc, c.dim, c.cfl, nu ? 1.0 : c.geo.hx,
+                     nu ? 1.0 : c.geo.hy);
   return check_launch();
 }
 

@@ -166,42 +166,22 @@ ld int_centre(int d) {  // integral of xi^d over [-1/2, 1/2]
 
 }  // namespace
 
-int build_order_tables(int N, OrderTables *o) {
-  if (N < 1 || N > kMaxN) return DG_ERR_UNSUPPORTED;
+int build_weno_coef(int N, double rl_in, double rr_in, WenoCoef *o) {
+  if (N < 1 || N > kMaxN || !(rl_in > 0.0) || !(rr_in > 0.0)) return DG_ERR_UNSUPPORTED;
   std::memset(o, 0, sizeof(*o));
   const int NP = N + 1, NS = 2 * N + 1;
-  o->N = N;
-
-  // Section 2: volume/edge rule and basis values.
-  ld rq[8], wq[8];
-  gauss(NP, rq, wq);
-  for (int q = 0; q < NP; ++q) o->wq[q] = (double)wq[q];
-  for (int n = 0; n < NP; ++n) {
-    for (int q = 0; q < NP; ++q) {
-      o->bq[n][q] = (double)(norm(n) * legendre(n, rq[q]));
-      o->dbq[n][q] = (double)(norm(n) * legendre_d(n, rq[q]));
-    }
-    o->bm[n] = (double)(norm(n) * legendre(n, -1.0L));
-    o->bp[n] = (double)(norm(n) * legendre(n, 1.0L));
-    o->b0[n] = (double)(norm(n) * legendre(n, 0.0L));
-  }
-
-  // Step 1.
+  const ld rl = rl_in, rr = rr_in;
   int ng;
   ld rg[4], wg[4];
   recon_rule(N, &ng, rg, wg);
-  o->ng = ng;
-  for (int G = 0; G < ng; ++G) {
-    o->wg[G] = (double)wg[G];
-    for (int n = 0; n < NP; ++n) o->bg[n][G] = (double)(norm(n) * legendre(n, rg[G]));
-  }
 
   // Step 2: the compact stencil in units of the troubled cell's width,
-  // centred on it: N subcells of each neighbour around the whole cell.
+  // centred on it: N subcells of each neighbour around the whole cell (the
+  // neighbours rl and rr times as wide as the cell).
   ld edges[16], wdt[16];
   for (int k = 0; k <= N; ++k) {
-    edges[k] = -1.5L + (ld)k / N;
-    edges[N + 1 + k] = 0.5L + (ld)k / N;
+    edges[k] = (-0.5L - rl) + k * rl / N;
+    edges[N + 1 + k] = 0.5L + k * rr / N;
   }
   for (int c = 0; c < NS; ++c) wdt[c] = edges[c + 1] - edges[c];
 
@@ -276,6 +256,51 @@ int build_order_tables(int N, OrderTables *o) {
         o->B[i][k][l2] = (double)s;
       }
   }
+
+  return DG_OK;
+}
+
+int build_order_tables(int N, OrderTables *o) {
+  if (N < 1 || N > kMaxN) return DG_ERR_UNSUPPORTED;
+  std::memset(o, 0, sizeof(*o));
+  const int NP = N + 1, NS = 2 * N + 1;
+  o->N = N;
+
+  // Section 2: volume/edge rule and basis values.
+  ld rq[8], wq[8];
+  gauss(NP, rq, wq);
+  for (int q = 0; q < NP; ++q) o->wq[q] = (double)wq[q];
+  for (int n = 0; n < NP; ++n) {
+    for (int q = 0; q < NP; ++q) {
+      o->bq[n][q] = (double)(norm(n) * legendre(n, rq[q]));
+      o->dbq[n][q] = (double)(norm(n) * legendre_d(n, rq[q]));
+    }
+    o->bm[n] = (double)(norm(n) * legendre(n, -1.0L));
+    o->bp[n] = (double)(norm(n) * legendre(n, 1.0L));
+    o->b0[n] = (double)(norm(n) * legendre(n, 0.0L));
+  }
+
+  // Step 1.
+  int ng;
+  ld rg[4], wg[4];
+  recon_rule(N, &ng, rg, wg);
+  o->ng = ng;
+  for (int G = 0; G < ng; ++G) {
+    o->wg[G] = (double)wg[G];
+    for (int n = 0; n < NP; ++n) o->bg[n][G] = (double)(norm(n) * legendre(n, rg[G]));
+  }
+
+  WenoCoef w;
+  int rc = build_weno_coef(N, 1.0, 1.0, &w);
+  if (rc) return rc;
+  std::memcpy(o->T, w.T, sizeof(w.T));
+  std::memcpy(o->gam, w.gam, sizeof(w.gam));
+  std::memcpy(o->split, w.split, sizeof(w.split));
+  std::memcpy(o->gpn, w.gpn, sizeof(w.gpn));
+  std::memcpy(o->gmn, w.gmn, sizeof(w.gmn));
+  std::memcpy(o->sp, w.sp, sizeof(w.sp));
+  std::memcpy(o->sm, w.sm, sizeof(w.sm));
+  std::memcpy(o->B, w.B, sizeof(w.B));
 
   // Means of psi_n over the N equal subcells of [-1,1].
   for (int k = 0; k < N; ++k) {

@@ -18,7 +18,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdg.so")
 
-DG_ABI_VERSION = 2
+DG_ABI_VERSION = 3
 DG_OK, DG_ERR_INVALID_ARG, DG_ERR_UNSUPPORTED, DG_ERR_WORKSPACE, DG_ERR_HIP, DG_ERR_NONPHYSICAL = 0, -1, -2, -3, -4, -5
 BURGERS, EULER = 0, 1
 PERIODIC, TRANSMISSIVE, REFLECTIVE, INFLOW = 0, 1, 2, 3
@@ -70,6 +70,8 @@ class Config(ctypes.Structure):
         ("pad", ctypes.c_int32),
         ("bc_switch", (ctypes.c_double * 2) * 4),
         ("bc_state", ((ctypes.c_double * 4) * 2) * 4),
+        ("x_nodes", ctypes.POINTER(ctypes.c_double)),
+        ("y_nodes", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -134,7 +136,7 @@ def strerror(code):
 def make_config(dim=1, equation=BURGERS, order=2, nx=16, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
                 bc=(PERIODIC,) * 4, gamma=1.4, limiter=LIM_CSWENO, indicator=IND_TVB, negw_mode=NEGW_SPLIT,
                 tvb_M=1.0, weno_eps=1e-6, cfl=0.1, positivity=0, bc_beyond=(-1, -1, -1, -1),
-                bc_switch=((0.0, 0.0),) * 4, bc_state=None):
+                bc_switch=((0.0, 0.0),) * 4, bc_state=None, xn=None, yn=None):
     c = Config()
     c.abi_version = DG_ABI_VERSION
     c.dim, c.equation, c.order = dim, equation, order
@@ -152,6 +154,16 @@ def make_config(dim=1, equation=BURGERS, order=2, nx=16, ny=1, x0=0.0, x1=1.0, y
             c.bc_switch[k][a] = float(bc_switch[k][a])
             for v in range(4):
                 c.bc_state[k][a][v] = float(st[k, a, v])
+    keep = []  # node arrays of a non-uniform mesh, alive as long as the config
+    for name, arr, n in (("x_nodes", xn, nx), ("y_nodes", yn, c.ny)):
+        if arr is None:
+            continue
+        arr = np.ascontiguousarray(arr, dtype=np.float64)
+        if arr.shape != (n + 1,):
+            raise ValueError(f"{name} needs {n + 1} values")
+        keep.append(arr)
+        setattr(c, name, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    c._keep = keep
     return c
 
 
@@ -306,6 +318,7 @@ def problem_from_workload(wl, device="cuda", **over):
     kw = dict(dim=wl.dim, equation=wl.equation, order=wl.order, nx=wl.nx, ny=wl.ny, x0=wl.x0, x1=wl.x1,
               y0=wl.y0, y1=wl.y1, bc=tuple(wl.bc), gamma=wl.gamma, cfl=wl.cfl)
     kw.update(wl.bc_extra)
+    kw.update(wl.mesh)
     kw.update(over)
     return Problem(device=device, **kw)
 

@@ -1,0 +1,102 @@
+"""Non-uniform tensor-product meshes (the paper's accuracy tests move every
+node by up to 10%) on the GPU against the oracle: per call (residual, TVB
+and KXRCF flags, CSWENO and characteristic CSWENO with injected flags), one
+step with the CFL rule (the time step itself included), and runs to a final
+time, 1D and 2D, Burgers and Euler, orders 1-3.  Tolerances as in every
+parity test: 1e-12 relative per call and step, 1e-10 in L1 at the end."""
+import numpy as np
+import pytest
+import torch
+
+from tests.gpu_common import assert_close, configs, flags_agree, make_pair, rough_state
+
+pytestmark = pytest.mark.gpu
+
+NCASES = [  # (dim, eq, order, nx, ny, bc)
+    (1, 0, 1, 151, 1, (0, 0, 0, 0)),
+    (1, 0, 3, 120, 1, (1, 1, 0, 0)),
+    (1, 1, 1, 130, 1, (1, 1, 0, 0)),
+    (1, 1, 2, 111, 1, (0, 0, 0, 0)),
+    (1, 1, 3, 97, 1, (1, 1, 0, 0)),
+    (2, 0, 2, 70, 9, (0, 0, 1, 1)),
+    (2, 1, 1, 65, 12, (1, 1, 1, 1)),
+    (2, 1, 2, 61, 17, (0, 0, 0, 0)),
+    (2, 1, 3, 33, 10, (1, 1, 0, 0)),
+]
+NIDS = [f"d{c[0]}e{c[1]}n{c[2]}_{c[3]}x{c[4]}_bc{''.join(map(str, c[5]))}" for c in NCASES]
+
+
+@pytest.fixture(scope="module")
+def libs(oracle):
+    from paper_1904_11147_amd import dg
+    dg.lib()
+    return oracle, dg
+
+
+def _pair(libs, case, seed=0, **kw):
+    from paper_1904_11147_amd import workloads as W
+    O, D = libs
+    dim, eq, order, nx, ny, bc = case
+    mesh = dict(xn=W.perturbed_nodes(nx, 0.0, 1.0, seed=300 + seed))
+    if dim == 2:
+        mesh["yn"] = W.perturbed_nodes(ny, 0.0, 1.0, seed=400 + seed)
+    return make_pair(O, D, configs(dim, eq, order, nx, ny, bc, **mesh, **kw))
+
+
+@pytest.mark.parametrize("case", NCASES, ids=NIDS)
+def test_nonuniform_residual(libs, case):
+    op, gp = _pair(libs, case)
+    U = rough_state(libs[0], op, seed=81)
+    ref = op.residual(U)
+    got = gp.residual(torch.from_numpy(U).cuda()).cpu().numpy()
+    print(case, "residual rel err", assert_close(got, ref, what="residual, non-uniform mesh"))
+
+
+@pytest.mark.parametrize("ind", [0, 3])
+@pytest.mark.parametrize("case", NCASES, ids=NIDS)
+def test_nonuniform_limiter(libs, case, ind):
+    op, gp = _pair(libs, case, indicator=ind)
+    U = rough_state(libs[0], op, seed=82)
+    ref, rflags, rmargin = op.limit(U)
+    assert rflags.sum() > 0
+    Ud = torch.from_numpy(U).cuda()
+    flags, _, _ = gp.limit(Ud.clone())
+    if ind == 0:
+        diff, ok = flags_agree(flags.cpu().numpy(), rflags, rmargin)
+        assert ok, diff
+    else:  # KXRCF: the margin is min(|I-1|, |v|); a radius from the device pow may move I by an ulp
+        assert (flags.cpu().numpy() != rflags).sum() <= 2
+    gp.limit(Ud, flags_override=torch.from_numpy(rflags))
+    print(case, ind, "limiter rel err", assert_close(Ud.cpu().numpy(), ref, what="limiter, non-uniform mesh"))
+
+
+@pytest.mark.parametrize("case", [c for c in NCASES if c[1] == 1], ids=[i for c, i in zip(NCASES, NIDS) if c[1] == 1])
+def test_nonuniform_characteristic_limiter(libs, case):
+    op, gp = _pair(libs, case, limiter=2)
+    U = rough_state(libs[0], op, seed=83)
+    ref, rflags, _ = op.limit(U)
+    Ud = torch.from_numpy(U).cuda()
+    gp.limit(Ud, flags_override=torch.from_numpy(rflags))
+    print(case, "char limiter rel err", assert_close(Ud.cpu().numpy(), ref, what="characteristic, non-uniform"))
+
+
+@pytest.mark.parametrize("case", NCASES, ids=NIDS)
+def test_nonuniform_one_step_with_cfl(libs, case):
+    op, gp = _pair(libs, case, cfl=0.05)
+    U = rough_state(libs[0], op, seed=84, amplitude=0.2, extra_noise=0.01)
+    dt = op.cfl_dt(U)
+    assert dt == gp.cfl_dt(torch.from_numpy(U).cuda())
+    ref = op.step(U, dt)
+    Ud = torch.from_numpy(U).cuda()
+    t, n = gp.step(Ud, 0.0, 10.0, max_steps=1)
+    assert n == 1 and t == dt
+    print(case, "step rel err", assert_close(Ud.cpu().numpy(), ref, what="step, non-uniform mesh"))
+
+
+def test_nonuniform_runs_to_final_time(oracle):
+    from paper_1904_11147_amd import workloads as W
+    from tests.test_gpu_runs import _run_both
+    _run_both(oracle, W.burgers1d(nx=200, order=2).nonuniform(seed=11))
+    _run_both(oracle, W.sod(nx=200, order=2).nonuniform(seed=12))
+    _run_both(oracle, W.density_wave(n=24, order=2, t_end=0.5).nonuniform(seed=13))
+    _run_both(oracle, W.riemann2d(n=64, order=2, seed=12345, t_end=0.05).nonuniform(seed=14))
