@@ -1513,23 +1513,36 @@ __device__ inline bool tvb_cell(const double *__restrict__ u, const Geometry &g,
   const long plane = (long)g.nx * g.ny;
   const double k0 = DIM == 1 ? T.b0[0] : T.b0[0] * T.b0[0];
   bool flag = false;
-  double C[NV][NM];
-  load_cell<NP, NM, NV, DIM>(u, plane, g, map_cell<BND>(g, i, j), C);
+  const CellIdx me = map_cell<BND>(g, i, j);
+  CellIdx cp[DIM], cm[DIM];
+  double Mh2[DIM];
 #pragma unroll
   for (int dir = 0; dir < DIM; ++dir) {
-    double Mh2 = dir == 0 ? g.tvb_Mx : g.tvb_My;
-    if (BND && g.mhx) Mh2 = dir == 0 ? g.mhx[i] : g.mhy[j];  // per column / row
-    const CellIdx cp = map_cell<BND>(g, i + (dir == 0), j + (dir == 1));
-    const CellIdx cm = map_cell<BND>(g, i - (dir == 0), j - (dir == 1));
+    Mh2[dir] = dir == 0 ? g.tvb_Mx : g.tvb_My;
+    if (BND && g.mhx) Mh2[dir] = dir == 0 ? g.mhx[i] : g.mhy[j];  // per column / row
+    cp[dir] = map_cell<BND>(g, i + (dir == 0), j + (dir == 1));
+    cm[dir] = map_cell<BND>(g, i - (dir == 0), j - (dir == 1));
+  }
+  // one variable at a time: only its modes are live (decisions and margins
+  // combine by or / min, so the order of the tests does not matter)
+#pragma unroll 1
+  for (int v = 0; v < NV; ++v) {
+    double C[NM];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      double mean = C[v][0] * k0;
-      double mp = cell_mode<NP, NM, DIM>(u, plane, g, cp, v, 0) * k0;
-      double mm = cell_mode<NP, NM, DIM>(u, plane, g, cm, v, 0) * k0;
+    for (int q = 0; q < NM; ++q) C[q] = cell_mode<NP, NM, DIM>(u, plane, g, me, v, q);
+    const double mean = C[0] * k0;
+#pragma unroll
+    for (int dir = 0; dir < DIM; ++dir) {
+      const double mp = cell_mode<NP, NM, DIM>(u, plane, g, cp[dir], v, 0) * k0;
+      const double mm = cell_mode<NP, NM, DIM>(u, plane, g, cm[dir], v, 0) * k0;
       double up = 0.0, um = 0.0;
 #pragma unroll
       for (int q = 0; q < NM; ++q) {
         int m = q % NP, n = q / NP;
+        // odd Legendre polynomials vanish at the centre, psi_n(0) = 0: a
+        // mode odd in the tangential direction adds nothing to a
+        // face-midpoint trace, and one odd in both (never loaded) to none
+        if (DIM == 2 && (dir == 0 ? (n & 1) : (m & 1))) continue;
         double bu, bd;
         if (DIM == 1) {
           bu = T.bp[m];
@@ -1541,12 +1554,12 @@ __device__ inline bool tvb_cell(const double *__restrict__ u, const Geometry &g,
           bu = T.b0[m] * T.bp[n];
           bd = T.b0[m] * T.bm[n];
         }
-        up += C[v][q] * bu;
-        um += C[v][q] * bd;
+        up += C[q] * bu;
+        um += C[q] * bd;
       }
-      double dp = mp - mean, dm = mean - mm;
-      flag |= tvb_test(up - mean, dp, dm, Mh2, mg);
-      flag |= tvb_test(mean - um, dp, dm, Mh2, mg);
+      const double dp = mp - mean, dm = mean - mm;
+      flag |= tvb_test(up - mean, dp, dm, Mh2[dir], mg);
+      flag |= tvb_test(mean - um, dp, dm, Mh2[dir], mg);
     }
   }
   return flag;
@@ -1669,7 +1682,9 @@ __device__ inline void append_troubled(const LimitArgs &a, bool flag, long cell)
   }
 }
 
-template <int N, int EQ, int DIM, bool BND>
+// KX: the KXRCF indicator (an instantiation of its own, so that the TVB one
+// keeps only one variable's modes live)
+template <int N, int EQ, int DIM, bool BND, bool KX>
 __global__ __launch_bounds__(kBlock) void k_indicator(LimitArgs a) {
   const Geometry &g = a.geo;
   if (a.check_done && a.sc->done) return;
@@ -1684,7 +1699,7 @@ __global__ __launch_bounds__(kBlock) void k_indicator(LimitArgs a) {
       flag = a.ovr[cell] != 0;
     } else if (a.mode == DG_IND_ALL) {
       flag = true;
-    } else if (a.mode == DG_IND_KXRCF) {
+    } else if (KX) {
       flag = kxrcf_cell<N, EQ, DIM, BND>(a.u, g, i, j, mg);
     } else {
       flag = tvb_cell<N, EQ, DIM, BND>(a.u, g, i, j, mg);
@@ -2284,7 +2299,10 @@ int launch_limit(const LaunchCtx &c, double *u, double *side, int count_slot, ui
         learned = true;
       }
     }
-    if (!learned) hipLaunchKernelGGL((k_indicator<n, e, d, bnd>), grid, block, 0, S(c), a);
+    if (!learned) {
+      if (c.indicator == DG_IND_KXRCF) hipLaunchKernelGGL((k_indicator<n, e, d, bnd, true>), grid, block, 0, S(c), a);
+      else hipLaunchKernelGGL((k_indicator<n, e, d, bnd, false>), grid, block, 0, S(c), a);
+    }
     if (c.limiter != DG_LIM_NONE) {
       bool chr = false;
       if constexpr (e == DG_EQ_EULER) {
