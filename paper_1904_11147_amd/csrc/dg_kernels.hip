@@ -1523,9 +1523,9 @@ __device__ inline bool tvb_cell(const double *__restrict__ u, const Geometry &g,
     cp[dir] = map_cell<BND>(g, i + (dir == 0), j + (dir == 1));
     cm[dir] = map_cell<BND>(g, i - (dir == 0), j - (dir == 1));
   }
-  // one variable at a time: only its modes are live (decisions and margins
-  // combine by or / min, so the order of the tests does not matter)
-#pragma unroll 1
+  // variable by variable: each variable's modes are dead once its tests are
+  // done (decisions and margins combine by or / min, in any order)
+#pragma unroll
   for (int v = 0; v < NV; ++v) {
     double C[NM];
 #pragma unroll
