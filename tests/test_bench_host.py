@@ -1,0 +1,30 @@
+"""Host-side checks of bench.py (no GPU): more than one GPU is refused with
+a message before any device work, and the HBM traffic figure is used only
+when the committed counter summary was taken on the current kernel source."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_traffic_only_for_the_current_kernel_source(tmp_path, monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1904_11147_amd.profiling import kernel_source_hash
+    f = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.traffic_for(1.0) is None  # no file
+    f.write_text(json.dumps({"kernel_source_sha256_16": kernel_source_hash(), "hbm_bytes_per_launch": 123.0}))
+    assert bench.traffic_for(1.0) == 123.0
+    f.write_text(json.dumps({"kernel_source_sha256_16": "0" * 16, "hbm_bytes_per_launch": 123.0}))
+    assert bench.traffic_for(1.0) is None  # stale: the kernels changed since
