@@ -141,14 +141,15 @@ def double_mach_leg(steps, warmup, n=1920, order=2, to_end=False):
     return res
 
 
-def batched_leg(steps, warmup, count=256, nets=None):
+def batched_leg(steps, warmup, count=256, nets=None, positivity=0):
     """256 mixed four-state Riemann problems (side uniform in [64,512], order
     uniform in {1,2,3}, one seed each): every instance advanced alone through
     dg_step, then all together through dg_batch_step (autotuned tiles), plain
     TVB and with the learned indicators.  Each instance takes the same number
     of steps in every variant; cell-DOF updates / wall time of the stepping.
-    Instances that reach a non-physical state within those steps (no
-    positivity limiter is applied) are listed and left out of all variants."""
+    Instances that reach a non-physical state within those steps are listed
+    and left out of all variants.  positivity=1: the same with the
+    positivity-preserving scaling on in every run (no learned variant)."""
     import numpy as np
     import torch
     from paper_1904_11147_amd import dg, workloads as W
@@ -156,7 +157,7 @@ def batched_leg(steps, warmup, count=256, nets=None):
     # each instance alone
     el_seq, keep, excluded = 0.0, [], []
     for wl in wls_all:
-        p = dg.problem_from_workload(wl, device="cuda:0")
+        p = dg.problem_from_workload(wl, device="cuda:0", positivity=positivity)
         st = dg.initial_state(p, wl, limit=True)
         t, _ = p.step(st, 0.0, wl.t_end, max_steps=warmup, allow_nonphysical=True)
         bad = p.status() != 0
@@ -179,11 +180,11 @@ def batched_leg(steps, warmup, count=256, nets=None):
     t_end = np.array([wl.t_end for wl in wls])
     res = {"workload": f"riemann2d_batch{count}: {count} 2D Euler four-state Riemann problems, side uniform in "
                        "[64,512], order uniform in {1,2,3} (CFL 0.1, Q3 0.05), seeds 10000+, transmissive, "
-                       "TVB M=1 + CSWENO",
+                       "TVB M=1 + CSWENO" + (" + positivity scaling" if positivity else ""),
            "instances": len(wls), "excluded_nonphysical": excluded, "dofs": int(dofs.sum()),
            "orders": {o: int(sum(w.order == o for w in wls)) for o in (1, 2, 3)}, "steps_each": steps,
            "sequential": {"value": dofs.sum() * steps / el_seq, "ms_per_step": 1e3 * el_seq / steps}}
-    b = dg.batch_from_workloads(wls, device="cuda:0")
+    b = dg.batch_from_workloads(wls, device="cuda:0", positivity=positivity)
     init = b.states.clone()
 
     def run(batch):
@@ -201,7 +202,7 @@ def batched_leg(steps, warmup, count=256, nets=None):
     res["batched"] = run(b)
     b.close()
     del b
-    if nets and all(o in nets for o in (1, 2, 3)):
+    if nets and not positivity and all(o in nets for o in (1, 2, 3)):
         cfgs = [dict(dim=2, equation=wl.equation, order=wl.order, nx=wl.nx, ny=wl.ny, x0=wl.x0, x1=wl.x1, y0=wl.y0,
                      y1=wl.y1, bc=tuple(wl.bc), gamma=wl.gamma, cfl=wl.cfl, indicator=dg.IND_LEARNED) for wl in wls]
         bl = dg.Batch(cfgs, device="cuda:0")
@@ -345,6 +346,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = batched_leg(args.batched_steps, 2, nets=nets)
+        torch.cuda.empty_cache()
+        out["batched_positivity"] = batched_leg(args.batched_steps, 2, positivity=1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(seed=args.seed)
     print(json.dumps(out), flush=True)

@@ -298,9 +298,9 @@ int dg_set_learned(dg_problem *p, const uint16_t *w_bf16, const float *master, d
 typedef struct dg_batch dg_batch;
 
 /* Workspace bytes for the n configurations cfgs[0..n-1] (n <= 4096; all 2D
- * Euler; equal limiter and indicator; periodic or transmissive sides and no
- * positivity scaling (else DG_ERR_UNSUPPORTED); at most 2^31 - 1 cells in
- * total). */
+ * Euler; equal limiter, indicator and positivity flag; periodic or
+ * transmissive sides on uniform meshes (else DG_ERR_UNSUPPORTED); at most
+ * 2^31 - 1 cells in total). */
 int dg_batch_workspace_bytes(const dg_config *cfgs, int32_t n, size_t *bytes);
 
 /* Creates the batch on the current device and the given stream (NULL =

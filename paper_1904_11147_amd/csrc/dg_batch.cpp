@@ -42,10 +42,11 @@ int validate_batch(const dg_config *cfgs, int32_t n) {
     if (rc) return rc;
     if (cfgs[i].dim != 2 || cfgs[i].equation != DG_EQ_EULER) return DG_ERR_UNSUPPORTED;
     if (cfgs[i].limiter != cfgs[0].limiter || cfgs[i].indicator != cfgs[0].indicator) return DG_ERR_INVALID_ARG;
-    // walls, inflow and switching sides and the positivity scaling run on single meshes only
+    // walls, inflow and switching sides and non-uniform meshes run on single meshes only
     for (int k = 0; k < 4; ++k)
       if (cfgs[i].bc[k] != DG_BC_PERIODIC && cfgs[i].bc[k] != DG_BC_TRANSMISSIVE) return DG_ERR_UNSUPPORTED;
-    if (cfgs[i].positivity || cfgs[i].bc_beyond[2] >= 0 || cfgs[i].bc_beyond[3] >= 0) return DG_ERR_UNSUPPORTED;
+    if (cfgs[i].positivity != cfgs[0].positivity) return DG_ERR_INVALID_ARG;
+    if (cfgs[i].bc_beyond[2] >= 0 || cfgs[i].bc_beyond[3] >= 0 || cfgs[i].x_nodes) return DG_ERR_UNSUPPORTED;
     cells += (long long)cfgs[i].nx * cfgs[i].ny;
   }
   if (cells > (1ll << 31) - 1) return DG_ERR_UNSUPPORTED;
@@ -172,7 +173,7 @@ int enqueue_batch_step(dg_batch *b) {
   for (int stage = 1; stage <= 3 && !rc; ++stage) {
     for (int o = 1; o <= kMaxN && !rc; ++o)
       if (b->present[o]) rc = dg::batch_launch_stage(b->ctx, o, stage, b->grid[o]);
-    if (b->ctx.limiter == DG_LIM_NONE) continue;
+    if (b->ctx.limiter == DG_LIM_NONE && !b->ctx.positivity) continue;
     for (int o = 1; o <= kMaxN && !rc; ++o)
       if (b->present[o]) rc = dg::batch_launch_limit(b->ctx, o, stage - 1);
   }
@@ -256,6 +257,7 @@ int dg_batch_init(const dg_config *cfgs, int32_t n, void *workspace, size_t work
   c.stream = stream;
   c.limiter = cfgs[0].limiter;
   c.indicator = cfgs[0].indicator;
+  c.positivity = cfgs[0].positivity;
   c.grid_cap = 2048;
   b->sc = (DevScalars *)(ws + L.scalars);
   b->inst.resize(n);

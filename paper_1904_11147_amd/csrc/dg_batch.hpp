@@ -217,6 +217,23 @@ __global__ __launch_bounds__(64) void k_batch_indicator(const BatchInst *__restr
   }
 }
 
+// Positivity-preserving scaling of the limited state over the queued row
+// segments (one wavefront per segment); a non-admissible mean stops that
+// instance (its status word).
+template <int N, int SLOT>
+__global__ __launch_bounds__(64) void k_batch_positivity(const BatchInst *__restrict__ inst,
+                                                         const BatchQueue *__restrict__ q) {
+  const int total = q->total_segs;
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const SegItem s = seg_item(inst, q, w);
+    const BatchInst &I = inst[s.id];
+    const int i = s.i0 + threadIdx.x;
+    if (i < I.geo.nx &&
+        positivity_cell<N, 2>(limit_target<SLOT>(I), (long)I.geo.nx * I.geo.ny, (long)s.j * I.geo.nx + i, I.geo))
+      atomicOr(&I.sc->status, 1);
+  }
+}
+
 // The learned indicator over the queued learned tiles (lm_waves(N) strips of
 // kLmRows rows each); the block keeps the order's network in LDS.
 template <int N, int SLOT>

@@ -175,6 +175,7 @@ struct BatchCtx {
   long long *list[kMaxN + 1];  // device, per order: troubled entries (instance << 32 | cell)
   void *stream;
   int limiter, indicator;  // one of each for the whole batch
+  int positivity;          // Zhang-Shu scaling after every limiter pass (all instances)
   int grid_cap;          // blocks of list-driven and indicator kernels
   BatchLearned learned[kMaxN + 1];
 };

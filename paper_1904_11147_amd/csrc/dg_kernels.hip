@@ -1381,92 +1381,97 @@ __device__ inline double pos_root(const double *wb, const double *wq, double eps
   return fmin(fmax(t, 0.0), 1.0);
 }
 
+// One cell of a state with `plane` cells per mode plane; returns true when
+// the cell's mean itself is not admissible (the cell is then left as it is).
 template <int N, int DIM>
-__global__ __launch_bounds__(kBlock) void k_positivity(double *__restrict__ u, DevScalars *sc, Geometry g,
-                                                       int check_done) {
+__device__ inline bool positivity_cell(double *__restrict__ u, long plane, long cell, const Geometry &g) {
   constexpr int NP = N + 1, NM = DIM == 1 ? NP : NP * NP, NV = DIM + 2, NL = N == 1 ? 2 : 3;
   const OrderTables &T = c_tab[N];
-  if (check_done && sc->done) return;
-  const long plane = (long)g.nx * g.ny;
   const double k0 = DIM == 1 ? T.b0[0] : T.b0[0] * T.b0[0];
   // basis rows of the Gauss-Lobatto points
   auto lob = [&](int a, int n) { return a == 0 ? T.bm[n] : (a == NL - 1 ? T.bp[n] : T.b0[n]); };
-  bool bad = false;
-  for (long cell = blockIdx.x * (long)blockDim.x + threadIdx.x; cell < plane; cell += (long)gridDim.x * blockDim.x) {
-    double C[NV][NM], wb[NV];
+
+  double C[NV][NM], wb[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
+  for (int v = 0; v < NV; ++v) {
 #pragma unroll
-      for (int q = 0; q < NM; ++q) C[v][q] = u[(long)(v * NM + q) * plane + cell];
-      wb[v] = C[v][0] * k0;
-    }
-    const double pb = pos_pressure<DIM>(wb, g.gamma);
-    if (!(wb[0] > 0.0 && pb > 0.0)) {
-      bad = true;
-      continue;
-    }
-    const double eps = fmin(kPosEps, fmin(wb[0], pb));
-    // visit(f): f(point values of the requested variables) at every point
-    auto visit = [&](auto nvars, auto f) {
-      constexpr int K = decltype(nvars)::value;
-      if (DIM == 1) {
-        for (int a = 0; a < NL + NP; ++a) {
+    for (int q = 0; q < NM; ++q) C[v][q] = u[(long)(v * NM + q) * plane + cell];
+    wb[v] = C[v][0] * k0;
+  }
+  const double pb = pos_pressure<DIM>(wb, g.gamma);
+  if (!(wb[0] > 0.0 && pb > 0.0)) return true;
+  const double eps = fmin(kPosEps, fmin(wb[0], pb));
+  // visit(f): f(point values of the requested variables) at every point
+  auto visit = [&](auto nvars, auto f) {
+    constexpr int K = decltype(nvars)::value;
+    if (DIM == 1) {
+      for (int a = 0; a < NL + NP; ++a) {
+        double w[NV];
+#pragma unroll
+        for (int v = 0; v < K; ++v) {
+          double acc = 0.0;
+#pragma unroll
+          for (int m = 0; m < NP; ++m) acc += C[v][m] * (a < NL ? lob(a, m) : T.bq[m][a - NL]);
+          w[v] = acc;
+        }
+        f(w);
+      }
+    } else {
+      // rows s: Gauss-Lobatto rows take the Gauss columns, Gauss rows take both
+      for (int b = 0; b < NL + NP; ++b) {
+        double cr[K][NP];  // partial sums over the y-degree at this row
+#pragma unroll
+        for (int v = 0; v < K; ++v)
+#pragma unroll
+          for (int m = 0; m < NP; ++m) {
+            double acc = 0.0;
+#pragma unroll
+            for (int n = 0; n < NP; ++n) acc += C[v][m + NP * n] * (b < NL ? lob(b, n) : T.bq[n][b - NL]);
+            cr[v][m] = acc;
+          }
+        const int a0 = b < NL ? NL : 0;
+        for (int a = a0; a < NL + NP; ++a) {
           double w[NV];
 #pragma unroll
           for (int v = 0; v < K; ++v) {
             double acc = 0.0;
 #pragma unroll
-            for (int m = 0; m < NP; ++m) acc += C[v][m] * (a < NL ? lob(a, m) : T.bq[m][a - NL]);
+            for (int m = 0; m < NP; ++m) acc += cr[v][m] * (a < NL ? lob(a, m) : T.bq[m][a - NL]);
             w[v] = acc;
           }
           f(w);
         }
-      } else {
-        // rows s: Gauss-Lobatto rows take the Gauss columns, Gauss rows take both
-        for (int b = 0; b < NL + NP; ++b) {
-          double cr[K][NP];  // partial sums over the y-degree at this row
-#pragma unroll
-          for (int v = 0; v < K; ++v)
-#pragma unroll
-            for (int m = 0; m < NP; ++m) {
-              double acc = 0.0;
-#pragma unroll
-              for (int n = 0; n < NP; ++n) acc += C[v][m + NP * n] * (b < NL ? lob(b, n) : T.bq[n][b - NL]);
-              cr[v][m] = acc;
-            }
-          const int a0 = b < NL ? NL : 0;
-          for (int a = a0; a < NL + NP; ++a) {
-            double w[NV];
-#pragma unroll
-            for (int v = 0; v < K; ++v) {
-              double acc = 0.0;
-#pragma unroll
-              for (int m = 0; m < NP; ++m) acc += cr[v][m] * (a < NL ? lob(a, m) : T.bq[m][a - NL]);
-              w[v] = acc;
-            }
-            f(w);
-          }
-        }
       }
-    };
-    double rmin = INFINITY;
-    visit(std::integral_constant<int, 1>{}, [&](const double *w) { rmin = fmin(rmin, w[0]); });
-    double th1 = 1.0, th2 = 1.0;
-    if (rmin < eps) {
-      th1 = (wb[0] - eps) / (wb[0] - rmin);
-#pragma unroll
-      for (int q = 1; q < NM; ++q) C[0][q] *= th1;
     }
-    visit(std::integral_constant<int, NV>{}, [&](const double *w) {
-      if (pos_pressure<DIM>(w, g.gamma) < eps) th2 = fmin(th2, pos_root<DIM>(wb, w, eps, g.gamma));
-    });
-    if (th1 < 1.0 || th2 < 1.0) {
+  };
+  double rmin = INFINITY;
+  visit(std::integral_constant<int, 1>{}, [&](const double *w) { rmin = fmin(rmin, w[0]); });
+  double th1 = 1.0, th2 = 1.0;
+  if (rmin < eps) {
+    th1 = (wb[0] - eps) / (wb[0] - rmin);
 #pragma unroll
-      for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int q = 1; q < NM; ++q) u[(long)(v * NM + q) * plane + cell] = th2 < 1.0 ? C[v][q] * th2 : C[v][q];
-    }
+    for (int q = 1; q < NM; ++q) C[0][q] *= th1;
   }
+  visit(std::integral_constant<int, NV>{}, [&](const double *w) {
+    if (pos_pressure<DIM>(w, g.gamma) < eps) th2 = fmin(th2, pos_root<DIM>(wb, w, eps, g.gamma));
+  });
+  if (th1 < 1.0 || th2 < 1.0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int q = 1; q < NM; ++q) u[(long)(v * NM + q) * plane + cell] = th2 < 1.0 ? C[v][q] * th2 : C[v][q];
+  }
+  return false;
+}
+
+template <int N, int DIM>
+__global__ __launch_bounds__(kBlock) void k_positivity(double *__restrict__ u, DevScalars *sc, Geometry g,
+                                                       int check_done) {
+  if (check_done && sc->done) return;
+  const long plane = (long)g.nx * g.ny;
+  bool bad = false;
+  for (long cell = blockIdx.x * (long)blockDim.x + threadIdx.x; cell < plane; cell += (long)gridDim.x * blockDim.x)
+    bad |= positivity_cell<N, DIM>(u, plane, cell, g);
   if (bad) atomicOr(&sc->status, 1);
 }
 
@@ -2521,6 +2526,8 @@ int batch_launch_limit(const BatchCtx &b, int order, int slot) {
           hipLaunchKernelGGL((k_batch_csweno<n, s>), dim3(b.grid_cap), dim3(kBlock), 0, st, b.inst, q, list);
         hipLaunchKernelGGL((k_batch_scatter<n, s>), dim3(b.grid_cap), dim3(kBlock), 0, st, b.inst, q, list);
       }
+      if (b.positivity)
+        hipLaunchKernelGGL((k_batch_positivity<n, s>), dim3(4 * b.grid_cap), dim3(64), 0, st, b.inst, q);
     };
     if (slot == 0) go(std::integral_constant<int, 0>{});
     else if (slot == 1) go(std::integral_constant<int, 1>{});

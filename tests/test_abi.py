@@ -131,10 +131,16 @@ def test_boundary_and_positivity_validation(dg):
     c.pad = 1
     with pytest.raises(dg.DGError):
         dg.workspace_bytes(c)
-    # batches take periodic and transmissive sides only, without the scaling
+    # batches take periodic and transmissive sides on uniform meshes, with
+    # the scaling on for all instances or for none
     n = ctypes.c_size_t()
     e2 = dict(dim=2, equation=dg.EULER, order=2, nx=8, ny=8)
     cf = (dg.Config * 1)(dg.make_config(**dict(e2, bc=(dg.REFLECTIVE, 1, dg.REFLECTIVE, 1))))
     assert dg.lib().dg_batch_workspace_bytes(cf, 1, ctypes.byref(n)) == dg.DG_ERR_UNSUPPORTED
-    cf = (dg.Config * 1)(dg.make_config(**dict(e2, bc=(1, 1, 1, 1), positivity=1)))
+    cf = (dg.Config * 1)(dg.make_config(**dict(e2, bc=(1, 1, 1, 1), xn=np.linspace(0, 1, 9), yn=np.linspace(0, 1, 9))))
     assert dg.lib().dg_batch_workspace_bytes(cf, 1, ctypes.byref(n)) == dg.DG_ERR_UNSUPPORTED
+    cf = (dg.Config * 1)(dg.make_config(**dict(e2, bc=(1, 1, 1, 1), positivity=1)))
+    assert dg.lib().dg_batch_workspace_bytes(cf, 1, ctypes.byref(n)) == 0
+    cf = (dg.Config * 2)(dg.make_config(**dict(e2, bc=(1, 1, 1, 1), positivity=1)),
+                         dg.make_config(**dict(e2, bc=(1, 1, 1, 1))))
+    assert dg.lib().dg_batch_workspace_bytes(cf, 2, ctypes.byref(n)) == dg.DG_ERR_INVALID_ARG

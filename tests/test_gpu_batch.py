@@ -169,3 +169,44 @@ def test_single_mesh_autotune_changes_no_result():
     b = s0.clone()
     t_b, n_b = p.step(b, 0.0, wl.t_end, max_steps=5)
     assert (t_a, n_a) == (t_b, n_b) and torch.equal(a, b)
+
+
+def test_batch_with_positivity_equals_single_runs_and_keeps_q3_physical():
+    """With the positivity scaling on for every instance, the batch equals the
+    single-mesh runs bit for bit; the Q3 instance of the mixed benchmark batch
+    that turns non-physical within 200 steps without the scaling (98^2, seed
+    10195) stays physical with it."""
+    from paper_1904_11147_amd import dg
+    from paper_1904_11147_amd import workloads as W
+    q3 = [wl for wl in W.riemann2d_batch() if wl.seed == 10195][0]
+    wls = _mixed() + [q3]
+    b = dg.batch_from_workloads(wls, positivity=1)
+    t_end = np.array([wl.t_end for wl in wls])
+    ref = []
+    for i, wl in enumerate(wls):
+        p = dg.problem_from_workload(wl, positivity=1)
+        st = b.view(i).clone()
+        tt, n = p.step(st, 0.0, float(t_end[i]), max_steps=40)
+        ref.append((st, tt, n))
+        p.close()
+    t, steps, status, _ = b.step(0.0, t_end, max_steps=40)
+    assert (status == 0).all() and (steps == 40).all()
+    _check_equal(b, ref, t, steps)
+    plain = dg.batch_from_workloads([q3])
+    _, _, st_plain, _ = plain.step(0.0, [q3.t_end], max_steps=200, allow_nonphysical=True)
+    assert st_plain[0] != 0  # without the scaling this instance fails
+
+
+def test_batch_with_positivity_one_step_matches_oracle(oracle):
+    from paper_1904_11147_amd import dg
+    from paper_1904_11147_amd import workloads as W
+    from tests.dgutil import oracle_problem
+    wls = [W.riemann2d(n=20, order=1, seed=41), W.riemann2d(n=18, order=2, seed=42),
+           W.riemann2d(n=16, order=3, seed=43)]
+    b = dg.batch_from_workloads(wls, positivity=1)
+    U0 = [b.view(i).cpu().numpy() for i in range(len(wls))]
+    t, steps, _, _ = b.step(0.0, [wl.t_end for wl in wls], max_steps=1)
+    for i, wl in enumerate(wls):
+        op = oracle_problem(oracle, wl, positivity=1)
+        ref = op.step(U0[i], t[i])
+        assert_close(b.view(i).cpu().numpy(), ref, what=f"batch instance {i} with positivity ({wl.name})")
