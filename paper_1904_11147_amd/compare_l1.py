@@ -7,8 +7,10 @@ throughput and the final L1 error of every instance.
 L1 is that of the density cell means against the plain method on the
 2x-refined mesh, averaged down (the refined run is the reference for every
 variant).  Instances whose plain or reference run meets a non-physical state
-(no positivity limiter is part of the method) are reported and left out of
-the L1 comparison.  Progress is printed per instance and per variant.
+are reported and left out of the L1 comparison; --positivity turns the
+positivity-preserving scaling on in every run (references included), which
+keeps the Q3 instances physical.  Progress is printed per instance and per
+variant.
 """
 import argparse
 import json
@@ -41,7 +43,9 @@ def main():
     ap.add_argument("--nmax", type=int, default=128)
     ap.add_argument("--t-end", type=float, default=0.25)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--positivity", action="store_true")
     a = ap.parse_args()
+    pos = {"positivity": 1} if a.positivity else {}
 
     wls = W.riemann2d_batch(count=a.count, first_seed=a.first_seed, nmin=a.nmin, nmax=a.nmax, t_end=a.t_end)
     nets = {o: learned.MLP.load(os.path.join(HERE, "weights", f"indicator_q{o}.npz")) for o in (1, 2, 3)}
@@ -52,14 +56,14 @@ def main():
     for i, wl in enumerate(wls):
         r = {"seed": wl.seed, "n": wl.nx, "order": wl.order}
         wf = W.riemann2d(n=2 * wl.nx, order=wl.order, seed=wl.seed, t_end=wl.t_end)
-        pf = dg.problem_from_workload(wf)
+        pf = dg.problem_from_workload(wf, **pos)
         sf = dg.initial_state(pf, wf, limit=True)
         pf.step(sf, 0.0, wf.t_end, allow_nonphysical=True)
         r["reference_nonphysical"] = pf.status() != 0
         r["_ref"] = _down(_means(sf))
         pf.close()
         del sf
-        p = dg.problem_from_workload(wl)
+        p = dg.problem_from_workload(wl, **pos)
         s = dg.initial_state(p, wl, limit=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -74,13 +78,13 @@ def main():
         p.close()
         rows.append(r)
         print(f"instance {i}: n={wl.nx} Q{wl.order} plain {n} steps", flush=True)
-    res = {"count": a.count, "sizes": [a.nmin, a.nmax], "t_end": a.t_end,
+    res = {"count": a.count, "sizes": [a.nmin, a.nmax], "t_end": a.t_end, "positivity": bool(a.positivity),
            "plain_per_instance": {"seconds": t_plain, "dof_updates_per_s": dofs_plain / t_plain}}
     for kind in ("batched_plain", "batched_learned"):
         over = {"indicator": dg.IND_LEARNED} if kind == "batched_learned" else {}
-        b = dg.batch_from_workloads(wls, limit=False, **over)
+        b = dg.batch_from_workloads(wls, limit=False, **over, **pos)
         for i, wl in enumerate(wls):  # the same TVB-limited initial states
-            p = dg.problem_from_workload(wl)
+            p = dg.problem_from_workload(wl, **pos)
             p.limit(b.view(i), want_margin=False)
             p.close()
         if kind == "batched_learned":
