@@ -9,8 +9,8 @@ LIB = os.path.join(HERE, "libdg.so")
 SOURCES = ["dg_kernels.hip", "dg_tables.cpp", "dg_api.cpp", "dg_batch.cpp"]
 ARCH = os.environ.get("DG_OFFLOAD_ARCH", "gfx950")
 
-# Packed FP32 instructions are disabled for all device code (see the design doc,
-# build notes); FP64 arithmetic is unaffected.
+# Packed FP32 instructions are disabled for all device code (some of their
+# forms are not trusted on this target); FP64 arithmetic is unaffected.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=on"]
 
 
