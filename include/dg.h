@@ -300,7 +300,9 @@ typedef struct dg_batch dg_batch;
 /* Workspace bytes for the n configurations cfgs[0..n-1] (n <= 4096; all 2D
  * Euler; equal limiter, indicator and positivity flag; periodic or
  * transmissive sides on uniform meshes (else DG_ERR_UNSUPPORTED); at most
- * 2^31 - 1 cells in total). */
+ * 2^31 - 1 cells in total, and at most 2^27 / (N+1)^2 cells per instance,
+ * e.g. 14.9 million at N = 2, as the batched stage kernel addresses an
+ * instance's state with 32-bit byte offsets (else DG_ERR_UNSUPPORTED)). */
 int dg_batch_workspace_bytes(const dg_config *cfgs, int32_t n, size_t *bytes);
 
 /* Creates the batch on the current device and the given stream (NULL =

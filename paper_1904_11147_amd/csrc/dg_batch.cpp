@@ -47,7 +47,10 @@ int validate_batch(const dg_config *cfgs, int32_t n) {
       if (cfgs[i].bc[k] != DG_BC_PERIODIC && cfgs[i].bc[k] != DG_BC_TRANSMISSIVE) return DG_ERR_UNSUPPORTED;
     if (cfgs[i].positivity != cfgs[0].positivity) return DG_ERR_INVALID_ARG;
     if (cfgs[i].bc_beyond[2] >= 0 || cfgs[i].bc_beyond[3] >= 0 || cfgs[i].x_nodes) return DG_ERR_UNSUPPORTED;
-    cells += (long long)cfgs[i].nx * cfgs[i].ny;
+    // the batched stage kernel addresses an instance's state with 32-bit byte offsets
+    const long long n_i = (long long)cfgs[i].nx * cfgs[i].ny;
+    if (32ll * (cfgs[i].order + 1) * (cfgs[i].order + 1) * n_i > (1ll << 32)) return DG_ERR_UNSUPPORTED;
+    cells += n_i;
   }
   if (cells > (1ll << 31) - 1) return DG_ERR_UNSUPPORTED;
   return DG_OK;

@@ -166,7 +166,7 @@ __global__ __launch_bounds__(64, 2) void k_batch_stage(const BatchInst *__restri
   a.sc = I.sc;
   a.geo = I.geo;
   a.want_speed = 1;
-  euler_tile<N, STAGE, false>(a, local % I.tiles_x, local / I.tiles_x, I.rows, row);
+  euler_tile<N, STAGE, false, true>(a, local % I.tiles_x, local / I.tiles_x, I.rows, row);
 }
 
 // Buffers of the limiter pass after stage SLOT+1: the state it limits and the

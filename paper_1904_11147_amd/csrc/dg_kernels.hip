@@ -223,6 +223,13 @@ __device__ inline double per_wy(const Geometry &g, int j, double s) { return g.h
 // Residual + SSP-RK3 stage.  STAGE 0: out = L(u).  1: u + dt L.  2: 3/4 un +
 // 1/4 (u + dt L).  3: 1/3 un + 2/3 (u + dt L).
 // ---------------------------------------------------------------------------
+// Last SSP-RK3 stage, 1/3 un + 2/3 v: products with the rounded constants
+// (within an ulp of the quotients, and no division sequence per value).
+__device__ __forceinline__ double rk3_last(double un, double v) {
+  constexpr double third = 1.0 / 3.0, two_thirds = 2.0 / 3.0;
+  return un * third + v * two_thirds;
+}
+
 struct StageArgs {
   const double *u;
   const double *un;
@@ -318,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_1d(StageArgs a) {
         if (STAGE == 0) r = L[v][n];
         else if (STAGE == 1) r = C[v][n] + dt * L[v][n];
         else if (STAGE == 2) r = 0.75 * a.un[k] + 0.25 * (C[v][n] + dt * L[v][n]);
-        else r = a.un[k] / 3.0 + 2.0 * (C[v][n] + dt * L[v][n]) / 3.0;
+        else r = rk3_last(a.un[k], C[v][n] + dt * L[v][n]);
         a.out[k] = r;
         if (n == 0) mean[v] = r * T.b0[0];
       }
@@ -484,7 +491,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_2d(StageArgs a) {
         if (STAGE == 0) r = L[v][q];
         else if (STAGE == 1) r = C[v][q] + dt * L[v][q];
         else if (STAGE == 2) r = 0.75 * a.un[k] + 0.25 * (C[v][q] + dt * L[v][q]);
-        else r = a.un[k] / 3.0 + 2.0 * (C[v][q] + dt * L[v][q]) / 3.0;
+        else r = rk3_last(a.un[k], C[v][q] + dt * L[v][q]);
         a.out[k] = r;
         if (q == 0) mean[v] = r * (T.b0[0] * T.b0[0]);
       }
@@ -781,7 +788,7 @@ __global__ __launch_bounds__(64) void k_stage_2d_march(StageArgs a, int rows_per
           if (STAGE == 0) r = L[v][q];
           else if (STAGE == 1) r = a.u[k] + dt * L[v][q];
           else if (STAGE == 2) r = 0.75 * a.un[k] + 0.25 * (a.u[k] + dt * L[v][q]);
-          else r = a.un[k] / 3.0 + 2.0 * (a.u[k] + dt * L[v][q]) / 3.0;
+          else r = rk3_last(a.un[k], a.u[k] + dt * L[v][q]);
           a.out[k] = r;
           if (q == 0) mean[v] = r * (T.b0[0] * T.b0[0]);
         }
@@ -858,18 +865,30 @@ __device__ inline double euler_speed(const EulerPrim &s, double rho, double g) {
 // Q3, whose modes would not fit two variables per lane).  `part` is the
 // lane's index within its cell.
 
+// The value of lane (lane ^ X) (X in 1..3: the cell's lanes are one aligned
+// group of four) by a DPP quad permutation, a register move with no LDS round
+// trip.  Every lane of the wavefront is active where it is called.
+template <int X>
+__device__ __forceinline__ double quad_xor(double v) {
+  constexpr int ctrl = (0 ^ X) | ((1 ^ X) << 2) | ((2 ^ X) << 4) | ((3 ^ X) << 6);
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), ctrl, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // The full state (rho, mx, my, E) at a point from the cell's lanes.
 template <int VPL>
 __device__ inline void gather_state(const double (&a)[VPL], int part, double (&w)[4]) {
   if constexpr (VPL == 2) {
-    const double b0 = __shfl_xor(a[0], 1), b1 = __shfl_xor(a[1], 1);
+    const double b0 = quad_xor<1>(a[0]), b1 = quad_xor<1>(a[1]);
     const bool h1 = part != 0;
     w[0] = h1 ? b0 : a[0];
     w[1] = h1 ? b1 : a[1];
     w[2] = h1 ? a[0] : b0;
     w[3] = h1 ? a[1] : b1;
   } else {
-    const double x1 = __shfl_xor(a[0], 1), x2 = __shfl_xor(a[0], 2), x3 = __shfl_xor(a[0], 3);
+    const double x1 = quad_xor<1>(a[0]), x2 = quad_xor<2>(a[0]), x3 = quad_xor<3>(a[0]);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int d = v ^ part;
@@ -923,7 +942,15 @@ __host__ __device__ constexpr int euler_strip(int N) { return 64 * euler_vpl(N) 
 // row by row by one wavefront.  `row` is the wavefront's LDS staging area of
 // VPL (N+1)^2 64 doubles (the current row's modes of each lane's variables,
 // [k*NM+q][lane]).
-template <int N, int STAGE, bool BND>
+// OFF32: every byte offset into the state arrays is below 2^32 (the host
+// checks 32 (N+1)^2 nx ny <= 2^32).  Each access is then the array's address
+// (a scalar) plus a 32-bit per-lane offset, and the plane offsets are 32-bit
+// scalars: far fewer scalar registers than one 64-bit address per plane.
+__host__ __device__ constexpr bool euler_off32_fits(int N, long long cells) {
+  return 32ll * (N + 1) * (N + 1) * cells <= (1ll << 32);
+}
+
+template <int N, int STAGE, bool BND, bool OFF32>
 __device__ __forceinline__ void euler_tile(const StageArgs &a, int bx, int by, int rows_per_block,
                                            double *__restrict__ row) {
   constexpr int NP = N + 1, NM = NP * NP, VPL = euler_vpl(N), LPC = 4 / VPL, STRIP = euler_strip(N);
@@ -944,8 +971,18 @@ __device__ __forceinline__ void euler_tile(const StageArgs &a, int bx, int by, i
   bool bad = false;
   double spx = 0.0, spy = 0.0;
 
-  // the lane's variables start at plane v0 * NM; offsets fit 32 bits
-  const double *ubase = a.u + (size_t)v0 * NM * plane;
+  // address in arr of mode q of the lane's variable k (variable v0 + k) of
+  // the cell at index idx
+  const unsigned plane8 = (unsigned)plane * 8u, lane8 = (unsigned)(v0 * NM) * plane8;
+  auto at = [&](auto *arr, int k, int q, unsigned idx) {
+    if constexpr (OFF32) {
+      using B = std::conditional_t<std::is_const<std::remove_pointer_t<decltype(arr)>>::value, const char, char>;
+      return reinterpret_cast<decltype(arr)>(reinterpret_cast<B *>(arr) +
+                                             (lane8 + idx * 8u + (unsigned)(k * NM + q) * plane8));
+    } else {
+      return arr + (size_t)(v0 * NM) * plane + ((size_t)(k * NM + q) * plane + idx);
+    }
+  };
   auto load2 = [&](const CellIdx &c, double (&U)[VPL][NM]) {
     const unsigned idx = (unsigned)c.idx;
     const unsigned long long sx = c.fx ? 0x8000000000000000ull : 0ull, sy = c.fy ? 0x8000000000000000ull : 0ull;
@@ -954,8 +991,7 @@ __device__ __forceinline__ void euler_tile(const StageArgs &a, int bx, int by, i
 #pragma unroll
       for (int q = 0; q < NM; ++q) {
         const int m = q % NP, n = q / NP;
-        const double *pl = ubase + (size_t)(k * NM + q) * plane;
-        double s = pl[idx];
+        double s = *at(a.u, k, q, idx);
         if ((m & 1) || (n & 1)) {
           const unsigned long long msk = ((m & 1) ? sx : 0ull) ^ ((n & 1) ? sy : 0ull);
           s = __longlong_as_double(__double_as_longlong(s) ^ (long long)msk);
@@ -1128,12 +1164,11 @@ __device__ __forceinline__ void euler_tile(const StageArgs &a, int bx, int by, i
     double Un[VPL][NM];
     auto load_un = [&]() {
       __builtin_amdgcn_sched_barrier(0);
-      const double *nbase = a.un + (size_t)v0 * NM * plane;
       const unsigned idx = (unsigned)(owner ? cellj : 0);
 #pragma unroll
       for (int k = 0; k < VPL; ++k)
 #pragma unroll
-        for (int q = 0; q < NM; ++q) Un[k][q] = nbase[(size_t)(k * NM + q) * plane + idx];
+        for (int q = 0; q < NM; ++q) Un[k][q] = *at(a.un, k, q, idx);
     };
     if (STAGE >= 2 && N <= 2) load_un();
     // y-faces: carried south flux, north flux from the next row's south trace
@@ -1168,15 +1203,15 @@ __device__ __forceinline__ void euler_tile(const StageArgs &a, int bx, int by, i
       for (int k = 0; k < VPL; ++k)
 #pragma unroll
         for (int q = 0; q < NM; ++q) {
-          const long kk = (long)((v0 + k) * NM + q) * plane + cellj;
+
           double r = 0.0;
           if (owner) {
             const double uo = rd(k, q);
             if (STAGE == 0) r = L[k][q];
             else if (STAGE == 1) r = uo + dt * L[k][q];
             else if (STAGE == 2) r = 0.75 * Un[k][q] + 0.25 * (uo + dt * L[k][q]);
-            else r = Un[k][q] / 3.0 + 2.0 * (uo + dt * L[k][q]) / 3.0;
-            a.out[kk] = r;
+            else r = rk3_last(Un[k][q], uo + dt * L[k][q]);
+            *at(a.out, k, q, (unsigned)cellj) = r;
           }
           if (q == 0) mm[k] = r * (T.b0[0] * T.b0[0]);
         }
@@ -1225,12 +1260,12 @@ __device__ inline int xcd_tile(int L, int total) {
   return x * q + min(x, r) + L / kXcd;
 }
 
-template <int N, int STAGE, bool BND>
+template <int N, int STAGE, bool BND, bool OFF32>
 __global__ __launch_bounds__(64, 2) void k_stage_2d_euler(StageArgs a, int rows_per_block) {
   __shared__ double row[euler_vpl(N) * (N + 1) * (N + 1) * 64];
   const int tiles_x = gridDim.x;
   const int w = xcd_tile(blockIdx.x + blockIdx.y * tiles_x, tiles_x * gridDim.y);
-  euler_tile<N, STAGE, BND>(a, w % tiles_x, w / tiles_x, rows_per_block, row);
+  euler_tile<N, STAGE, BND, OFF32>(a, w % tiles_x, w / tiles_x, rows_per_block, row);
 }
 
 // ---------------------------------------------------------------------------
@@ -2238,8 +2273,14 @@ void stage_launch(const LaunchCtx &c, const StageArgs &a) {
     constexpr int strip = euler_strip(NN);
     const int rows = march_rows(c, strip);
     dim3 grid((c.geo.nx + strip - 1) / strip, (c.geo.ny + rows - 1) / rows, 1);
-    if (c.special_bc) hipLaunchKernelGGL((k_stage_2d_euler<NN, STAGE, true>), grid, dim3(64), 0, S(c), a, rows);
-    else hipLaunchKernelGGL((k_stage_2d_euler<NN, STAGE, false>), grid, dim3(64), 0, S(c), a, rows);
+    const bool off32 = euler_off32_fits(NN, (long long)c.geo.nx * c.geo.ny);
+    if (c.special_bc) {
+      if (off32) hipLaunchKernelGGL((k_stage_2d_euler<NN, STAGE, true, true>), grid, dim3(64), 0, S(c), a, rows);
+      else hipLaunchKernelGGL((k_stage_2d_euler<NN, STAGE, true, false>), grid, dim3(64), 0, S(c), a, rows);
+    } else {
+      if (off32) hipLaunchKernelGGL((k_stage_2d_euler<NN, STAGE, false, true>), grid, dim3(64), 0, S(c), a, rows);
+      else hipLaunchKernelGGL((k_stage_2d_euler<NN, STAGE, false, false>), grid, dim3(64), 0, S(c), a, rows);
+    }
     return;
   }
   if (D == 2 && march && c.use_march) {

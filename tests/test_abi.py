@@ -96,6 +96,11 @@ def test_batch_workspace_and_validation(dg):
     assert nbytes(dict(e2, order=2, nx=8, ny=8), dict(e2, order=1, nx=8, ny=8, indicator=dg.IND_ALL))[0] == \
         dg.DG_ERR_INVALID_ARG
     assert nbytes(dict(e2, order=2, nx=50000, ny=50000))[0] == dg.DG_ERR_UNSUPPORTED
+    # per instance at most 2^27 / (N+1)^2 cells (32-bit byte offsets in the batched stage kernel)
+    assert nbytes(dict(e2, order=2, nx=4096, ny=3640))[0] == 0  # 14.91e6 cells: 32 * 9 * n <= 2^32
+    assert nbytes(dict(e2, order=2, nx=4096, ny=3641))[0] == dg.DG_ERR_UNSUPPORTED
+    assert nbytes(dict(e2, order=3, nx=4096, ny=2048))[0] == 0
+    assert nbytes(dict(e2, order=3, nx=4096, ny=2049))[0] == dg.DG_ERR_UNSUPPORTED
     n = ctypes.c_size_t()
     assert dg.lib().dg_batch_workspace_bytes(arr(dict(e2, order=2, nx=8, ny=8)), 0, ctypes.byref(n)) == \
         dg.DG_ERR_INVALID_ARG

@@ -8,7 +8,8 @@ benchmark (dg_step replaying its captured step after dg_autotune):
 The initial state is the oracle's (projection in bands of rows, then one
 limiter pass over the whole mesh); the GPU takes one SSP-RK3 step (CFL time
 step) of the whole mesh from it; sampled windows are then recomputed by the
-oracle from the same initial data and the GPU's time step.  One step with limiting after each stage reads at most six
+oracle from the same initial data and the oracle's CFL time step (which the
+GPU's must equal bit for bit).  One step with limiting after each stage reads at most six
 cells in each direction (per stage: one for the residual, one for the
 limiter), so each window carries a six-cell halo (the true boundary condition
 where it meets the domain boundary, wrapped data on periodic domains) and
@@ -42,15 +43,20 @@ def _oracle_initial_state(O, wl, band=128):
 
 
 def _gpu_one_step(wl, O):
+    """One GPU step (CFL rule) from the oracle's initial state; returns that
+    state (host), the GPU's result and the oracle's time step."""
     from paper_1904_11147_amd import dg
+    from tests.dgutil import oracle_problem
+    U0 = _oracle_initial_state(O, wl)
+    dt = oracle_problem(O, wl).cfl_dt(U0)
+    assert dt < wl.t_end
     p = dg.problem_from_workload(wl)
-    u0 = torch.from_numpy(_oracle_initial_state(O, wl)).cuda()
+    u0 = torch.from_numpy(U0).cuda()
     p.autotune(u0)
-    u1 = u0.clone()
-    t, n = p.step(u1, 0.0, wl.t_end, max_steps=1)
-    assert n == 1
+    t, n = p.step(u0, 0.0, wl.t_end, max_steps=1)
+    assert n == 1 and t == dt, (t, dt)  # the device's CFL rule gives the oracle's step exactly
     p.close()
-    return u0, u1, t
+    return torch.from_numpy(U0), u0, dt
 
 
 def _window_1d(O, wl, u0, u1, dt, a, b):
@@ -158,3 +164,43 @@ def test_double_mach_1920x480_q2_full_size(oracle):
             (100, 300), (480 - w, 0)]
     for ja, ia in wins:
         _window_dmr(oracle, wl, u0, u1, dt, ja, ia, w)
+
+
+def test_large_mesh_64bit_offsets(oracle):
+    """2D Euler Q1 on 5840 x 5800 periodic cells (4.3 GB of state): beyond
+    32 (N+1)^2 cells = 2^32 bytes, so the stage kernel runs its form with
+    64-bit addresses.  A smooth seeded state built here from closed forms, one
+    SSP-RK3 step with a fixed dt and the limiter, windows against the oracle
+    (interior, wrapped corners)."""
+    from types import SimpleNamespace
+    from paper_1904_11147_amd import dg
+    from paper_1904_11147_amd import workloads as W
+    nx, ny, order = 5840, 5800, 1
+    assert 32 * (order + 1) ** 2 * nx * ny > 2 ** 32
+    xc = (np.arange(nx) + 0.5) / nx
+    yc = (np.arange(ny) + 0.5) / ny
+    fx, gy = np.sin(2 * np.pi * xc)[None, :], np.cos(2 * np.pi * yc)[:, None]
+    rho = 1.0 + 0.2 * fx * gy
+    cons = W.euler2d_conserved(rho, 0.3, -0.2, 1.0 + 0.1 * fx * gy)
+    U = np.empty((4, 4, ny, nx))
+    for v in range(4):
+        c = np.broadcast_to(cons[v], (ny, nx))
+        U[v, 0] = 2.0 * c  # the mean is mode (0,0) / 2
+        U[v, 1] = 0.01 * c * np.cos(2 * np.pi * xc)[None, :]  # psi_1(x) psi_0(y)
+        U[v, 2] = 0.01 * c * np.sin(2 * np.pi * yc)[:, None]  # psi_0(x) psi_1(y)
+        U[v, 3] = 0.002 * c * fx * gy
+        del c
+    h = 1.0 / nx
+    dt = 0.02 * h
+    cfg = dict(dim=2, equation=dg.EULER, order=order, nx=nx, ny=ny, bc=(0, 0, 0, 0), limiter=dg.LIM_CSWENO,
+               indicator=dg.IND_TVB, cfl=0.1)
+    p = dg.Problem(**cfg)
+    u1 = torch.from_numpy(U).cuda()
+    t, n = p.step(u1, 0.0, 1.0, dt=dt, max_steps=1)
+    assert n == 1 and t == dt
+    p.close()
+    wl = SimpleNamespace(name="euler2d q1 5840x5800", nx=nx, ny=ny, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
+                         bc=(0, 0, 0, 0), equation=dg.EULER, order=order, gamma=1.4, cfl=0.1)
+    u0 = torch.from_numpy(U)
+    for ja, ia in ((0, 0), (ny - 16, nx - 16), (2900, 2920), (17, 5000), (4321, 1234)):
+        _window_2d(oracle, wl, u0, u1, dt, ja, ia, 16)
