@@ -476,6 +476,21 @@ __device__ inline void lm_load_weights(const LearnedArgs &L, uint16_t *wl) {
   __syncthreads();
 }
 
+// The value of lane r - 1 (UP) or r + 1 within each row of 16 lanes by a DPP
+// row shift (a register move, no LDS round trip); the lane with no source in
+// its row keeps its own value.  The shift writes a register other than its
+// source.
+template <bool UP>
+__device__ __forceinline__ double row_shift1(double v) {
+  constexpr int ctrl = UP ? 0x111 : 0x101;  // row_shr:1 / row_shl:1
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctrl, 0xF, 0xF, false);
+  const int r = __lane_id() & 15;
+  return (UP ? r == 0 : r == 15) ? v
+                                 : __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // One wavefront's strip: columns x0-1 .. x0+14 (owned x0 .. x0+13), rows
 // j0 .. j1-1.  emit(active, flag, margin, p, cell) is called by every lane
 // once per row (active: an owned cell, from lane group 0).
@@ -525,17 +540,17 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
     if constexpr (keep_we) {
 #pragma unroll
       for (int q = 0; q < NM; ++q) {
-        Wv[q] = __shfl_up(Cv[q], 1, 16);
-        Ev[q] = __shfl_down(Cv[q], 1, 16);
+        Wv[q] = row_shift1<true>(Cv[q]);
+        Ev[q] = row_shift1<false>(Cv[q]);
       }
     }
     auto west = [&](int q) -> double {
       if constexpr (keep_we) return Wv[q];
-      else return __shfl_up(Cv[q], 1, 16);
+      else return row_shift1<true>(Cv[q]);
     };
     auto east = [&](int q) -> double {
       if constexpr (keep_we) return Ev[q];
-      else return __shfl_down(Cv[q], 1, 16);
+      else return row_shift1<false>(Cv[q]);
     };
     // TVB decision of this variable (the expressions of tvb_cell), combined over the cell's lanes
     bool tflag = false;
