@@ -530,6 +530,15 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
 #pragma unroll
   for (int f = FV; f < BV; ++f) fl[(f / 4) * 256 + f % 4] = 0;
   const double k0 = T.b0[0] * T.b0[0];
+  // Q1, Q2: the layer-2 weight fragments stay in registers for the whole strip
+  constexpr bool w2_regs = N <= 2;
+  bf16x4_t w2f[w2_regs ? 4 : 1][w2_regs ? 4 : 1];
+  if constexpr (w2_regs) {
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) w2f[nb][kb] = load4(wl + S::W1 + ((nb * 4 + kb) * 64 + lane) * 4);
+  }
   for (int j = j0; j < j1; ++j) {
     double Pv[NM];
     loadrow(j + 2, Pv);  // in flight while this row is evaluated
@@ -618,7 +627,9 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
     for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb)
-        h[nb] = mfma16(load4(wl + S::W1 + ((nb * 4 + kb) * 64 + lane) * 4), h1[kb], h[nb]);
+        h[nb] = mfma16(w2_regs ? w2f[w2_regs ? nb : 0][w2_regs ? kb : 0]
+                               : load4(wl + S::W1 + ((nb * 4 + kb) * 64 + lane) * 4),
+                       h1[kb], h[nb]);
     // layer 3 and the decision
     float part = 0.f;
 #pragma unroll
