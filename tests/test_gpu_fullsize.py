@@ -166,12 +166,32 @@ def test_double_mach_1920x480_q2_full_size(oracle):
         _window_dmr(oracle, wl, u0, u1, dt, ja, ia, w)
 
 
-def test_large_mesh_64bit_offsets(oracle):
-    """2D Euler Q1 on 5840 x 5800 periodic cells (4.3 GB of state): beyond
+def _window_sides(O, cfg, u0, u1, dt, ja, ia, w):
+    """Window of a non-periodic mesh: sides on the domain boundary keep their
+    true kinds, inner sides are transmissive (contaminated halo)."""
+    nx, ny = cfg["nx"], cfg["ny"]
+    hx, hy = (cfg["x1"] - cfg["x0"]) / nx, (cfg["y1"] - cfg["y0"]) / ny
+    ilo, ihi = max(ia - HALO, 0), min(ia + w + HALO, nx)
+    jlo, jhi = max(ja - HALO, 0), min(ja + w + HALO, ny)
+    at_edge = (ilo == 0, ihi == nx, jlo == 0, jhi == ny)
+    bc = tuple(cfg["bc"][k] if at_edge[k] else 1 for k in range(4))
+    c = dict(cfg, nx=ihi - ilo, ny=jhi - jlo, x0=cfg["x0"] + ilo * hx, x1=cfg["x0"] + ihi * hx,
+             y0=cfg["y0"] + jlo * hy, y1=cfg["y0"] + jhi * hy, bc=bc)
+    op = O.Problem(**c)
+    ref = op.step(np.ascontiguousarray(u0[..., jlo:jhi, ilo:ihi].cpu().numpy()), dt)
+    oi, oj = ia - ilo, ja - jlo
+    got = u1[..., ja:ja + w, ia:ia + w].cpu().numpy()
+    assert_close(got, ref[..., oj:oj + w, oi:oi + w], what=f"window ({ja},{ia}) size {w}, sides {cfg['bc']}")
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0, 0), (2, 1, 2, 1)], ids=["periodic", "walls"])
+def test_large_mesh_64bit_offsets(oracle, bc):
+    """2D Euler Q1 on 5840 x 5800 cells (4.3 GB of state): beyond
     32 (N+1)^2 cells = 2^32 bytes, so the stage kernel runs its form with
-    64-bit addresses.  A smooth seeded state built here from closed forms, one
-    SSP-RK3 step with a fixed dt and the limiter, windows against the oracle
-    (interior, wrapped corners)."""
+    64-bit addresses (with reflective west and south sides: its boundary-aware
+    form).  A smooth seeded state built here from closed forms, one SSP-RK3
+    step with a fixed dt and the limiter, windows against the oracle
+    (corners, interior)."""
     from types import SimpleNamespace
     from paper_1904_11147_amd import dg
     from paper_1904_11147_amd import workloads as W
@@ -192,15 +212,19 @@ def test_large_mesh_64bit_offsets(oracle):
         del c
     h = 1.0 / nx
     dt = 0.02 * h
-    cfg = dict(dim=2, equation=dg.EULER, order=order, nx=nx, ny=ny, bc=(0, 0, 0, 0), limiter=dg.LIM_CSWENO,
-               indicator=dg.IND_TVB, cfl=0.1)
-    p = dg.Problem(**cfg)
+    cfg = dict(dim=2, equation=dg.EULER, order=order, nx=nx, ny=ny, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc=bc,
+               gamma=1.4, cfl=0.1)
+    p = dg.Problem(**cfg, limiter=dg.LIM_CSWENO, indicator=dg.IND_TVB)
     u1 = torch.from_numpy(U).cuda()
     t, n = p.step(u1, 0.0, 1.0, dt=dt, max_steps=1)
     assert n == 1 and t == dt
     p.close()
-    wl = SimpleNamespace(name="euler2d q1 5840x5800", nx=nx, ny=ny, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
-                         bc=(0, 0, 0, 0), equation=dg.EULER, order=order, gamma=1.4, cfl=0.1)
     u0 = torch.from_numpy(U)
-    for ja, ia in ((0, 0), (ny - 16, nx - 16), (2900, 2920), (17, 5000), (4321, 1234)):
-        _window_2d(oracle, wl, u0, u1, dt, ja, ia, 16)
+    wins = ((0, 0), (ny - 16, nx - 16), (2900, 2920), (17, 5000), (4321, 1234), (0, 3000), (3000, 0))
+    for ja, ia in wins:
+        if bc[0] == 0:
+            wl = SimpleNamespace(name="euler2d q1 5840x5800", bc=bc, equation=dg.EULER, order=order, gamma=1.4,
+                                 cfl=0.1, **{k: cfg[k] for k in ("nx", "ny", "x0", "x1", "y0", "y1")})
+            _window_2d(oracle, wl, u0, u1, dt, ja, ia, 16)
+        else:
+            _window_sides(oracle, cfg, u0, u1, dt, ja, ia, 16)
