@@ -865,35 +865,34 @@ __device__ inline double euler_speed(const EulerPrim &s, double rho, double g) {
 // Q3, whose modes would not fit two variables per lane).  `part` is the
 // lane's index within its cell.
 
-// The value of lane (lane ^ X) (X in 1..3: the cell's lanes are one aligned
-// group of four) by a DPP quad permutation, a register move with no LDS round
-// trip.  Every lane of the wavefront is active where it is called.
-template <int X>
-__device__ __forceinline__ double quad_xor(double v) {
-  constexpr int ctrl = (0 ^ X) | ((1 ^ X) << 2) | ((2 ^ X) << 4) | ((3 ^ X) << 6);
+// Lane P_{l} of each aligned group of four lanes, for lane l of the group, by
+// a DPP quad permutation: a register move with no LDS round trip (the cell's
+// lanes are one such group or half of one).  Every lane of the wavefront is
+// active where it is called.
+template <int P0, int P1, int P2, int P3>
+__device__ __forceinline__ double quad_perm(double v) {
+  constexpr int ctrl = P0 | (P1 << 2) | (P2 << 4) | (P3 << 6);
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_mov_dpp((int)b, ctrl, 0xF, 0xF, false);
   const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), ctrl, 0xF, 0xF, false);
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// The full state (rho, mx, my, E) at a point from the cell's lanes.
+// The full state (rho, mx, my, E) at a point from the cell's lanes, each
+// component broadcast from the lane that holds it (no selects).
 template <int VPL>
 __device__ inline void gather_state(const double (&a)[VPL], int part, double (&w)[4]) {
-  if constexpr (VPL == 2) {
-    const double b0 = quad_xor<1>(a[0]), b1 = quad_xor<1>(a[1]);
-    const bool h1 = part != 0;
-    w[0] = h1 ? b0 : a[0];
-    w[1] = h1 ? b1 : a[1];
-    w[2] = h1 ? a[0] : b0;
-    w[3] = h1 ? a[1] : b1;
-  } else {
-    const double x1 = quad_xor<1>(a[0]), x2 = quad_xor<2>(a[0]), x3 = quad_xor<3>(a[0]);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int d = v ^ part;
-      w[v] = d == 0 ? a[0] : (d == 1 ? x1 : (d == 2 ? x2 : x3));
-    }
+  (void)part;
+  if constexpr (VPL == 2) {  // variables 0, 1 in the even lane of the pair, 2, 3 in the odd one
+    w[0] = quad_perm<0, 0, 2, 2>(a[0]);
+    w[1] = quad_perm<0, 0, 2, 2>(a[1]);
+    w[2] = quad_perm<1, 1, 3, 3>(a[0]);
+    w[3] = quad_perm<1, 1, 3, 3>(a[1]);
+  } else {  // variable v in lane v of the four
+    w[0] = quad_perm<0, 0, 0, 0>(a[0]);
+    w[1] = quad_perm<1, 1, 1, 1>(a[0]);
+    w[2] = quad_perm<2, 2, 2, 2>(a[0]);
+    w[3] = quad_perm<3, 3, 3, 3>(a[0]);
   }
 }
 
