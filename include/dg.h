@@ -82,8 +82,9 @@ typedef struct dg_config {
                           direction, eigenvectors of the flux Jacobian at the troubled
                           cell's mean state, end of Sec. 3; Burgers: as DG_LIM_CSWENO) */
   int32_t indicator;   /* DG_IND_TVB (TVB-modified minmod), DG_IND_ALL (every cell),
-                          DG_IND_LEARNED (2D Euler only: the MLP of dg_set_learned with the
-                          TVB decision in its uncertain band), or DG_IND_KXRCF (the
+                          DG_IND_LEARNED (2D Euler with periodic or transmissive sides
+                          only: the MLP of dg_set_learned with the TVB decision in its
+                          uncertain band), or DG_IND_KXRCF (the
                           inflow-jump indicator of Krivodonova et al. that Sec. 3, step 1
                           cites: |integral of the trace jump over the inflow boundary| /
                           (h^((N+1)/2) |inflow boundary| max_q |u|) > 1, h the cell's
@@ -194,8 +195,12 @@ int dg_cfl_dt(dg_problem *p, const double *state, double *dt);
  * max_steps steps.  dt > 0: fixed step; dt <= 0: the CFL rule of dg_cfl_dt,
  * recomputed each step on the device.  The last step is clipped so that t
  * lands on t_end.  *t (host) is updated; *steps_taken (host, may be NULL)
- * receives the number of steps.  The step sequence is captured once in a HIP
- * graph per state pointer and replayed. */
+ * receives the number of steps.  A step in which a kernel meets a
+ * non-physical state is the last one: the call returns DG_ERR_NONPHYSICAL
+ * with *t and *steps_taken after that step (also returned, without ending
+ * the run early, for a non-physical state met before the call and not yet
+ * read by dg_status).  The step sequence is captured once in a HIP graph per
+ * state pointer and replayed. */
 int dg_step(dg_problem *p, double *state, double *t, double t_end, double dt, int32_t max_steps,
             int32_t *steps_taken);
 
@@ -338,9 +343,13 @@ int dg_batch_step(dg_batch *b, double *states, const int64_t *offsets, double *t
 
 /* Weights of the learned indicator for the instances of one order (required
  * for each order present when the batch uses DG_IND_LEARNED); as
- * dg_set_learned. */
+ * dg_set_learned.  prob (device float, may be NULL; kept as a pointer like
+ * the weights) receives, at every indicator pass, p of cell c of instance i
+ * of this order at prob[offsets[i] + c] (offsets as given to dg_batch_step,
+ * so a buffer with as many elements as the states buffer serves every
+ * order). */
 int dg_batch_set_learned(dg_batch *b, int32_t order, const uint16_t *w_bf16, const float *master, double band_lo,
-                         double band_hi);
+                         double band_hi, float *prob);
 
 #ifdef __cplusplus
 }

@@ -100,6 +100,12 @@ int validate_config(const dg_config *c) {
       c->indicator != DG_IND_KXRCF)
     return DG_ERR_UNSUPPORTED;
   if (c->indicator == DG_IND_LEARNED && (c->dim != 2 || c->equation != DG_EQ_EULER)) return DG_ERR_UNSUPPORTED;
+  // the network's features see ghost cells by periodic wrap or even reflection
+  // only (the sides it was trained on): no walls, inflow or switching sides
+  if (c->indicator == DG_IND_LEARNED)
+    for (int k = 0; k < 4; ++k)
+      if (c->bc[k] == DG_BC_REFLECTIVE || c->bc[k] == DG_BC_INFLOW || c->bc_beyond[k] != -1)
+        return DG_ERR_UNSUPPORTED;
   if (c->negw_mode != DG_NEGW_SPLIT && c->negw_mode != DG_NEGW_RAW) return DG_ERR_INVALID_ARG;
   if (!(c->x1 > c->x0) || (c->dim == 2 && !(c->y1 > c->y0))) return DG_ERR_INVALID_ARG;
   if (c->equation == DG_EQ_EULER && !(c->gamma > 1.0)) return DG_ERR_INVALID_ARG;
@@ -122,7 +128,12 @@ int ensure_tables(int device) {
     int rc = dg::build_order_tables(N, &tabs[N]);
     if (rc) return rc;
   }
-  int rc = dg::upload_tables(tabs);
+  int rc = dg::upload_tables_part0(tabs);
+  if (!rc) rc = dg::upload_tables_part1(tabs);
+  if (!rc) rc = dg::upload_tables_part2(tabs);
+  if (!rc) rc = dg::upload_tables_part3(tabs);
+  if (!rc) rc = dg::upload_tables_part4(tabs);
+  if (!rc) rc = dg::upload_tables_part5(tabs);
   if (rc) return rc;
   g_tables_ready[device] = true;
   return DG_OK;
@@ -357,6 +368,39 @@ int build_graph(dg_problem *p, double *state, bool cfl_mode) {
   return DG_OK;
 }
 
+// Launch context of a configuration on a uniform mesh: geometry, modes and
+// the scalar block sc; the state-sized buffers, flags, margins and list are
+// left null for the caller to point at its memory.
+void fill_ctx(const dg_config *cfg, void *stream, DevScalars *sc, LaunchCtx *out) {
+  LaunchCtx &c = *out;
+  c = LaunchCtx{};
+  c.dim = cfg->dim;
+  c.eq = cfg->equation;
+  c.N = cfg->order;
+  c.nv = dg::num_vars(cfg);
+  c.nm = dg::num_modes(cfg);
+  dg::fill_geometry(cfg, &c.geo);
+  c.stream = stream;
+  c.sc = sc;
+  c.cfl = cfg->cfl;
+  c.limiter = cfg->limiter;
+  c.indicator = cfg->indicator;
+  c.positivity = cfg->positivity;
+  c.timed_bc = 0;
+  for (int k = 2; k < 4; ++k)
+    if (c.geo.bcb[k] >= 0 && c.geo.bsw[k][1] != 0.0) c.timed_bc = 1;
+  c.special_bc = dg::special_bc(c.geo);
+  c.geo.tb = &sc->tb;
+  c.grid_cap = 2048;
+  c.use_march = 1;
+  c.rows = 0;
+  c.mlp_w = nullptr;
+  c.mlp_m = nullptr;
+  c.mlp_prob = nullptr;
+  c.band_lo = 0.2;
+  c.band_hi = 0.8;
+}
+
 }  // namespace
 
 extern "C" {
@@ -390,43 +434,20 @@ int dg_init(const dg_config *cfg, void *workspace, size_t workspace_bytes, void 
   p->state_elems = (size_t)cfg->nx * cfg->ny * num_vars(cfg) * num_modes(cfg);
   char *ws = (char *)workspace;
   LaunchCtx &c = p->ctx;
-  c.dim = cfg->dim;
-  c.eq = cfg->equation;
-  c.N = cfg->order;
-  c.nv = dg::num_vars(cfg);
-  c.nm = dg::num_modes(cfg);
-  dg::fill_geometry(cfg, &c.geo);
-  c.stream = stream;
-  c.sc = (DevScalars *)(ws + L.scalars);
+  fill_ctx(cfg, stream, (DevScalars *)(ws + L.scalars), &c);
   c.bufA = (double *)(ws + L.bufA);
   c.bufB = (double *)(ws + L.bufB);
   c.flags = (uint8_t *)(ws + L.flags);
   c.margin = (double *)(ws + L.margin);
   c.list = (int32_t *)(ws + L.list);
-  c.cfl = cfg->cfl;
-  c.limiter = cfg->limiter;
-  c.indicator = cfg->indicator;
-  c.positivity = cfg->positivity;
   if (cfg->x_nodes) {
     rc = upload_mesh(cfg, ws, L, p->user_stream, &c.geo);
     if (rc) {
       delete p;
       return rc;
     }
+    c.special_bc = dg::special_bc(c.geo);
   }
-  c.timed_bc = 0;
-  for (int k = 2; k < 4; ++k)
-    if (c.geo.bcb[k] >= 0 && c.geo.bsw[k][1] != 0.0) c.timed_bc = 1;
-  c.special_bc = dg::special_bc(c.geo);
-  c.geo.tb = &c.sc->tb;
-  c.grid_cap = 2048;
-  c.use_march = 1;
-  c.rows = 0;
-  c.mlp_w = nullptr;
-  c.mlp_m = nullptr;
-  c.mlp_prob = nullptr;
-  c.band_lo = 0.2;
-  c.band_hi = 0.8;
   if (hipMemsetAsync(c.sc, 0, sizeof(DevScalars), p->user_stream) != hipSuccess ||
       hipStreamSynchronize(p->user_stream) != hipSuccess) {
     delete p;
@@ -526,6 +547,11 @@ int dg_step(dg_problem *p, double *state, double *t, double t_end, double dt, in
   DevScalars h;
   int rc = sync_status(p, &h);
   if (rc == DG_ERR_HIP) return rc;
+  // A non-physical state met before this call is reported by the return
+  // value; the step loop starts with a clear status word and ends after the
+  // step in which a kernel meets one (the time-step kernel marks the run done).
+  const int32_t entry_status = h.status;
+  h.status = 0;
   h.t = *t;
   h.t_end = t_end;
   h.dt_fixed = cfl_mode ? 0.0 : dt;
@@ -578,7 +604,13 @@ int dg_step(dg_problem *p, double *state, double *t, double t_end, double dt, in
   }
   *t = h.t;
   if (steps_taken) *steps_taken = h.steps;
-  return h.status ? DG_ERR_NONPHYSICAL : DG_OK;
+  if (entry_status && !h.status) {  // the status word stays set until dg_status reads it
+    const int32_t one = 1;
+    if (hipMemcpyAsync(&p->ctx.sc->status, &one, sizeof(one), hipMemcpyHostToDevice, p->user_stream) != hipSuccess ||
+        hipStreamSynchronize(p->user_stream) != hipSuccess)
+      return DG_ERR_HIP;
+  }
+  return (h.status || entry_status) ? DG_ERR_NONPHYSICAL : DG_OK;
 }
 
 int dg_autotune(dg_problem *p, const double *state, int32_t *rows, float *ms) {

@@ -131,6 +131,14 @@ int upload_inst(dg_batch *b) {
   return hip_ok(hipStreamSynchronize(b->user_stream));
 }
 
+// Learned-indicator probability outputs of the instances, at the states' offsets.
+void set_prob_pointers(dg_batch *b) {
+  for (int i = 0; i < b->n; ++i) {
+    float *base = b->ctx.learned[b->inst[i].order].prob;
+    b->inst[i].prob = (base && b->states) ? base + b->offsets[i] : nullptr;
+  }
+}
+
 // Points the descriptors at the caller's states (uploaded when they change).
 int set_states(dg_batch *b, double *states, const int64_t *offsets) {
   if (!states || !offsets) return DG_ERR_INVALID_ARG;
@@ -149,6 +157,7 @@ int set_states(dg_batch *b, double *states, const int64_t *offsets) {
     b->offsets[i] = offsets[i];
   }
   b->states = states;
+  set_prob_pointers(b);
   return upload_inst(b);
 }
 
@@ -361,11 +370,12 @@ int dg_batch_autotune(dg_batch *b, double *states, const int64_t *offsets, int32
 }
 
 int dg_batch_set_learned(dg_batch *b, int32_t order, const uint16_t *w_bf16, const float *master, double band_lo,
-                         double band_hi) {
+                         double band_hi, float *prob) {
   if (!b || order < 1 || order > kMaxN || !w_bf16 || !master || !(band_lo <= band_hi)) return DG_ERR_INVALID_ARG;
-  b->ctx.learned[order] = dg::BatchLearned{w_bf16, master, (float)band_lo, (float)band_hi};
+  b->ctx.learned[order] = dg::BatchLearned{w_bf16, master, (float)band_lo, (float)band_hi, prob};
   drop_graph(b);
-  return DG_OK;
+  set_prob_pointers(b);
+  return b->states ? upload_inst(b) : DG_OK;
 }
 
 int dg_batch_step(dg_batch *b, double *states, const int64_t *offsets, double *t, const double *t_end,

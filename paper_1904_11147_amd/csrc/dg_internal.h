@@ -51,8 +51,15 @@ struct WenoCoef {
 };
 int build_weno_coef(int N, double rl, double rr, WenoCoef *out);
 
-// Uploads tables of all orders to the current device (kernel TU).
-int upload_tables(const OrderTables *tabs /* [kMaxN+1], index N */);
+// Uploads tables of all orders to the current device, one call per part of
+// the kernel code (each part is its own code object with its own copy).
+constexpr int kKernelParts = 6;
+int upload_tables_part0(const OrderTables *tabs /* [kMaxN+1], index N */);
+int upload_tables_part1(const OrderTables *tabs);
+int upload_tables_part2(const OrderTables *tabs);
+int upload_tables_part3(const OrderTables *tabs);
+int upload_tables_part4(const OrderTables *tabs);
+int upload_tables_part5(const OrderTables *tabs);
 
 // Device scalars at the head of the workspace.
 struct DevScalars {
@@ -146,6 +153,7 @@ struct BatchInst {
   int32_t indicator;   // DG_IND_*
   int32_t pad;
   double cfl;
+  float *prob;         // learned indicator: p of every cell at each pass (optional, caller memory)
 };
 
 // Work queue of the instances of one order, rebuilt on the device after every
@@ -164,6 +172,7 @@ struct BatchLearned {  // learned indicator of one order (null weights: not set)
   const uint16_t *W;
   const float *M;
   float band_lo, band_hi;
+  float *prob;  // optional: p of instance i's cell c at prob[offsets[i] + c]
 };
 
 // Work of one batched call, described to the kernel TU.
@@ -191,6 +200,10 @@ int num_modes(const dg_config *c);
 // Kernel-TU entry points (host functions, enqueue only).
 int launch_residual(const LaunchCtx &c, const double *u, double *out);
 int launch_stage(const LaunchCtx &c, int stage, const double *u, const double *un, double *out, bool want_speed);
+// The stage launches of one order (stage 0: residual of u into out).
+int launch_stage_order1(const LaunchCtx &c, int stage, const double *u, const double *un, double *out, bool want_speed);
+int launch_stage_order2(const LaunchCtx &c, int stage, const double *u, const double *un, double *out, bool want_speed);
+int launch_stage_order3(const LaunchCtx &c, int stage, const double *u, const double *un, double *out, bool want_speed);
 int launch_limit(const LaunchCtx &c, double *u, double *side, int count_slot, uint8_t *flags, double *margin,
                  const uint8_t *flags_override);
 int launch_speed(const LaunchCtx &c, const double *u);

@@ -29,11 +29,24 @@
 
 #include "dg_internal.h"
 
+// The file is compiled kKernelParts times, with DG_PART = 0 .. kKernelParts-1,
+// so that the kernel families build in parallel: parts 0, 4, 5 the stage
+// kernels of orders 1, 2, 3 (part 0 also the time-step and set-up kernels),
+// part 1 the limiter, part 2 the network, part 3 the batched launches.  Each
+// part is its own code object with its own copy of the coefficient tables.
+#ifndef DG_PART
+#error "compile with -DDG_PART=0..5"
+#endif
+#define DG_CAT2(a, b) a##b
+#define DG_CAT(a, b) DG_CAT2(a, b)
+
 namespace dg {
 
-__constant__ OrderTables c_tab[kMaxN + 1];
+namespace {
+__constant__ OrderTables c_tab[kMaxN + 1];  // this part's copy (internal linkage)
+}  // namespace
 
-int upload_tables(const OrderTables *tabs) {
+int DG_CAT(upload_tables_part, DG_PART)(const OrderTables *tabs) {
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_tab), tabs, sizeof(OrderTables) * (kMaxN + 1), 0,
                                    hipMemcpyHostToDevice);
   return e == hipSuccess ? DG_OK : DG_ERR_HIP;
@@ -1349,7 +1362,10 @@ __device__ inline void decide_dt(DevScalars *sc, int dim, double cfl, double hx,
 }
 
 __global__ void k_dt_finalize(DevScalars *sc, int dim, double cfl, double hx, double hy) {
-  if (threadIdx.x == 0) decide_dt(sc, dim, cfl, hx, hy);
+  if (threadIdx.x == 0) {
+    if (sc->status) sc->done = 1;  // a non-physical state ends the run after the step that met it
+    decide_dt(sc, dim, cfl, hx, hy);
+  }
 }
 
 // Time of the boundary data: tn + frac dt during a step (frac >= 0), or the
@@ -2295,23 +2311,63 @@ void stage_launch(const LaunchCtx &c, const StageArgs &a) {
 
 }  // namespace
 
-int launch_residual(const LaunchCtx &c, const double *u, double *out) {
-  StageArgs a{u, nullptr, out, c.sc, c.geo, 0};
-  return dispatch(c, [&](auto D, auto E, auto NN) {
-    stage_launch<decltype(D)::value, decltype(E)::value, decltype(NN)::value, 0>(c, a);
-  });
-}
-
-int launch_stage(const LaunchCtx &c, int stage, const double *u, const double *un, double *out, bool want_speed) {
+// Stage kernels of one order (the largest share of the build): order 1 in
+// part 0, order 2 in part 4, order 3 in part 5.  stage 0 is the residual.
+#if DG_PART == 0 || DG_PART == 4 || DG_PART == 5
+#if DG_PART == 0
+#define DG_STAGE_N 1
+#elif DG_PART == 4
+#define DG_STAGE_N 2
+#else
+#define DG_STAGE_N 3
+#endif
+int DG_CAT(launch_stage_order, DG_STAGE_N)(const LaunchCtx &c, int stage, const double *u, const double *un,
+                                           double *out, bool want_speed) {
+  constexpr int n = DG_STAGE_N;
   StageArgs a{u, un, out, c.sc, c.geo, want_speed ? 1 : 0};
-  return dispatch(c, [&](auto D, auto E, auto NN) {
-    constexpr int d = decltype(D)::value, e = decltype(E)::value, n = decltype(NN)::value;
-    if (stage == 1) stage_launch<d, e, n, 1>(c, a);
+  auto go = [&](auto D, auto E) {
+    constexpr int d = decltype(D)::value, e = decltype(E)::value;
+    if (stage == 0) stage_launch<d, e, n, 0>(c, a);
+    else if (stage == 1) stage_launch<d, e, n, 1>(c, a);
     else if (stage == 2) stage_launch<d, e, n, 2>(c, a);
     else stage_launch<d, e, n, 3>(c, a);
-  });
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  if (c.N != n || stage < 0 || stage > 3) return DG_ERR_INVALID_ARG;
+  if (c.dim == 1 && c.eq == 0) go(I1{}, I0{});
+  else if (c.dim == 1 && c.eq == 1) go(I1{}, I1{});
+  else if (c.dim == 2 && c.eq == 0) go(I2{}, I0{});
+  else if (c.dim == 2 && c.eq == 1) go(I2{}, I1{});
+  else return DG_ERR_UNSUPPORTED;
+  return check_launch();
+}
+#endif  // DG_PART == 0 || DG_PART == 4 || DG_PART == 5
+
+#if DG_PART == 0
+int launch_stage(const LaunchCtx &c, int stage, const double *u, const double *un, double *out, bool want_speed) {
+  if (stage < 1 || stage > 3) return DG_ERR_INVALID_ARG;
+  switch (c.N) {
+    case 1: return launch_stage_order1(c, stage, u, un, out, want_speed);
+    case 2: return launch_stage_order2(c, stage, u, un, out, want_speed);
+    case 3: return launch_stage_order3(c, stage, u, un, out, want_speed);
+    default: return DG_ERR_UNSUPPORTED;
+  }
 }
 
+int launch_residual(const LaunchCtx &c, const double *u, double *out) {
+  switch (c.N) {
+    case 1: return launch_stage_order1(c, 0, u, nullptr, out, false);
+    case 2: return launch_stage_order2(c, 0, u, nullptr, out, false);
+    case 3: return launch_stage_order3(c, 0, u, nullptr, out, false);
+    default: return DG_ERR_UNSUPPORTED;
+  }
+}
+
+#endif  // DG_PART == 0
+
+#if DG_PART == 1
 int launch_limit(const LaunchCtx &c, double *u, double *side, int count_slot, uint8_t *flags, double *margin,
                  const uint8_t *flags_override) {
   LimitArgs a;
@@ -2333,13 +2389,13 @@ int launch_limit(const LaunchCtx &c, double *u, double *side, int count_slot, ui
     constexpr int NV = Phys<e, d>::NV;
     dim3 block, grid = cell_grid(c, block);
     bool learned = false;
-    if constexpr (d == 2 && e == DG_EQ_EULER) {
+    if constexpr (d == 2 && e == DG_EQ_EULER && !bnd) {  // (the learned indicator takes no special sides)
       if (c.indicator == DG_IND_LEARNED && !flags_override) {
         LearnedArgs L{c.mlp_w, c.mlp_m, MlpLayout{5 * NM * NV, (5 * NM * NV + 15) / 16 * 16}, (float)c.band_lo,
                       (float)c.band_hi, c.mlp_prob};
         constexpr int waves = lm_waves(n);
         const int groups = ((c.geo.nx + kLmStrip - 1) / kLmStrip + waves - 1) / waves;
-        hipLaunchKernelGGL((k_indicator_learned<n, e, bnd>), dim3(groups, (c.geo.ny + kLmRows - 1) / kLmRows),
+        hipLaunchKernelGGL((k_indicator_learned<n, e, false>), dim3(groups, (c.geo.ny + kLmRows - 1) / kLmRows),
                            dim3(64 * waves), 0, S(c), a, L, kLmRows);
         learned = true;
       }
@@ -2368,6 +2424,9 @@ int launch_limit(const LaunchCtx &c, double *u, double *side, int count_slot, ui
   });
 }
 
+#endif  // DG_PART == 1
+
+#if DG_PART == 0
 int launch_speed(const LaunchCtx &c, const double *u) {
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, S(c), c.sc, 1);
   const long cells = (long)c.geo.nx * c.geo.ny;
@@ -2424,6 +2483,9 @@ int launch_project(const LaunchCtx &c, const double *pv, int j0, int nrows, doub
 }
 
 
+#endif  // DG_PART == 0
+
+#if DG_PART == 2
 int launch_mlp_features(const LaunchCtx &c, const double *u, float *f32, uint16_t *bf, int KP) {
   const long cells = (long)c.geo.nx * c.geo.ny;
   dim3 grid((unsigned)((cells + kBlock - 1) / kBlock));
@@ -2492,6 +2554,9 @@ int launch_mlp_adam(float *M, float *m1, float *m2, float *G, uint16_t *W, int F
   return check_launch();
 }
 
+#endif  // DG_PART == 2
+
+#if DG_PART == 3
 // ---------------------------------------------------------------------------
 // Batched execution launchers.
 // ---------------------------------------------------------------------------
@@ -2574,5 +2639,7 @@ int batch_launch_limit(const BatchCtx &b, int order, int slot) {
     else go(std::integral_constant<int, 2>{});
   });
 }
+
+#endif  // DG_PART == 3
 
 }  // namespace dg

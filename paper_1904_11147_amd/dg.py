@@ -113,7 +113,7 @@ def lib():
             "dg_batch_autotune": [vp, vp, P(ctypes.c_int64), P(i32), P(i32), P(ctypes.c_float)],
             "dg_batch_set_tiles": [vp, i32, i32],
             "dg_batch_step": [vp, vp, P(ctypes.c_int64), P(d), P(d), i32, P(i32), P(i32), P(ctypes.c_int64)],
-            "dg_batch_set_learned": [vp, i32, vp, vp, d, d],
+            "dg_batch_set_learned": [vp, i32, vp, vp, d, d, vp],
             "dg_set_time": [vp, d],
         }
         for name, args in sigs.items():
@@ -427,10 +427,13 @@ class Batch:
         if rc:
             raise DGError(rc, "dg_batch_set_tiles")
 
-    def set_learned(self, order, w_bf16, master, band=(0.2, 0.8)):
-        self._learned[order] = (w_bf16, master)  # the library keeps the pointers
+    def set_learned(self, order, w_bf16, master, band=(0.2, 0.8), prob=None):
+        """prob: optional float tensor with as many elements as `states`;
+        every indicator pass writes p of instance i's cell c at
+        prob[offsets[i] + c]."""
+        self._learned[order] = (w_bf16, master, prob)  # the library keeps the pointers
         rc = lib().dg_batch_set_learned(self._h, int(order), _ptr(w_bf16), _ptr(master), float(band[0]),
-                                        float(band[1]))
+                                        float(band[1]), _ptr(prob) if prob is not None else None)
         if rc:
             raise DGError(rc, "dg_batch_set_learned")
 

@@ -25,6 +25,10 @@ Workloads (names are what the problem is, with its sizes):
   t = 0.25.
 * ``riemann2d_batch256``  -- 256 such problems, side n uniform in
   [64,512], order uniform in {1,2,3}.
+* ``patchwork2d_2048_q2`` -- 2D Euler on [0,1]^2 from a 127 x 127 patchwork of
+  random constant states in the same ranges (a jump every 16.1 cells, inside
+  cells): a state with many troubled cells from the start, for limiter-heavy
+  parity and timing.
 * ``double_mach_960x240_q2`` -- the paper's Example 11: 2D Euler on
   [0,4]x[0,1], a Mach 10 shock through (1/6, 0) at 60 degrees to the x-axis
   moving right into (rho,u,v,p) = (1.4,0,0,1); behind it (8, 8.25 cos 30deg,
@@ -302,6 +306,27 @@ def riemann2d(n=2048, order=2, seed=12345, t_end=0.25, cfl=None, xc=0.5, yc=0.5)
         return euler2d_conserved(*prim)
     return Workload(f"riemann2d_{n}_q{order}_s{seed}", 2, EULER, order, n, n, 0.0, 1.0, 0.0, 1.0,
                     (TRANSMISSIVE,) * 4, cfl, t_end, ic, seed=seed, extra=dict(states=st, center=(xc, yc)))
+
+
+def patchwork2d(n=2048, order=2, seed=4242, blocks=127, t_end=0.25, cfl=None):
+    """2D Euler on [0,1]^2, transmissive: a blocks x blocks patchwork of
+    constant primitive states, each drawn (numpy PCG64, row by row) from the
+    ranges of the four-state Riemann problem.  Jumps every n/blocks cells in
+    both directions (inside cells unless blocks divides n) give a state with
+    many troubled cells from the start, as a Riemann run has after its waves
+    have spread."""
+    if cfl is None:
+        cfl = 0.05 if order == 3 else 0.1
+    rng = np.random.default_rng(seed)
+    prim = np.stack([rng.uniform(0.1, 1.5, size=(blocks, blocks)), rng.uniform(-1.0, 1.0, size=(blocks, blocks)),
+                     rng.uniform(-1.0, 1.0, size=(blocks, blocks)), rng.uniform(0.03, 1.5, size=(blocks, blocks))])
+
+    def ic(X, Y):
+        bi = np.clip(np.floor(X * blocks).astype(np.int64), 0, blocks - 1)
+        bj = np.clip(np.floor(Y * blocks).astype(np.int64), 0, blocks - 1)
+        return euler2d_conserved(*[prim[k][bj, bi] for k in range(4)])
+    return Workload(f"patchwork2d_{n}_q{order}_b{blocks}_s{seed}", 2, EULER, order, n, n, 0.0, 1.0, 0.0, 1.0,
+                    (TRANSMISSIVE,) * 4, cfl, t_end, ic, seed=seed)
 
 
 def riemann2d_batch(count=256, first_seed=10000, nmin=64, nmax=512, t_end=0.25):

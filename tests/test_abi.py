@@ -149,3 +149,28 @@ def test_boundary_and_positivity_validation(dg):
     cf = (dg.Config * 2)(dg.make_config(**dict(e2, bc=(1, 1, 1, 1), positivity=1)),
                          dg.make_config(**dict(e2, bc=(1, 1, 1, 1))))
     assert dg.lib().dg_batch_workspace_bytes(cf, 2, ctypes.byref(n)) == dg.DG_ERR_INVALID_ARG
+
+
+def test_learned_indicator_takes_periodic_and_transmissive_sides_only(dg):
+    """The network's features see ghost cells by periodic wrap or even
+    reflection (the sides it was trained on); walls, inflow and switching
+    sides are rejected on the host."""
+    from paper_1904_11147_amd import workloads as W
+    e2 = dict(dim=2, equation=dg.EULER, order=2, nx=8, ny=8, indicator=dg.IND_LEARNED)
+    assert dg.workspace_bytes(dg.make_config(**dict(e2, bc=(1, 1, 1, 1)))) > 0
+    assert dg.workspace_bytes(dg.make_config(**dict(e2, bc=(0, 0, 1, 1)))) > 0
+    for bc in ((dg.REFLECTIVE, 1, 1, 1), (1, 1, dg.REFLECTIVE, 1)):
+        with pytest.raises(dg.DGError) as e:
+            dg.workspace_bytes(dg.make_config(**dict(e2, bc=bc)))
+        assert e.value.code == dg.DG_ERR_UNSUPPORTED
+    wl = W.double_mach(64)  # inflow and wall sides, a switching north side
+    with pytest.raises(dg.DGError) as e:
+        dg.workspace_bytes(dg.make_config(**dict(wl.config(), indicator=dg.IND_LEARNED)))
+    assert e.value.code == dg.DG_ERR_UNSUPPORTED
+    st = np.zeros((4, 2, 4))
+    st[:, :, 0], st[:, :, 3] = 1.0, 2.5  # an admissible inflow state
+    with pytest.raises(dg.DGError) as e:
+        dg.workspace_bytes(dg.make_config(**dict(e2, bc=(1, 1, 1, dg.INFLOW), bc_state=st)))
+    assert e.value.code == dg.DG_ERR_UNSUPPORTED
+    assert dg.workspace_bytes(dg.make_config(**dict(e2, indicator=dg.IND_TVB, bc=(1, 1, 1, dg.INFLOW),
+                                                    bc_state=st))) > 0

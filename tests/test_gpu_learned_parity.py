@@ -1,0 +1,173 @@
+"""The learned indicator's inference kernels on the step path against the
+FP64 reference network (oracle/mlp_oracle.py) with the trained weights.
+
+* dg_limit with DG_IND_LEARNED (k_indicator_learned): the probability of
+  every cell against forward(features(U)) at the BF16 tolerance of the
+  forward kernel test (1e-2 relative + 1e-3); the flags against the band rule
+  applied to the reference p with the oracle's TVB flags inside the band; the
+  limited state against the oracle limiter with those flags (1e-12).  Cells
+  whose reference p lies within 1e-2 of a band edge where the two sides of
+  the edge decide differently, or whose in-band TVB margin is below 1e-10,
+  are listed and may differ.
+* dg_batch_step (k_batch_learned): one SSP-RK3 step of a mixed Q1/Q2/Q3
+  batch against the oracle's step with the reference network deciding the
+  flags of every limiter pass; the probabilities of the last pass and the
+  final states compared as above, outside a six-cell halo of the listed
+  cells of any pass.
+
+Initial states are the oracle's (projection and TVB limiting)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp_oracle as M
+from tests.dgutil import oracle_initial_state, oracle_problem
+from tests.gpu_common import MARGIN_TOL, REL_TOL, configs, make_pair, rel_err, rough_state
+
+pytestmark = pytest.mark.gpu
+
+P_RTOL, P_ATOL, EDGE = 1e-2, 1e-3, 1e-2
+BAND = (0.2, 0.8)
+
+
+def _net(order):
+    from paper_1904_11147_amd import learned
+    path = os.path.join(os.path.dirname(learned.__file__), "weights", f"indicator_q{order}.npz")
+    net = learned.MLP.load(path)
+    F = 5 * (order + 1) ** 2 * 4
+    P = M.unpack(net.master.cpu().numpy().astype(np.float64), F)  # the fp32 master values the GPU holds
+    return net, P
+
+
+def _reference_decision(op, P, U):
+    """(p, flags, ambiguous) of the band rule on the reference network, with
+    the oracle's TVB decision inside the band."""
+    p = M.forward(P, M.features(U, op.hx, 1.0, op.bc))["p"].reshape(op.ny, op.nx)
+    tvb, margin = op.indicator(U)
+    lo, hi = BAND
+    flags = np.where(p > hi, 1, np.where(p < lo, 0, tvb)).astype(np.uint8)
+    # a cell near an edge is ambiguous only where the two sides decide differently
+    amb = ((np.abs(p - hi) < EDGE) & (tvb == 0)) | ((np.abs(p - lo) < EDGE) & (tvb == 1))
+    amb |= (p >= lo) & (p <= hi) & (margin < MARGIN_TOL)
+    return p, flags, amb
+
+
+CASES = [(order, bc, kind) for order in (1, 2, 3) for bc in ((1, 1, 1, 1), (0, 0, 0, 0))
+         for kind in ("rough", "riemann")]
+
+
+@pytest.mark.parametrize("order,bc,kind", CASES)
+def test_learned_limit_matches_reference_network(oracle, order, bc, kind):
+    from paper_1904_11147_amd import dg, learned
+    from paper_1904_11147_amd import workloads as W
+    nx, ny = 75, 37  # ragged: 5 strips of 14 plus 5 columns, 2 chunks of 16 rows plus 5
+    cfg = configs(2, 1, order, nx, ny, bc)
+    op, _ = make_pair(oracle, dg, cfg)
+    if kind == "rough":
+        U = rough_state(oracle, op, seed=100 + 10 * order + bc[0])
+    else:  # the four-state Riemann data of the benchmark family, with its discontinuities
+        wl = W.riemann2d(n=nx, order=order, seed=700 + order).with_(ny=ny, bc=bc)
+        _, U = oracle_initial_state(oracle, wl, prob=op, limit=True)
+    net, P = _net(order)
+    gp = dg.Problem(indicator=dg.IND_LEARNED, **cfg)
+    probs = torch.full((ny * nx,), -1.0, device="cuda")
+    learned.attach(gp, net, BAND, probs)
+    Ud = torch.from_numpy(U.copy()).cuda()
+    flags, _, n = gp.limit(Ud)
+    p_gpu = probs.cpu().numpy().reshape(ny, nx)
+    f_gpu = flags.cpu().numpy()
+    p_ref, f_ref, amb = _reference_decision(op, P, U)
+    dp = np.abs(p_gpu - p_ref)
+    assert (dp <= P_RTOL * p_ref + P_ATOL).all(), (float(dp.max()), np.unravel_index(np.argmax(dp), dp.shape))
+    diff = np.argwhere(f_gpu != f_ref)
+    listed = [tuple(c) for c in np.argwhere(amb)]
+    print(f"order {order} bc {bc} {kind}: max |dp| {dp.max():.2e}, troubled {int(f_ref.sum())}/{f_ref.size}, "
+          f"differing flags {[tuple(c) for c in diff]}, listed near-edge cells {listed}")
+    assert all(amb[tuple(c)] for c in diff), diff
+    assert n == int(f_gpu.sum())
+    # the limited state: the oracle limiter with the reference decisions
+    ref, _, _ = op.limit(U, flags=f_ref)
+    got = Ud.cpu().numpy()
+    keep = (f_gpu == f_ref)
+    for v in range(ref.shape[0]):
+        d = np.abs(got[v] - ref[v])[:, keep].max()
+        assert d <= REL_TOL * max(1.0, np.abs(ref[v]).max()), (v, d)
+    gp.close()
+
+
+def _oracle_learned_step(op, P, U0, dt):
+    """SSP-RK3 step (Sec. 3, last paragraph) with the reference network
+    deciding each limiter pass.  Returns the new state, the pre-limit state
+    and the reference p of the last pass, and the union of ambiguous cells."""
+    amb_all = np.zeros((op.ny, op.nx), dtype=bool)
+
+    def lim(U):
+        p, f, amb = _reference_decision(op, P, U)
+        amb_all[...] |= amb
+        out, _, _ = op.limit(U, flags=f)
+        return out, p
+
+    u1, _ = lim(U0 + dt * op.residual(U0))
+    u2, _ = lim(0.75 * U0 + 0.25 * (u1 + dt * op.residual(u1)))
+    pre = U0 / 3.0 + 2.0 / 3.0 * (u2 + dt * op.residual(u2))
+    u3, p3 = lim(pre)
+    return u3, p3, amb_all
+
+
+def _halo(mask, r, periodic):
+    out = mask.copy()
+    for _ in range(r):
+        m = out.copy()
+        for ax in (0, 1):
+            for s in (-1, 1):
+                sh = np.roll(out, s, axis=ax)
+                if not periodic:  # no wrap on transmissive sides
+                    if ax == 0:
+                        sh[0 if s == 1 else -1, :] = False
+                    else:
+                        sh[:, 0 if s == 1 else -1] = False
+                m |= sh
+        out = m
+    return out
+
+
+def test_batch_learned_matches_reference_network(oracle):
+    from paper_1904_11147_amd import dg
+    from paper_1904_11147_amd import workloads as W
+    wls = [W.riemann2d(n=47, order=1, seed=811).with_(ny=35),
+           W.riemann2d(n=61, order=2, seed=812).with_(ny=40),
+           W.riemann2d(n=30, order=3, seed=813).with_(ny=29)]
+    b = dg.batch_from_workloads(wls, indicator=dg.IND_LEARNED, limit=False)
+    ops, U0s = [], []
+    for i, wl in enumerate(wls):
+        op, U0 = oracle_initial_state(oracle, wl, limit=True)
+        b.view(i).copy_(torch.from_numpy(U0))
+        ops.append(op)
+        U0s.append(U0)
+    prob = torch.full((b.states.numel(),), -1.0, dtype=torch.float32, device="cuda")
+    nets = {}
+    for wl in wls:
+        nets[wl.order] = _net(wl.order)
+        b.set_learned(wl.order, nets[wl.order][0].w, nets[wl.order][0].master, BAND, prob)
+    t, steps, status, _ = b.step(0.0, [wl.t_end for wl in wls], max_steps=1)
+    assert (steps == 1).all() and (status == 0).all()
+    pc = prob.cpu().numpy()
+    for i, wl in enumerate(wls):
+        op = ops[i]
+        dt = op.cfl_dt(U0s[i])
+        assert abs(t[i] - dt) <= 1e-13 * dt, (i, t[i], dt)
+        ref, p_ref, amb = _oracle_learned_step(op, nets[wl.order][1], U0s[i], dt)
+        cells = op.nx * op.ny
+        p_gpu = pc[int(b.offsets[i]): int(b.offsets[i]) + cells].reshape(op.ny, op.nx)
+        keep = ~_halo(amb, 6, periodic=False)
+        print(f"instance {i} ({wl.name}, {op.nx}x{op.ny}): listed near-edge cells {[tuple(c) for c in np.argwhere(amb)]}"
+              f", compared {int(keep.sum())}/{cells}")
+        assert keep.mean() >= 0.8
+        dp = np.abs(p_gpu - p_ref)[keep]
+        assert (dp <= P_RTOL * p_ref[keep] + P_ATOL).all(), float(dp.max())
+        got = b.view(i).cpu().numpy()
+        for v in range(4):
+            d = np.abs(got[v] - ref[v])[:, keep].max()
+            assert d <= REL_TOL * max(1.0, np.abs(ref[v]).max()), (i, v, d)
