@@ -204,6 +204,25 @@ int dg_cfl_dt(dg_problem *p, const double *state, double *dt);
 int dg_step(dg_problem *p, double *state, double *t, double t_end, double dt, int32_t max_steps,
             int32_t *steps_taken);
 
+/* dg_limit for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): no
+ * problem handle and no workspace.  The configuration is passed directly
+ * (validated as by dg_workspace_bytes; uniform meshes, any indicator but
+ * DG_IND_LEARNED), t is the time of time-dependent boundary data, stream a
+ * hipStream_t (NULL = null stream); state, flags, margin, flags_override and
+ * n_troubled mean what they mean for dg_limit.  The limiter's scratch (scalar
+ * words, troubled-cell list, Jacobi side buffer) lives in a static device
+ * array of 64 MiB that each device holds from the first call until the
+ * process ends: a problem needs 256 + 4 cells (rounded up to 256 bytes) +
+ * the state's bytes, e.g. up to 229,000 cells of 2D Euler Q2; larger ones
+ * return DG_ERR_WORKSPACE.  The call allocates nothing, enqueues its work on
+ * stream and returns after the stream has finished it.  Every call on a
+ * device shares that device's array: calls that overlap on one device
+ * (several host threads or streams) race and must be serialised by the
+ * caller. */
+int dg_limit_noalloc(const dg_config *cfg, double *state, uint8_t *flags, double *margin,
+                     const uint8_t *flags_override, double t, int32_t *n_troubled, void *stream);
+
 /* Time at which dg_residual and dg_limit evaluate time-dependent boundary
  * data (switching sides).  Enqueued on the problem's stream. */
 int dg_set_time(dg_problem *p, double t);

@@ -510,6 +510,38 @@ int dg_limit(dg_problem *p, double *state, uint8_t *flags, double *margin, const
   return rc;
 }
 
+int dg_limit_noalloc(const dg_config *cfg, double *state, uint8_t *flags, double *margin,
+                     const uint8_t *flags_override, double t, int32_t *n_troubled, void *stream) {
+  if (!state || !std::isfinite(t)) return DG_ERR_INVALID_ARG;
+  int rc = dg::validate_config(cfg);
+  if (rc) return rc;
+  if (cfg->indicator == DG_IND_LEARNED || cfg->x_nodes || cfg->y_nodes) return DG_ERR_UNSUPPORTED;
+  const size_t cells = (size_t)cfg->nx * cfg->ny;
+  const size_t side_off = dg::kStaticListOffset + align_up(cells * sizeof(int32_t));
+  const size_t state_bytes = cells * dg::num_vars(cfg) * dg::num_modes(cfg) * sizeof(double);
+  if (side_off + state_bytes > dg::kStaticScratchBytes) return DG_ERR_WORKSPACE;
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return DG_ERR_HIP;
+  if ((rc = dg::ensure_tables(device))) return rc;
+  void *scratch = nullptr;
+  if ((rc = dg::static_scratch(device, &scratch))) return rc;
+  char *base = (char *)scratch;
+  LaunchCtx c;
+  fill_ctx(cfg, stream, (DevScalars *)base, &c);
+  c.list = (int32_t *)(base + dg::kStaticListOffset);
+  c.bufA = (double *)(base + side_off);
+  if ((rc = dg::launch_scratch_init(c, t))) return rc;
+  rc = dg::launch_limit(c, state, c.bufA, 3, flags, margin, flags_override);
+  if (!rc && cfg->positivity) rc = dg::launch_positivity(c, state, 0);
+  if (rc) return rc;
+  DevScalars h;
+  if (hipMemcpyAsync(&h, c.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess ||
+      hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+    return DG_ERR_HIP;
+  if (n_troubled) *n_troubled = h.count[3];
+  return h.status ? DG_ERR_NONPHYSICAL : DG_OK;
+}
+
 int dg_set_time(dg_problem *p, double t) {
   if (!p || !std::isfinite(t)) return DG_ERR_INVALID_ARG;
   return dg::launch_set_tb(p->ctx, -1.0, t);

@@ -206,6 +206,13 @@ int launch_stage_order2(const LaunchCtx &c, int stage, const double *u, const do
 int launch_stage_order3(const LaunchCtx &c, int stage, const double *u, const double *un, double *out, bool want_speed);
 int launch_limit(const LaunchCtx &c, double *u, double *side, int count_slot, uint8_t *flags, double *margin,
                  const uint8_t *flags_override);
+// Allocation-free limiter call: the device address of this device's static
+// scratch array (kStaticScratchBytes; looked up once per device), and a
+// kernel that clears its count and status words and sets the boundary time.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr size_t kStaticListOffset = 256;
+int static_scratch(int device, void **ptr);
+int launch_scratch_init(const LaunchCtx &c, double tb);
 int launch_speed(const LaunchCtx &c, const double *u);
 int launch_dt_finalize(const LaunchCtx &c);
 // Positivity scaling of every cell of u (Euler); check_done: skip once the

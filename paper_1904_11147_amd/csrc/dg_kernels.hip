@@ -25,6 +25,7 @@
 #include <algorithm>
 
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "dg_internal.h"
@@ -39,6 +40,13 @@
 #endif
 #define DG_CAT2(a, b) a##b
 #define DG_CAT(a, b) DG_CAT2(a, b)
+
+#if DG_PART == 1
+// Scratch of dg_limit_noalloc (each device holds its own copy until the
+// process ends).  Host code never passes this name to a kernel: it takes the
+// device address from hipGetSymbolAddress (static_scratch below).
+static __device__ __align__(256) unsigned char scratch[dg::kStaticScratchBytes];
+#endif
 
 namespace dg {
 
@@ -2368,6 +2376,39 @@ int launch_residual(const LaunchCtx &c, const double *u, double *out) {
 #endif  // DG_PART == 0
 
 #if DG_PART == 1
+// Allocation-free limiter call (dg_limit_noalloc): scratch in a file-scope
+// device array instead of a caller workspace.  Layout: DevScalars at 0, the
+// troubled list at kStaticListOffset, the side buffer after it.
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64];
+
+__global__ void k_scratch_init(DevScalars *sc, double tb) {
+  if (threadIdx.x != 0) return;
+  sc->count[3] = 0;
+  sc->status = 0;
+  sc->done = 0;
+  sc->tb = tb;
+}
+}  // namespace
+
+int static_scratch(int device, void **ptr) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= 64 || !ptr) return DG_ERR_HIP;
+  if (!g_scratch_ptr[device]) {
+    void *q = nullptr;
+    if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return DG_ERR_HIP;
+    g_scratch_ptr[device] = q;
+  }
+  *ptr = g_scratch_ptr[device];
+  return DG_OK;
+}
+
+int launch_scratch_init(const LaunchCtx &c, double tb) {
+  hipLaunchKernelGGL(k_scratch_init, dim3(1), dim3(64), 0, S(c), c.sc, tb);
+  return check_launch();
+}
+
 int launch_limit(const LaunchCtx &c, double *u, double *side, int count_slot, uint8_t *flags, double *margin,
                  const uint8_t *flags_override) {
   LimitArgs a;

@@ -31,7 +31,7 @@ EXPORTS = ("dg_workspace_bytes", "dg_init", "dg_destroy", "dg_proj_nodes", "dg_p
            "dg_limit", "dg_cfl_dt", "dg_step", "dg_status", "dg_strerror", "dg_profile_enable", "dg_profile_read",
            "dg_autotune", "dg_mlp_layout", "dg_mlp_features", "dg_mlp_forward", "dg_mlp_gradient", "dg_mlp_adam", "dg_set_learned",
            "dg_batch_workspace_bytes", "dg_batch_init", "dg_batch_destroy", "dg_batch_autotune", "dg_batch_set_tiles",
-           "dg_batch_step", "dg_batch_set_learned", "dg_set_time")
+           "dg_batch_step", "dg_batch_set_learned", "dg_set_time", "dg_limit_noalloc")
 PROF_KINDS = ("stage1", "stage23", "limiter", "dt")
 
 
@@ -115,6 +115,7 @@ def lib():
             "dg_batch_step": [vp, vp, P(ctypes.c_int64), P(d), P(d), i32, P(i32), P(i32), P(ctypes.c_int64)],
             "dg_batch_set_learned": [vp, i32, vp, vp, d, d, vp],
             "dg_set_time": [vp, d],
+            "dg_limit_noalloc": [P(Config), vp, vp, vp, vp, d, P(i32), vp],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -165,6 +166,20 @@ def make_config(dim=1, equation=BURGERS, order=2, nx=16, ny=1, x0=0.0, x1=1.0, y
         setattr(c, name, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     c._keep = keep
     return c
+
+
+def limit_noalloc(state, t=0.0, flags=None, margin=None, flags_override=None, stream=None, **cfg):
+    """dg_limit_noalloc: the limiter on `state` (in place) for the
+    configuration `cfg` with the library's static scratch; flags / margin are
+    optional output tensors.  Returns (status code, n_troubled)."""
+    c = make_config(**cfg)
+    st = stream if stream is not None else torch.cuda.current_stream(state.device)
+    n = ctypes.c_int32()
+    rc = lib().dg_limit_noalloc(ctypes.byref(c), _ptr(state), _ptr(flags), _ptr(margin), _ptr(flags_override),
+                                float(t), ctypes.byref(n), ctypes.c_void_p(st.cuda_stream))
+    if rc not in (DG_OK, DG_ERR_NONPHYSICAL):
+        raise DGError(rc, "dg_limit_noalloc")
+    return rc, n.value
 
 
 def workspace_bytes(cfg: Config) -> int:
