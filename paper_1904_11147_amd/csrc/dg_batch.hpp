@@ -267,12 +267,12 @@ template <int N, int SLOT>
 __global__ __launch_bounds__(kBlock) void k_batch_csweno(const BatchInst *__restrict__ inst,
                                                          const BatchQueue *__restrict__ q,
                                                          const long long *__restrict__ list) {
-  const long total = (long)q->count[SLOT] * 4;
+  const long count = q->count[SLOT], total = count * 4;
   for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-    const long long e = list[t / 4];
+    const long long e = list[t % count];  // one variable of consecutive entries per wavefront
     const BatchInst &I = inst[(int)(e >> 32)];
     csweno_cell<N, 1, 2, false>(limit_target<SLOT>(I), limit_side<SLOT>(I), I.geo, (long)(e & 0xffffffffll),
-                                (int)(t % 4));
+                                (int)(t / count));
   }
 }
 
@@ -293,11 +293,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_scatter(const BatchInst *__res
                                                           const BatchQueue *__restrict__ q,
                                                           const long long *__restrict__ list) {
   constexpr int NM = (N + 1) * (N + 1), NV = 4;
-  const long total = (long)q->count[SLOT] * NV * (NM - 1);
+  const long count = q->count[SLOT], total = count * NV * (NM - 1);
   for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-    const int m = 1 + (int)(t % (NM - 1));
-    const int v = (int)((t / (NM - 1)) % NV);
-    const long long e = list[t / ((NM - 1) * NV)];
+    const long r = t / count;  // consecutive threads: consecutive entries of one plane
+    const int m = 1 + (int)(r % (NM - 1));
+    const int v = (int)(r / (NM - 1));
+    const long long e = list[t % count];
     const BatchInst &I = inst[(int)(e >> 32)];
     const long plane = (long)I.geo.nx * I.geo.ny;
     const long k = (long)(v * NM + m) * plane + (long)(e & 0xffffffffll);

@@ -1780,7 +1780,10 @@ __global__ __launch_bounds__(kBlock) void k_indicator(LimitArgs a) {
 // WENO values at the Step-1 points of one row of 2N+1 stencil means.  The
 // row is taken relative to the troubled cell's mean a[N] (the smoothness
 // indicators only see derivatives and the normalised weights sum to one), so
-// the quadratic forms do not cancel O(1) means.
+// the quadratic forms do not cancel O(1) means.  The normalised weights
+// (gamma_i / (eps + beta_i)^2) / sum_k (...) equal gamma_i d_i / sum_k gamma_k d_k
+// with d_i = prod_{k != i} (eps + beta_k)^2 (numerator and denominator times
+// the product of all (eps + beta_k)^2), which leaves one reciprocal per point.
 template <int N, typename Tab>
 __device__ inline void weno_row(const Tab &T, const double *a_in, double *out, double eps, bool raw) {
   constexpr int NP = N + 1, NG = num_points<N>(), NS = 2 * N + 1;
@@ -1788,7 +1791,7 @@ __device__ inline void weno_row(const Tab &T, const double *a_in, double *out, d
   double a[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) a[k] = a_in[k] - a0;
-  double d[NP];
+  double e2[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
     double beta = 0.0;
@@ -1799,8 +1802,20 @@ __device__ inline void weno_row(const Tab &T, const double *a_in, double *out, d
       for (int l = 0; l < NP; ++l) s += T.B[i][k][l] * a[i + l];
       beta += a[i + k] * s;
     }
-    double e = eps + beta;
-    d[i] = 1.0 / (e * e);
+    const double e = eps + beta;
+    e2[i] = e * e;
+  }
+  double d[NP];  // products of the other stencils' (eps + beta)^2
+  {
+    double pre[NP], suf[NP];
+    pre[0] = 1.0;
+#pragma unroll
+    for (int i = 1; i < NP; ++i) pre[i] = pre[i - 1] * e2[i - 1];
+    suf[NP - 1] = 1.0;
+#pragma unroll
+    for (int i = NP - 2; i >= 0; --i) suf[i] = suf[i + 1] * e2[i + 1];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) d[i] = pre[i] * suf[i];
   }
 #pragma unroll
   for (int G = 0; G < NG; ++G) {
@@ -1822,7 +1837,7 @@ __device__ inline void weno_row(const Tab &T, const double *a_in, double *out, d
         wm += y;
         um += y * p[i];
       }
-      out[G] = a0 + (T.sp[G] * (up / wp) - T.sm[G] * (um / wm));
+      out[G] = a0 + (T.sp[G] * (up * fast_rcp(wp)) - T.sm[G] * (um * fast_rcp(wm)));
     } else {
       double ws = 0.0, us = 0.0;
 #pragma unroll
@@ -1831,7 +1846,7 @@ __device__ inline void weno_row(const Tab &T, const double *a_in, double *out, d
         ws += x;
         us += x * p[i];
       }
-      out[G] = a0 + us / ws;
+      out[G] = a0 + us * fast_rcp(ws);
     }
   }
 }
@@ -1952,13 +1967,16 @@ __device__ inline void csweno_cell(const double *__restrict__ u, double *__restr
   }
 }
 
+// Thread t takes variable t / count of list entry t % count: a wavefront works
+// on one variable of consecutive entries (neighbouring cells).
 template <int N, int EQ, int DIM, bool BND>
 __global__ __launch_bounds__(kBlock) void k_csweno(LimitArgs a) {
   constexpr int NV = Phys<EQ, DIM>::NV;
   if (a.check_done && a.sc->done) return;
-  const long total = (long)(*a.count) * NV;
+  const long count = *a.count;
+  const long total = count * NV;
   for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x)
-    csweno_cell<N, EQ, DIM, BND>(a.u, a.side, a.geo, a.list[t / NV], (int)(t % NV));
+    csweno_cell<N, EQ, DIM, BND>(a.u, a.side, a.geo, a.list[t % count], (int)(t / count));
 }
 
 // ---------------------------------------------------------------------------
@@ -2195,16 +2213,19 @@ __global__ __launch_bounds__(kBlock) void k_csweno_char(LimitArgs a) {
     csweno_char_cell<N, DIM, BND>(a.u, a.side, a.geo, a.list[t]);
 }
 
+// Consecutive threads take consecutive list entries of one (variable, mode)
+// plane, so a wavefront's accesses fall on the few cache lines that
+// neighbouring troubled cells share.
 template <int NM, int NV>
 __global__ __launch_bounds__(kBlock) void k_scatter(LimitArgs a, double *dst) {
   if (a.check_done && a.sc->done) return;
   const long plane = (long)a.geo.nx * a.geo.ny;
-  const long total = (long)(*a.count) * NV * (NM - 1);
+  const long count = *a.count;
+  const long total = count * NV * (NM - 1);
   for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-    const int q = 1 + (int)(t % (NM - 1));
-    const int v = (int)((t / (NM - 1)) % NV);
-    const long cell = a.list[t / ((NM - 1) * NV)];
-    const long k = (long)(v * NM + q) * plane + cell;
+    const long e = t % count, r = t / count;  // r = v (NM - 1) + q - 1
+    const int q = 1 + (int)(r % (NM - 1)), v = (int)(r / (NM - 1));
+    const long k = (long)(v * NM + q) * plane + a.list[e];
     dst[k] = a.side[k];
   }
 }

@@ -28,3 +28,24 @@ def test_traffic_only_for_the_current_kernel_source(tmp_path, monkeypatch):
     assert bench.traffic_for(1.0) == 123.0
     f.write_text(json.dumps({"kernel_source_sha256_16": "0" * 16, "hbm_bytes_per_launch": 123.0}))
     assert bench.traffic_for(1.0) is None  # stale: the kernels changed since
+
+
+def test_fp64_figure_only_for_the_current_kernel_source(tmp_path, monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1904_11147_amd.profiling import kernel_source_hash
+    f = tmp_path / "fp64.json"
+    monkeypatch.setattr(bench, "FP64_FILE", str(f))
+    assert bench.fp64_per_launch() is None
+    f.write_text(json.dumps({"kernel_source_sha256_16": kernel_source_hash(), "fp64_flops_per_launch": 7.0}))
+    assert bench.fp64_per_launch() == 7.0
+    f.write_text(json.dumps({"kernel_source_sha256_16": "1" * 16, "fp64_flops_per_launch": 7.0}))
+    assert bench.fp64_per_launch() is None
+
+
+def test_host_info_names_the_cpu():
+    sys.path.insert(0, ROOT)
+    import bench
+    h = bench.host_info()
+    assert h["host_cpus_usable"] >= 1 and h["host_cpus_total"] >= h["host_cpus_usable"]
+    assert h["cpu_model"]
