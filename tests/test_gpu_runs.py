@@ -79,3 +79,14 @@ def test_riemann2d_q1_q3(oracle):
     from paper_1904_11147_amd import workloads as W
     _run_both(oracle, W.riemann2d(n=40, order=1, seed=3, t_end=0.05))
     _run_both(oracle, W.riemann2d(n=24, order=3, seed=3, t_end=0.003))
+
+
+def test_shu_osher_k4000_p3_with_positivity(oracle):
+    """The full 1D Euler shock/entropy-wave workload (4000 cells, P3) past
+    step 22, where its componentwise P3 solution loses positivity without the
+    scaling (in the oracle as on the GPU), to t = 0.005 (about 190 steps)
+    with the positivity-preserving scaling, componentwise and characteristic."""
+    from paper_1904_11147_amd import workloads as W
+    wl = W.shu_osher().with_(t_end=0.005)
+    _run_both(oracle, wl, positivity=1)
+    _run_both(oracle, wl, positivity=1, limiter=2)
