@@ -1745,6 +1745,31 @@ __device__ inline void append_troubled(const LimitArgs &a, bool flag, long cell)
   }
 }
 
+// The same for a whole block (every thread of the block calls it): one atomic
+// per block instead of one per wavefront, since every wavefront that flags a
+// cell would otherwise contend for the same counter.
+__device__ inline void append_troubled_block(const LimitArgs &a, bool flag, long cell) {
+  __shared__ int s_cnt[kBlock / 64];
+  __shared__ int s_base;
+  const unsigned long long ballot = __ballot(flag);
+  const int lane = __lane_id();
+  const int wave = (threadIdx.x + threadIdx.y * blockDim.x) >> 6, waves = (blockDim.x * blockDim.y) >> 6;
+  if (lane == 0) s_cnt[wave] = __popcll(ballot);
+  __syncthreads();
+  if (wave == 0 && lane == 0) {
+    int total = 0;
+    for (int w = 0; w < waves; ++w) total += s_cnt[w];
+    s_base = total ? atomicAdd(a.count, total) : 0;
+    if (total) atomicAdd(&a.sc->troubled_total, (unsigned long long)total);
+  }
+  __syncthreads();
+  if (flag) {
+    int base = s_base;
+    for (int w = 0; w < wave; ++w) base += s_cnt[w];
+    a.list[base + __popcll(ballot & ((1ull << lane) - 1ull))] = (int32_t)cell;
+  }
+}
+
 // KX: the KXRCF indicator (an instantiation of its own, so that the TVB one
 // keeps only one variable's modes live)
 template <int N, int EQ, int DIM, bool BND, bool KX>
@@ -1770,7 +1795,7 @@ __global__ __launch_bounds__(kBlock) void k_indicator(LimitArgs a) {
     if (a.flags) a.flags[cell] = flag ? 1 : 0;
     if (a.margin) a.margin[cell] = mg;
   }
-  append_troubled(a, flag, cell);
+  append_troubled_block(a, flag, cell);
 }
 
 // ---------------------------------------------------------------------------

@@ -4,6 +4,8 @@
     python -m paper_1904_11147_amd.profiling traffic --fetch <csv> --write <csv> --kernel <regex>
             --copy-kernel <regex> --copy-bytes <B> --cmd "<command>" --out <traffic.json>
     python -m paper_1904_11147_amd.profiling counters <counter_collection.csv> --cmd "<command>" --out <summary.txt>
+    python -m paper_1904_11147_amd.profiling fp64 <counter_collection.csv> --kernel <regex> --cmd "<command>"
+            --out <fp64.json>
 
 `stats` shortens the kernel names of a `--kernel-trace --stats` CSV and keeps
 calls, total, average, min and max duration.  `traffic` turns two `--pmc`
@@ -11,7 +13,11 @@ runs (FETCH_SIZE, then WRITE_SIZE, both in KiB per dispatch) into HBM bytes
 per launch of one kernel, each counter scaled by what it reads for a plain
 copy kernel that moves a known number of bytes (read once, written once).
 The result records the hash of the kernel source it was taken on, so that a
-reader can tell when the kernel has changed since.
+reader can tell when the kernel has changed since.  `fp64` turns a `--pmc`
+run of SQ_INSTS_VALU_ADD_F64, _MUL_F64, _FMA_F64 and _TRANS_F64 (wavefront
+instructions per dispatch) into FP64 flops per launch of one kernel: 64
+lanes per instruction, two flops per FMA (inactive lanes count too, so this
+is an upper bound on the useful flops).
 """
 import argparse
 import csv
@@ -126,6 +132,19 @@ def counters(path, cmd, out):
     print("\n".join(lines))
 
 
+def fp64(path, kernel, cmd, out):
+    names = ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_TRANS_F64")
+    per = {c: _pick(_per_dispatch(path, c), kernel) for c in names}
+    hits = per[names[0]][0]
+    mean = {c: statistics.mean(v[1]) for c, v in per.items()}
+    flops = 64.0 * (mean[names[0]] + mean[names[1]] + mean[names[3]]) + 128.0 * mean[names[2]]
+    res = {"kernel": short_name(hits[0]), "kernel_source_sha256_16": kernel_source_hash(),
+           "dispatches": len(per[names[0]][1]), "wave_instructions_per_launch": mean,
+           "fp64_flops_per_launch": flops, "command": cmd}
+    json.dump(res, open(out, "w"), indent=1)
+    print(json.dumps(res, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -145,8 +164,15 @@ def main():
     c.add_argument("csv")
     c.add_argument("--cmd", required=True)
     c.add_argument("--out", required=True)
+    f = sub.add_parser("fp64")
+    f.add_argument("csv")
+    f.add_argument("--kernel", required=True, help="regular expression on the kernel name")
+    f.add_argument("--cmd", required=True)
+    f.add_argument("--out", required=True)
     a = ap.parse_args()
-    if a.what == "stats":
+    if a.what == "fp64":
+        fp64(a.csv, a.kernel, a.cmd, a.out)
+    elif a.what == "stats":
         stats(a.csv, a.cmd, a.out)
     elif a.what == "counters":
         counters(a.csv, a.cmd, a.out)

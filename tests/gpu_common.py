@@ -73,9 +73,13 @@ def assert_close(got, ref, tol=REL_TOL, what=""):
     return e
 
 
-def flags_agree(gpu_flags, ref_flags, ref_margin, tol=MARGIN_TOL):
+def flags_agree(gpu_flags, ref_flags, ref_margin, tol=MARGIN_TOL, what=""):
     """Cells whose flags differ, and whether every one of them is near the
-    threshold by the oracle's margin."""
+    threshold by the oracle's margin.  Differing cells are listed (printed
+    with their margins), as the parity bar asks."""
     diff = np.argwhere(np.asarray(gpu_flags) != np.asarray(ref_flags))
     near = [tuple(c) for c in diff if ref_margin[tuple(c)] < tol]
+    if len(diff):
+        cells = [(tuple(int(x) for x in c), float(ref_margin[tuple(c)])) for c in diff]
+        print(f"flags differ {what}: {len(diff)} cell(s) (index, oracle margin): {cells}")
     return diff, len(near) == len(diff)
