@@ -522,10 +522,19 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
       }
     }
   };
+  // largest |mode| but the mean of a cell's variable (per row, so that the
+  // features' scale takes 5 of these instead of all 45 entries)
+  auto hi_modes = [&](const double (&R)[NM]) {
+    double m = 0.0;
+#pragma unroll
+    for (int q = 1; q < NM; ++q) m = fmax(m, fabs(R[q]));
+    return m;
+  };
   double Sv[NM], Cv[NM], Nv[NM];
   loadrow(j0 - 1, Sv);
   loadrow(j0, Cv);
   loadrow(j0 + 1, Nv);
+  double hS = hi_modes(Sv), hC = hi_modes(Cv), hN = hi_modes(Nv);
   uint16_t *fl = feat + lane * 4;  // feature f at fl[(f / 4) * 256 + f % 4]
 #pragma unroll
   for (int f = FV; f < BV; ++f) fl[(f / 4) * 256 + f % 4] = 0;
@@ -561,15 +570,19 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
       if constexpr (keep_we) return Ev[q];
       else return row_shift1<false>(Cv[q]);
     };
-    // TVB decision of this variable (the expressions of tvb_cell), combined over the cell's lanes
-    bool tflag = false;
-    double tmg = INFINITY;
-    {
+    // TVB decision of this variable (the expressions of tvb_cell), combined
+    // over the cell's lanes; only needed for a probability inside the band
+    auto tvb_decision = [&](bool &tflag, double &tmg) {
+      tflag = false;
+      tmg = INFINITY;
       const double mean = Cv[0] * k0;
 #pragma unroll
       for (int dir = 0; dir < 2; ++dir) {
         const double Mh2 = dir == 0 ? g.tvb_Mx : g.tvb_My;
-        const double mp = (dir == 0 ? east(0) : Nv[0]) * k0, mm = (dir == 0 ? west(0) : Sv[0]) * k0;
+        // the x-neighbours' means by a fresh shift (the stored west/east rows
+        // are dead by now)
+        const double mp = (dir == 0 ? row_shift1<false>(Cv[0]) : Nv[0]) * k0;
+        const double mm = (dir == 0 ? row_shift1<true>(Cv[0]) : Sv[0]) * k0;
         double upv = 0.0, umv = 0.0;
 #pragma unroll
         for (int q = 0; q < NM; ++q) {
@@ -589,18 +602,21 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
       tflag = fi != 0;
       tmg = fmin(tmg, __shfl_xor(tmg, 16));
       tmg = fmin(tmg, __shfl_xor(tmg, 32));
-    }
+    };
     // features: C, W, E, S, N of variable gv; mode 0 relative to the centre's; scaled
     {
       const double c0 = Cv[0];
-      double mx = g.tvb_Mx;
       auto val = [&](int f) -> double {
         const int c = f / NM, q = f % NM;
         const double v = c == 0 ? Cv[q] : (c == 1 ? west(q) : (c == 2 ? east(q) : (c == 3 ? Sv[q] : Nv[q])));
         return q == 0 ? v - c0 : v;
       };
-#pragma unroll
-      for (int f = 0; f < FV; ++f) mx = fmax(mx, fabs(val(f)));
+      // the largest |entry|: the five cells' non-mean maxima and the four
+      // shifted means (the centre's is 0), with M h^2 as the floor
+      double mx = fmax(g.tvb_Mx, fmax(hC, fmax(hS, hN)));
+      mx = fmax(mx, fmax(row_shift1<true>(hC), row_shift1<false>(hC)));
+      mx = fmax(mx, fmax(fabs(west(0) - c0), fabs(east(0) - c0)));
+      mx = fmax(mx, fmax(fabs(Sv[0] - c0), fabs(Nv[0] - c0)));
       const double inv = 1.0 / mx;
 #pragma unroll
       for (int f = 0; f < FV; ++f) fl[(f / 4) * 256 + f % 4] = f2bf_hw((float)(val(f) * inv));
@@ -644,11 +660,17 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
     const float p = 1.f / (1.f + __expf(-(part + par[3 * kHidden])));
     bool flag = false;
     double mg = INFINITY;
-    if (p > L.band_hi) flag = true;
-    else if (!(p < L.band_lo)) {
-      flag = tflag;
-      mg = tmg;
+    const bool in_band = !(p > L.band_hi) && !(p < L.band_lo);
+    if (__any(in_band)) {  // the whole wavefront takes part (shuffles inside)
+      bool tflag;
+      double tmg;
+      tvb_decision(tflag, tmg);
+      if (in_band) {
+        flag = tflag;
+        mg = tmg;
+      }
     }
+    if (p > L.band_hi) flag = true;
     emit(owner && gv == 0, flag, mg, p, (long)j * g.nx + col);
 #pragma unroll
     for (int q = 0; q < NM; ++q) {
@@ -656,6 +678,9 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
       Cv[q] = Nv[q];
       Nv[q] = Pv[q];
     }
+    hS = hC;
+    hC = hN;
+    hN = hi_modes(Nv);
   }
 }
 
