@@ -194,22 +194,29 @@ def timed_steps(prob, state, t, t_end, steps, profile):
     return t, n, el, prof, troubled
 
 
-def late_window_leg(prob, wl, state, t, t_late, steps):
+def late_window_leg(prob, wl, state, t, t_late, steps, net=None):
     """The same C4 run advanced (untimed) to t_late, then `steps` steps timed
     by graph replay and once more with kernel events: the late-time cost,
-    when the waves have spread and more cells are troubled."""
+    when the waves have spread and more cells are troubled; and the same
+    steps from the same late state with the learned indicator."""
     import torch
+    from paper_1904_11147_amd import dg
     torch.cuda.synchronize()
     a = time.perf_counter()
     t, n_adv = prob.step(state, t, t_late)
     torch.cuda.synchronize()
     adv_s = time.perf_counter() - a
+    late = state.clone()
     t1, n, el, _, troubled = timed_steps(prob, state, t, wl.t_end, steps, profile=False)
     t2, n2, el2, prof, troubled2 = timed_steps(prob, state, t1, wl.t_end, steps, profile=True)
-    return {"t_start": t, "advance_steps": n_adv, "advance_seconds": adv_s, "steps": n,
-            "value": wl.dofs * n / el, "ms_per_step": 1e3 * el / n,
-            "troubled_fraction": troubled2 / max(1, 3 * wl.cells * n2),
-            "kernels_ms_per_step": {k: v[0] / max(1, n2) for k, v in prof.items()}}
+    out = {"t_start": t, "advance_steps": n_adv, "advance_seconds": adv_s, "steps": n,
+           "value": wl.dofs * n / el, "ms_per_step": 1e3 * el / n,
+           "troubled_fraction": troubled2 / max(1, 3 * wl.cells * n2),
+           "kernels_ms_per_step": {k: v[0] / max(1, n2) for k, v in prof.items()}}
+    if net is not None:
+        out["learned"] = indicator_leg(wl, late, t, steps, 2, dg.IND_LEARNED, net=net)
+    del late
+    return out
 
 
 def burgers2d_leg(steps, warmup, n=1024):
@@ -512,7 +519,7 @@ def main():
     out["characteristic"] = indicator_leg(wl, state_warm, t_warm, args.steps, 2, limiter=dg.LIM_CSWENO_CHAR)
     del state_warm
     if not args.no_late:
-        out["late_window"] = late_window_leg(prob, wl, state, t, args.late_t, args.steps)
+        out["late_window"] = late_window_leg(prob, wl, state, t, args.late_t, args.steps, net=nets.get(2))
     prob.close()
     del state
     torch.cuda.empty_cache()

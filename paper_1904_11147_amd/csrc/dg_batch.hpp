@@ -180,26 +180,16 @@ __device__ inline double *limit_side(const BatchInst &I) {
   return SLOT == 0 ? I.B : I.A;
 }
 
-__device__ inline void append_batch(BatchQueue *q, int slot, long long *list, DevScalars *sc, bool flag,
-                                    long long entry) {
-  const unsigned long long ballot = __ballot(flag);
-  if (!ballot) return;
-  const int lane = __lane_id();
-  const int leader = __ffsll((long long)ballot) - 1;
-  int base = 0;
-  if (lane == leader) {
-    base = atomicAdd(&q->count[slot], __popcll(ballot));
-    atomicAdd(&sc->troubled_total, (unsigned long long)__popcll(ballot));
-  }
-  base = __shfl(base, leader);
-  if (flag) list[base + __popcll(ballot & ((1ull << lane) - 1ull))] = entry;
-}
-
 // Troubled-cell indicator over the queued row segments (one wavefront per
 // segment).  IND: DG_IND_TVB, DG_IND_ALL or DG_IND_KXRCF.
+// The flagged cells of a wavefront's segments are gathered in LDS and
+// appended to the order's list with one atomic per few segments (WaveList).
 template <int N, int SLOT, int IND>
 __global__ __launch_bounds__(64) void k_batch_indicator(const BatchInst *__restrict__ inst, BatchQueue *q,
                                                         long long *__restrict__ list) {
+  __shared__ long long flagged[WaveList<long long>::kCap];
+  WaveList<long long> wl{flagged, 0};
+  auto reserve = [&](int k) { return atomicAdd(&q->count[SLOT], k); };
   const int total = q->total_segs;
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const SegItem s = seg_item(inst, q, w);
@@ -213,8 +203,12 @@ __global__ __launch_bounds__(64) void k_batch_indicator(const BatchInst *__restr
              : IND == DG_IND_KXRCF ? kxrcf_cell<N, 1, 2, false>(limit_target<SLOT>(I), g, i, s.j, mg)
                                    : tvb_cell<N, 1, 2, false>(limit_target<SLOT>(I), g, i, s.j, mg);
     const long long cell = (long long)s.j * g.nx + i;
-    append_batch(q, SLOT, list, I.sc, flag, ((long long)s.id << 32) | cell);
+    const unsigned long long ballot = __ballot(flag);
+    if (ballot && __lane_id() == 0) atomicAdd(&I.sc->troubled_total, (unsigned long long)__popcll(ballot));
+    wl.push(flag, ((long long)s.id << 32) | cell);
+    if (wl.n > WaveList<long long>::kCap - 64) wl.flush(reserve, list);
   }
+  wl.flush(reserve, list);
 }
 
 // Positivity-preserving scaling of the limited state over the queued row
@@ -241,9 +235,11 @@ __global__ __launch_bounds__(64 * lm_waves(N), 2) void k_batch_learned(const Bat
                                                                     long long *__restrict__ list, BatchLearned BL) {
   using S = LmShape<N>;
   __shared__ __align__(16) uint16_t lds[S::LDS];
+  __shared__ long long flagged[S::WAVES][WaveList<long long>::kCap];
   const LearnedArgs L{BL.W, BL.M, MlpLayout{4 * S::FV, S::KP}, BL.band_lo, BL.band_hi, nullptr};
   lm_load_weights<N>(L, lds);
   const int wave = threadIdx.x >> 6;
+  WaveList<long long> wl{flagged[wave], 0};
   const int total = q->total_ltiles;
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int k = queue_find(q->ltile_end, q->n_active, w);
@@ -258,8 +254,12 @@ __global__ __launch_bounds__(64 * lm_waves(N), 2) void k_batch_learned(const Bat
     lm_strip<N, false>(limit_target<SLOT>(I), g, x0, j0, j1, L, lds, lds + S::FEAT0 + wave * S::FEAT,
                 [&](bool active, bool flag, double, float p, long cell) {
                   if (active && I.prob) I.prob[cell] = p;
-                  append_batch(q, SLOT, list, I.sc, active && flag, ((long long)id << 32) | cell);
+                  wl.push(active && flag, ((long long)id << 32) | cell);
                 });
+    wl.flush([&](int k) {
+      atomicAdd(&I.sc->troubled_total, (unsigned long long)k);
+      return atomicAdd(&q->count[SLOT], k);
+    }, list);
   }
 }
 

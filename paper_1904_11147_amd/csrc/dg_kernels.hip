@@ -1728,26 +1728,9 @@ __device__ inline bool kxrcf_cell(const double *__restrict__ u, const Geometry &
   return flag;
 }
 
-// Appends the flagged cells of a wavefront to the troubled list (one atomic
-// per wavefront).
-__device__ inline void append_troubled(const LimitArgs &a, bool flag, long cell) {
-  unsigned long long ballot = __ballot(flag);
-  if (ballot) {
-    const int lane = __lane_id();
-    const int leader = __ffsll((long long)ballot) - 1;
-    int base = 0;
-    if (lane == leader) {
-      base = atomicAdd(a.count, __popcll(ballot));
-      atomicAdd(&a.sc->troubled_total, (unsigned long long)__popcll(ballot));
-    }
-    base = __shfl(base, leader);
-    if (flag) a.list[base + __popcll(ballot & ((1ull << lane) - 1ull))] = (int32_t)cell;
-  }
-}
-
-// The same for a whole block (every thread of the block calls it): one atomic
-// per block instead of one per wavefront, since every wavefront that flags a
-// cell would otherwise contend for the same counter.
+// Appends the flagged cells of a block to the troubled list (every thread of
+// the block calls it): one atomic per block, since one per wavefront contends
+// for the counter once most wavefronts flag a cell.
 __device__ inline void append_troubled_block(const LimitArgs &a, bool flag, long cell) {
   __shared__ int s_cnt[kBlock / 64];
   __shared__ int s_base;
