@@ -251,7 +251,7 @@ __global__ __launch_bounds__(64 * lm_waves(N), 2) void k_batch_learned(const Bat
     const int x0 = ((local % groups) * S::WAVES + wave) * kLmStrip;
     const int j0 = (local / groups) * kLmRows, j1 = min(j0 + kLmRows, g.ny);
     if (x0 >= g.nx) continue;  // no barrier in the loop
-    lm_strip<N, false>(limit_target<SLOT>(I), g, x0, j0, j1, L, lds, lds + S::FEAT0 + wave * S::FEAT,
+    lm_strip<N, false>(limit_target<SLOT>(I), g, x0, j0, j1, L, lds,
                 [&](bool active, bool flag, double, float p, long cell) {
                   if (active && I.prob) I.prob[cell] = p;
                   wl.push(active && flag, ((long long)id << 32) | cell);

@@ -47,9 +47,10 @@ __device__ inline bf16x4_t load4(const uint16_t *p) { return *reinterpret_cast<c
 // four lane groups of an MFMA fragment handles one of the four conserved
 // variables: the F = 4 FV features split into four per-variable blocks of FV,
 // each padded to BV = 4 ceil(FV / 4) (so 4 BV = KP for FV = 5 (N+1)^2), and
-// stored as [nb][kb][lane][4] A-fragments: element e of lane (r, g) of
-// k-block kb and output block nb is W1[16 nb + r][g FV + 4 kb + e] (zero in
-// the padding).  Defined when F is a multiple of 4 with 4 BV = KP.
+// stored as [nb][kb][lane][K] A-fragments: element e of lane (r, g) of
+// k-block kb and output block nb is W1[16 nb + r][g FV + K kb + e] (zero in
+// the padding), with K = 8 (the 16x16x32 MFMA) when BV is a multiple of 8,
+// else K = 4 (16x16x16).  Defined when F is a multiple of 4 with 4 BV = KP.
 struct MlpLayout {
   int F, KP;
   __host__ __device__ long w1() const { return 0; }
@@ -62,6 +63,12 @@ struct MlpLayout {
   __host__ __device__ int bv() const { return (F / 4 + 3) / 4 * 4; }
   __host__ __device__ bool has_w1p() const { return F % 4 == 0 && 4 * bv() == KP; }
   __host__ __device__ long npad() const { return has_w1p() ? (long)kHidden * 4 * (bv() - fv()) : 0; }
+  __host__ __device__ int frag() const { return bv() % 8 == 0 ? 8 : 4; }
+  // W1P position of W1[o][v FV + f]
+  __host__ __device__ long w1p_at(int o, int v, int f) const {
+    const int K = frag(), KB = bv() / K;
+    return w1p() + ((long)((o / 16) * KB + f / K) * 64 + v * 16 + o % 16) * K + f % K;
+  }
   // master fp32: W1 [64][F] | W2 [64][64] | w3 [64] | b1 [64] | b2 [64] | b3
   __host__ __device__ long mW2() const { return (long)kHidden * F; }
   __host__ __device__ long mw3() const { return mW2() + kHidden * kHidden; }
@@ -381,13 +388,12 @@ __global__ __launch_bounds__(64) void k_mlp_wgrad1(const uint16_t *__restrict__ 
 __global__ __launch_bounds__(kBlock) void k_mlp_adam(float *M, float *m1, float *m2, float *G, uint16_t *W,
                                                      MlpLayout lay, float lr, int step) {
   const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int KB = lay.bv() / 4;
   if (k >= lay.nmaster()) {  // zeros in the padding of W1P
     const long idx = k - lay.nmaster();
     if (idx >= lay.npad()) return;
     const int pad = lay.bv() - lay.fv();
     const int o = (int)(idx / (4 * pad)), v = (int)(idx / pad % 4), f = lay.fv() + (int)(idx % pad);
-    W[lay.w1p() + ((long)((o / 16) * KB + f / 4) * 64 + v * 16 + o % 16) * 4 + f % 4] = 0;
+    W[lay.w1p_at(o, v, f)] = 0;
     return;
   }
   float w = M[k];
@@ -409,7 +415,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_adam(float *M, float *m1, float 
     W[lay.w1() + o * lay.KP + c] = f2bf(w);
     if (lay.has_w1p()) {
       const int v = (int)(c / lay.fv()), f = (int)(c % lay.fv());
-      W[lay.w1p() + ((long)((o / 16) * KB + f / 4) * 64 + v * 16 + o % 16) * 4 + f % 4] = f2bf(w);
+      W[lay.w1p_at((int)o, v, f)] = f2bf(w);
     }
   } else if (k < lay.mw3()) {
     const long o = (k - lay.mW2()) / kHidden, c = (k - lay.mW2()) % kHidden;
@@ -439,17 +445,19 @@ struct LearnedArgs {
 // at and above the current one are kept in registers (one load per value),
 // west and east neighbours come from the adjacent slots.  The network is
 // evaluated transposed, H^T = W X^T, with the weights as the MFMA A operand:
-// a lane's features (variable g of cell r) are its B fragments and each
-// layer's output fragments are the next layer's B fragments.
+// the B fragment of k-block kb held by lane (r, g) is features 4 kb .. 4 kb + 3
+// of variable g of cell r, i.e. the lane's own features, so they go to the
+// MFMA straight from registers; each layer's output fragments are the next
+// layer's B fragments.
 template <int N>
 struct LmShape {
-  static constexpr int NP = N + 1, NM = NP * NP, FV = 5 * NM, BV = (FV + 3) / 4 * 4, KB = BV / 4;
+  static constexpr int NP = N + 1, NM = NP * NP, FV = 5 * NM, BV = (FV + 3) / 4 * 4;
+  static constexpr int FK = BV % 8 == 0 ? 8 : 4, KB = BV / FK;  // features per lane and k-block (MlpLayout::frag)
   static constexpr int KP = 4 * BV;  // padded input width (= (F + 15) / 16 * 16 for F = 4 FV)
-  static constexpr int W1 = kHidden * KP, W2 = kHidden * kHidden, FEAT = KB * 256;
+  static constexpr int W1 = kHidden * KP, W2 = kHidden * kHidden;
   static constexpr int PAR = 2 * (3 * kHidden + 2);  // b1 | b2 | w3 | b3 as floats (in bf16 slots)
   static constexpr int WAVES = lm_waves(N);
-  static constexpr int LDS = W1 + W2 + PAR + WAVES * FEAT;
-  static constexpr int FEAT0 = W1 + W2 + PAR;  // first per-wave feature slot
+  static constexpr int LDS = W1 + W2 + PAR;
 };
 
 // Copies the weights into LDS in fragment order (whole block), then a barrier.
@@ -460,11 +468,23 @@ __device__ inline void lm_load_weights(const LearnedArgs &L, uint16_t *wl) {
   const uint16_t *__restrict__ W1P = L.W + L.lay.w1p();
   for (int k = tid; k < S::W1 / 4; k += nt)
     reinterpret_cast<uint2 *>(wl)[k] = reinterpret_cast<const uint2 *>(W1P)[k];
-  // W2 A-fragments: element e of lane (r, g), k-block kb, output block nb is W2[16 nb + r][16 kb + 4 g + e]
+  // W2 A-fragments: element e of lane (r, g), k-block kb, output block nb is
+  // W2[16 nb + r][c] with c = 16 kb + 4 g + e (K = 4), or, for K = 8, the
+  // hidden units that lane's layer-1 output blocks 2 kb and 2 kb + 1 hold:
+  // c = 16 (2 kb + e / 4) + 4 g + e % 4
   const uint16_t *__restrict__ W2 = L.W + L.lay.w2();
   for (int k = tid; k < S::W2; k += nt) {
-    const int e = k & 3, ln = (k >> 2) & 63, kb = (k >> 8) & 3, nb = k >> 10;
-    wl[S::W1 + k] = W2[(16 * nb + (ln & 15)) * kHidden + 16 * kb + 4 * (ln >> 4) + e];
+    int e, ln, c, nb;
+    if constexpr (S::FK == 8) {
+      e = k & 7, ln = (k >> 3) & 63, nb = k >> 10;
+      const int kb = (k >> 9) & 1;
+      c = 16 * (2 * kb + e / 4) + 4 * (ln >> 4) + e % 4;
+    } else {
+      e = k & 3, ln = (k >> 2) & 63, nb = k >> 10;
+      const int kb = (k >> 8) & 3;
+      c = 16 * kb + 4 * (ln >> 4) + e;
+    }
+    wl[S::W1 + k] = W2[(16 * nb + (ln & 15)) * kHidden + c];
   }
   float *par = reinterpret_cast<float *>(wl + S::W1 + S::W2);
   for (int k = tid; k < kHidden; k += nt) {
@@ -491,15 +511,64 @@ __device__ __forceinline__ double row_shift1(double v) {
                                  : __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
+// The same shifts reading 0 in the lane with no source (the x-halo slots,
+// whose results are never used): no select, and the f32 form folds into the
+// DPP operand of the instruction that uses it.
+template <bool UP>
+__device__ __forceinline__ float row_shift0(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), UP ? 0x111 : 0x101, 0xF, 0xF, true));
+}
+template <bool UP>
+__device__ __forceinline__ double row_shift0(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, UP ? 0x111 : 0x101, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), UP ? 0x111 : 0x101, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// max(x, 0) on the bit pattern: a negative float is a negative integer
+// (one integer max, no NaN quieting of the MFMA results first)
+__device__ __forceinline__ float relu_bits(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+// the larger of two non-negative floats, by their bit patterns
+__device__ __forceinline__ float max_nonneg(float a, float b) {
+  return __uint_as_float(max(__float_as_uint(a), __float_as_uint(b)));
+}
+
+typedef __bf16 bf16x2h_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+// two floats to bf16 (nearest even) in one conversion
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{a, b}, bf16x2h_t));
+}
+__device__ __forceinline__ bf16x4_t pk4_bf16(float a, float b, float c, float d) {
+  const uint2 v{pk_bf16(a, b), pk_bf16(c, d)};
+  return __builtin_bit_cast(bf16x4_t, v);
+}
+__device__ __forceinline__ bf16x8_t cat8(bf16x4_t lo, bf16x4_t hi) {
+  const uint2 a = __builtin_bit_cast(uint2, lo), b = __builtin_bit_cast(uint2, hi);
+  return __builtin_bit_cast(bf16x8_t, uint4{a.x, a.y, b.x, b.y});
+}
+__device__ __forceinline__ bf16x8_t load8(const uint16_t *p) { return *reinterpret_cast<const bf16x8_t *>(p); }
+// D += A B for 16 x 32 A and 32 x 16 B fragments (eight bf16 per lane each)
+__device__ __forceinline__ f32x4_t mfma32(bf16x8_t a, bf16x8_t b, f32x4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
 // One wavefront's strip: columns x0-1 .. x0+14 (owned x0 .. x0+13), rows
 // j0 .. j1-1.  emit(active, flag, margin, p, cell) is called by every lane
 // once per row (active: an owned cell, from lane group 0).
+//
+// Features are formed in FP32 from the FP64 state: the four mean
+// differences (to the centre's mean) in FP64 and then rounded, the other
+// modes rounded once per row they enter; the scale s is the FP32 rounding of
+// the exact maximum (rounding is monotonic), and each feature is the FP32
+// product with 1 / s, then rounded to BF16 for the network.
 template <int N, bool BND, typename Emit>
 __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g, int x0, int j0, int j1,
-                                const LearnedArgs &L, const uint16_t *__restrict__ wl, uint16_t *__restrict__ feat,
-                                Emit &&emit) {
+                                const LearnedArgs &L, const uint16_t *__restrict__ wl, Emit &&emit) {
   using S = LmShape<N>;
-  constexpr int NP = S::NP, NM = S::NM, FV = S::FV, BV = S::BV, KB = S::KB;
+  constexpr int NP = S::NP, NM = S::NM, NH = NM - 1, FV = S::FV, KB = S::KB;
   const OrderTables &T = c_tab[N];
   const int lane = threadIdx.x & 63, r = lane & 15, gv = lane >> 4;
   int col = x0 + r - 1;
@@ -522,54 +591,47 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
       }
     }
   };
-  // largest |mode| but the mean of a cell's variable (per row, so that the
-  // features' scale takes 5 of these instead of all 45 entries)
-  auto hi_modes = [&](const double (&R)[NM]) {
-    double m = 0.0;
+  // a row's modes but the mean in FP32; returns their largest magnitude
+  auto to32 = [&](const double (&R)[NM], float (&F)[NH]) {
+    float m = 0.f;
 #pragma unroll
-    for (int q = 1; q < NM; ++q) m = fmax(m, fabs(R[q]));
+    for (int q = 1; q < NM; ++q) {
+      F[q - 1] = (float)R[q];
+      m = fmaxf(m, fabsf(F[q - 1]));
+    }
     return m;
   };
-  double Sv[NM], Cv[NM], Nv[NM];
-  loadrow(j0 - 1, Sv);
+  double Sm, Cv[NM], Nv[NM];  // Sm: the south neighbour's mean
+  float S32[NH], C32[NH], N32[NH], hS, hC, hN;
+  {
+    double Sv[NM];
+    loadrow(j0 - 1, Sv);
+    Sm = Sv[0];
+    hS = to32(Sv, S32);
+  }
   loadrow(j0, Cv);
   loadrow(j0 + 1, Nv);
-  double hS = hi_modes(Sv), hC = hi_modes(Cv), hN = hi_modes(Nv);
-  uint16_t *fl = feat + lane * 4;  // feature f at fl[(f / 4) * 256 + f % 4]
-#pragma unroll
-  for (int f = FV; f < BV; ++f) fl[(f / 4) * 256 + f % 4] = 0;
+  hC = to32(Cv, C32);
+  hN = to32(Nv, N32);
+  const float Mh2 = (float)g.tvb_Mx;
   const double k0 = T.b0[0] * T.b0[0];
+  const f32x4_t *b1f = reinterpret_cast<const f32x4_t *>(par + 4 * gv);
+  const f32x4_t *b2f = reinterpret_cast<const f32x4_t *>(par + kHidden + 4 * gv);
   // Q1, Q2: the layer-2 weight fragments stay in registers for the whole strip
   constexpr bool w2_regs = N <= 2;
-  bf16x4_t w2f[w2_regs ? 4 : 1][w2_regs ? 4 : 1];
+  constexpr int FK = S::FK, KB2 = kHidden / (4 * FK);  // layer-2 k-blocks
+  auto w2frag = [&](int nb, int kb) { return wl + S::W1 + ((nb * KB2 + kb) * 64 + lane) * FK; };
+  bf16x4_t w2f[w2_regs ? 4 : 1][w2_regs ? 4 : 1];  // K = 8: [nb][2 kb + half]
   if constexpr (w2_regs) {
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
-      for (int kb = 0; kb < 4; ++kb) w2f[nb][kb] = load4(wl + S::W1 + ((nb * 4 + kb) * 64 + lane) * 4);
+      for (int kb = 0; kb < 4; ++kb)
+        w2f[nb][kb] = FK == 8 ? load4(w2frag(nb, kb / 2) + 4 * (kb % 2)) : load4(w2frag(nb, kb));
   }
   for (int j = j0; j < j1; ++j) {
     double Pv[NM];
     loadrow(j + 2, Pv);  // in flight while this row is evaluated
-    // west and east neighbours from the adjacent slots: kept for Q1, Q2;
-    // Q3 fetches them when each feature is formed (registers)
-    constexpr bool keep_we = N <= 2;
-    double Wv[keep_we ? NM : 1], Ev[keep_we ? NM : 1];
-    if constexpr (keep_we) {
-#pragma unroll
-      for (int q = 0; q < NM; ++q) {
-        Wv[q] = row_shift1<true>(Cv[q]);
-        Ev[q] = row_shift1<false>(Cv[q]);
-      }
-    }
-    auto west = [&](int q) -> double {
-      if constexpr (keep_we) return Wv[q];
-      else return row_shift1<true>(Cv[q]);
-    };
-    auto east = [&](int q) -> double {
-      if constexpr (keep_we) return Ev[q];
-      else return row_shift1<false>(Cv[q]);
-    };
     // TVB decision of this variable (the expressions of tvb_cell), combined
     // over the cell's lanes; only needed for a probability inside the band
     auto tvb_decision = [&](bool &tflag, double &tmg) {
@@ -579,10 +641,8 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
 #pragma unroll
       for (int dir = 0; dir < 2; ++dir) {
         const double Mh2 = dir == 0 ? g.tvb_Mx : g.tvb_My;
-        // the x-neighbours' means by a fresh shift (the stored west/east rows
-        // are dead by now)
         const double mp = (dir == 0 ? row_shift1<false>(Cv[0]) : Nv[0]) * k0;
-        const double mm = (dir == 0 ? row_shift1<true>(Cv[0]) : Sv[0]) * k0;
+        const double mm = (dir == 0 ? row_shift1<true>(Cv[0]) : Sm) * k0;
         double upv = 0.0, umv = 0.0;
 #pragma unroll
         for (int q = 0; q < NM; ++q) {
@@ -603,57 +663,76 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
       tmg = fmin(tmg, __shfl_xor(tmg, 16));
       tmg = fmin(tmg, __shfl_xor(tmg, 32));
     };
-    // features: C, W, E, S, N of variable gv; mode 0 relative to the centre's; scaled
-    {
-      const double c0 = Cv[0];
-      auto val = [&](int f) -> double {
-        const int c = f / NM, q = f % NM;
-        const double v = c == 0 ? Cv[q] : (c == 1 ? west(q) : (c == 2 ? east(q) : (c == 3 ? Sv[q] : Nv[q])));
-        return q == 0 ? v - c0 : v;
-      };
-      // the largest |entry|: the five cells' non-mean maxima and the four
-      // shifted means (the centre's is 0), with M h^2 as the floor
-      double mx = fmax(g.tvb_Mx, fmax(hC, fmax(hS, hN)));
-      mx = fmax(mx, fmax(row_shift1<true>(hC), row_shift1<false>(hC)));
-      mx = fmax(mx, fmax(fabs(west(0) - c0), fabs(east(0) - c0)));
-      mx = fmax(mx, fmax(fabs(Sv[0] - c0), fabs(Nv[0] - c0)));
-      const double inv = 1.0 / mx;
-#pragma unroll
-      for (int f = 0; f < FV; ++f) fl[(f / 4) * 256 + f % 4] = f2bf_hw((float)(val(f) * inv));
-    }
-    // layer 1: H1^T = W1 X^T
+    // features of variable gv: C, W, E, S, N, each with its modes; the
+    // means relative to the centre's (whose own entry is 0); scaled by 1 / s
+    const double c0 = Cv[0];
+    const float dW = (float)(row_shift0<true>(c0) - c0), dE = (float)(row_shift0<false>(c0) - c0);
+    const float dS = (float)(Sm - c0), dN = (float)(Nv[0] - c0);
+    float mx = max_nonneg(max_nonneg(Mh2, hC), max_nonneg(hS, hN));
+    mx = max_nonneg(mx, max_nonneg(row_shift0<true>(hC), row_shift0<false>(hC)));
+    mx = max_nonneg(mx, max_nonneg(max_nonneg(fabsf(dW), fabsf(dE)), max_nonneg(fabsf(dS), fabsf(dN))));
+    const float inv = 1.0f / mx;
+    auto feature = [&](int f) -> float {
+      if (f >= FV) return 0.f;  // padding
+      const int c = f / NM, q = f % NM;
+      if (q == 0) return c == 0 ? 0.f : (c == 1 ? dW : (c == 2 ? dE : (c == 3 ? dS : dN))) * inv;
+      switch (c) {
+        case 0: return C32[q - 1] * inv;
+        case 1: return row_shift0<true>(C32[q - 1]) * inv;
+        case 2: return row_shift0<false>(C32[q - 1]) * inv;
+        case 3: return S32[q - 1] * inv;
+        default: return N32[q - 1] * inv;
+      }
+    };
+    // layer 1: H1^T = W1 X^T (+ b1 as the accumulator's start)
     f32x4_t h[4];
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) h[nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-    for (int kb = 0; kb < KB; ++kb) {
-      const bf16x4_t x = load4(feat + (kb * 64 + lane) * 4);
+    for (int nb = 0; nb < 4; ++nb) h[nb] = b1f[4 * nb];
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) h[nb] = mfma16(load4(wl + ((nb * KB + kb) * 64 + lane) * 4), x, h[nb]);
+    for (int kb = 0; kb < KB; ++kb) {
+      const int f = FK * kb;
+      const bf16x4_t x = pk4_bf16(feature(f), feature(f + 1), feature(f + 2), feature(f + 3));
+      if constexpr (FK == 8) {
+        const bf16x8_t x8 = cat8(x, pk4_bf16(feature(f + 4), feature(f + 5), feature(f + 6), feature(f + 7)));
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) h[nb] = mfma32(load8(wl + ((nb * KB + kb) * 64 + lane) * 8), x8, h[nb]);
+      } else {
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) h[nb] = mfma16(load4(wl + ((nb * KB + kb) * 64 + lane) * 4), x, h[nb]);
+      }
+      __builtin_amdgcn_sched_barrier(0);  // keeps each k-block's fragment loads next to their use (registers)
     }
     bf16x4_t h1[4];
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb)
+      h1[nb] = pk4_bf16(relu_bits(h[nb][0]), relu_bits(h[nb][1]), relu_bits(h[nb][2]), relu_bits(h[nb][3]));
+    // layer 2: H2^T = W2 H1^T (+ b2); for K = 8 the B fragment of k-block kb
+    // is the lane's layer-1 blocks 2 kb and 2 kb + 1
 #pragma unroll
-      for (int e = 0; e < 4; ++e) h1[nb][e] = (short)f2bf_hw(fmaxf(h[nb][e] + par[16 * nb + 4 * gv + e], 0.f));
-    // layer 2: H2^T = W2 H1^T
+    for (int nb = 0; nb < 4; ++nb) h[nb] = b2f[4 * nb];
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) h[nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int kb = 0; kb < KB2; ++kb)
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb)
-        h[nb] = mfma16(w2_regs ? w2f[w2_regs ? nb : 0][w2_regs ? kb : 0]
-                               : load4(wl + S::W1 + ((nb * 4 + kb) * 64 + lane) * 4),
-                       h1[kb], h[nb]);
-    // layer 3 and the decision
+      for (int nb = 0; nb < 4; ++nb) {
+        if constexpr (FK == 8) {
+          const bf16x8_t a = w2_regs ? cat8(w2f[w2_regs ? nb : 0][w2_regs ? 2 * kb : 0],
+                                            w2f[w2_regs ? nb : 0][w2_regs ? 2 * kb + 1 : 0])
+                                     : load8(w2frag(nb, kb));
+          h[nb] = mfma32(a, cat8(h1[2 * kb], h1[2 * kb + 1]), h[nb]);
+        } else {
+          h[nb] = mfma16(w2_regs ? w2f[w2_regs ? nb : 0][w2_regs ? kb : 0] : load4(w2frag(nb, kb)), h1[kb], h[nb]);
+        }
+      }
+    // layer 3 (on the BF16-rounded activations) and the decision
     float part = 0.f;
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < 4; e += 2) {
         const int k = 16 * nb + 4 * gv + e;
-        part += bf2f(f2bf_hw(fmaxf(h[nb][e] + par[kHidden + k], 0.f))) * par[2 * kHidden + k];
+        const uint32_t hb = pk_bf16(relu_bits(h[nb][e]), relu_bits(h[nb][e + 1]));
+        part += __uint_as_float(hb << 16) * par[2 * kHidden + k];
+        part += __uint_as_float(hb & 0xffff0000u) * par[2 * kHidden + k + 1];
       }
     part += __shfl_xor(part, 16);
     part += __shfl_xor(part, 32);
@@ -672,15 +751,20 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
     }
     if (p > L.band_hi) flag = true;
     emit(owner && gv == 0, flag, mg, p, (long)j * g.nx + col);
+    Sm = c0;
 #pragma unroll
     for (int q = 0; q < NM; ++q) {
-      Sv[q] = Cv[q];
       Cv[q] = Nv[q];
       Nv[q] = Pv[q];
     }
+#pragma unroll
+    for (int q = 0; q < NH; ++q) {
+      S32[q] = C32[q];
+      C32[q] = N32[q];
+    }
     hS = hC;
     hC = hN;
-    hN = hi_modes(Nv);
+    hN = to32(Nv, N32);
   }
 }
 
@@ -728,7 +812,7 @@ __global__ __launch_bounds__(64 * lm_waves(N), 2) void k_indicator_learned(Limit
   if (x0 >= g.nx) return;  // no barrier follows
   const int j0 = blockIdx.y * rows, j1 = min(j0 + min(rows, kLmRows), g.ny);
   WaveList<int32_t> wl{flagged[wave], 0};
-  lm_strip<N, BND>(a.u, g, x0, j0, j1, L, lds, lds + S::FEAT0 + wave * S::FEAT,
+  lm_strip<N, BND>(a.u, g, x0, j0, j1, L, lds,
               [&](bool active, bool flag, double mg, float p, long cell) {
                 if (active) {
                   if (L.prob) L.prob[cell] = p;
