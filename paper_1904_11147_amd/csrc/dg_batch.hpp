@@ -231,7 +231,7 @@ __global__ __launch_bounds__(64) void k_batch_positivity(const BatchInst *__rest
 // The learned indicator over the queued learned tiles (lm_waves(N) strips of
 // kLmRows rows each); the block keeps the order's network in LDS.
 template <int N, int SLOT>
-__global__ __launch_bounds__(64 * lm_waves(N), 2) void k_batch_learned(const BatchInst *__restrict__ inst, BatchQueue *q,
+__global__ __launch_bounds__(64 * lm_waves(N), lm_occupancy(N)) void k_batch_learned(const BatchInst *__restrict__ inst, BatchQueue *q,
                                                                     long long *__restrict__ list, BatchLearned BL) {
   using S = LmShape<N>;
   __shared__ __align__(16) uint16_t lds[S::LDS];

@@ -132,6 +132,7 @@ struct LaunchCtx {
 // wavefronts, each marching kLmRows rows of a kLmStrip-column strip.
 constexpr int kLmStrip = 14, kLmRows = 16;
 constexpr int lm_waves(int order) { return order == 3 ? 8 : 4; }  // constexpr: usable in device code too
+constexpr int lm_occupancy(int order) { return order == 3 ? 2 : 3; }  // wavefronts per SIMD the kernels are built for
 
 // ---------------------------------------------------------------------------
 // Batched execution: many independent 2D Euler meshes of any size and order,

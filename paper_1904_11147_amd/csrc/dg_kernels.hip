@@ -1859,6 +1859,136 @@ __device__ inline void weno_row(const Tab &T, const double *a_in, double *out, d
   }
 }
 
+// The uniform-mesh tables of order N through a pointer the compiler cannot
+// see through, produced after `dep` is computed.  Coefficients read through
+// it are loaded into scalar registers at that point of the program: a phase
+// of the limiter loads only its own coefficients once the previous phase's
+// result exists.  (Read through c_tab directly, every coefficient the kernel
+// uses is loaded once at its start; they overflow the scalar register file
+// and are read back from vector-register lanes at every use.)
+typedef const __attribute__((address_space(4))) OrderTables *tab_sptr;
+template <int N>
+__device__ __forceinline__ tab_sptr tab_after(double dep) {
+  tab_sptr p = (tab_sptr)&c_tab[N];
+  asm volatile("" : "+s"(p) : "v"(dep));
+  return p;
+}
+
+// weno_row on rows F .. F+R-1 of src (row r: 2N+1 stencil means) with the
+// uniform-mesh tables, out[G][r] = the WENO value at point G.  The same
+// arithmetic, grouped by coefficient: one phase per stencil's smoothness
+// matrix, then one per point, each over all R rows.
+template <int N, int F, int R, int NR>
+__device__ inline double weno_rows(const double (&src)[NR][2 * N + 1], double (&out)[num_points<N>()][NR], double eps,
+                                   bool raw, double dep) {
+  constexpr int NP = N + 1, NG = num_points<N>(), NS = 2 * N + 1;
+  double a[R][NS], a0[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    a0[r] = src[F + r][N];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) a[r][k] = src[F + r][k] - a0[r];
+  }
+  double e2[R][NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const tab_sptr T = tab_after<N>(dep);
+    double B[NP][NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+#pragma unroll
+      for (int l = 0; l < NP; ++l) B[k][l] = T->B[i][k][l];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      double beta = 0.0;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < NP; ++l) s += B[k][l] * a[r][i + l];
+        beta += a[r][i + k] * s;
+      }
+      const double e = eps + beta;
+      e2[r][i] = e * e;
+    }
+    dep = e2[0][i];
+  }
+  double d[R][NP];  // products of the other stencils' (eps + beta)^2
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double pre[NP], suf[NP];
+    pre[0] = 1.0;
+#pragma unroll
+    for (int i = 1; i < NP; ++i) pre[i] = pre[i - 1] * e2[r][i - 1];
+    suf[NP - 1] = 1.0;
+#pragma unroll
+    for (int i = NP - 2; i >= 0; --i) suf[i] = suf[i + 1] * e2[r][i + 1];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) d[r][i] = pre[i] * suf[i];
+  }
+#pragma unroll
+  for (int G = 0; G < NG; ++G) {
+    // the stencils' polynomials at x_G (one phase), then their weights (another)
+    double p[R][NP];
+    {
+      const tab_sptr T = tab_after<N>(dep);
+      double Tg[NP][NP];
+#pragma unroll
+      for (int i = 0; i < NP; ++i)
+#pragma unroll
+        for (int k = 0; k < NP; ++k) Tg[i][k] = T->T[G][i][k];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          double s = 0.0;
+#pragma unroll
+          for (int k = 0; k < NP; ++k) s += Tg[i][k] * a[r][i + k];
+          p[r][i] = s;
+        }
+      dep = p[0][0];
+    }
+    const tab_sptr T = tab_after<N>(dep);
+    const bool split = N == 3 && T->split[G] && !raw;
+    double c1[NP], c2[NP], s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      c1[i] = split ? T->gpn[G][i] : T->gam[G][i];
+      c2[i] = split ? T->gmn[G][i] : 0.0;
+    }
+    if (split) {
+      s1 = T->sp[G];
+      s2 = T->sm[G];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (split) {
+        double wp = 0.0, up = 0.0, wm = 0.0, um = 0.0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          const double x = c1[i] * d[r][i], y = c2[i] * d[r][i];
+          wp += x;
+          up += x * p[r][i];
+          wm += y;
+          um += y * p[r][i];
+        }
+        out[G][F + r] = a0[r] + (s1 * (up * fast_rcp(wp)) - s2 * (um * fast_rcp(wm)));
+      } else {
+        double ws = 0.0, us = 0.0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          const double x = c1[i] * d[r][i];
+          ws += x;
+          us += x * p[r][i];
+        }
+        out[G][F + r] = a0[r] + us * fast_rcp(ws);
+      }
+    }
+    dep = out[G][F];
+  }
+  return dep;
+}
+
 // mean of psi_n over stencil interval k (0..2N) of the compact stencil
 template <int N>
 __device__ inline double interval_mean(const OrderTables &T, int k, int n) {
@@ -1906,39 +2036,129 @@ __device__ inline void csweno_cell(const double *__restrict__ u, double *__restr
       side[(long)(v * NM + n) * plane + cell] = s;
     }
   } else {
-    // (2N+1)^2 sub-rectangle means of the 3x3 block, [iy][ix]
+    // (2N+1)^2 sub-rectangle means of the 3x3 block, [iy][ix]; im(k, n) is
+    // interval_mean
     double st[NS][NS];
+    auto fill_st = [&](auto im) {
 #pragma unroll
-    for (int cy = 0; cy < 3; ++cy)
+      for (int cy = 0; cy < 3; ++cy)
 #pragma unroll
-      for (int cx = 0; cx < 3; ++cx) {
-        CellIdx ci = map_cell<BND>(g, i + cx - 1, j + cy - 1);
-        double md[NM];
+        for (int cx = 0; cx < 3; ++cx) {
+          CellIdx ci = map_cell<BND>(g, i + cx - 1, j + cy - 1);
+          double md[NM];
 #pragma unroll
-        for (int q = 0; q < NM; ++q) md[q] = cell_mode<NP, NM, 2>(u, plane, g, ci, v, q);
-        const int x0 = cx == 0 ? 0 : (cx == 1 ? N : N + 1), x1 = cx == 0 ? N : (cx == 1 ? N + 1 : NS);
-        const int y0 = cy == 0 ? 0 : (cy == 1 ? N : N + 1), y1 = cy == 0 ? N : (cy == 1 ? N + 1 : NS);
+          for (int q = 0; q < NM; ++q) md[q] = cell_mode<NP, NM, 2>(u, plane, g, ci, v, q);
+          const int x0 = cx == 0 ? 0 : (cx == 1 ? N : N + 1), x1 = cx == 0 ? N : (cx == 1 ? N + 1 : NS);
+          const int y0 = cy == 0 ? 0 : (cy == 1 ? N : N + 1), y1 = cy == 0 ? N : (cy == 1 ? N + 1 : NS);
 #pragma unroll
-        for (int ix = 0; ix < NS; ++ix) {
-          if (ix < x0 || ix >= x1) continue;
-          double tn[NP];
+          for (int ix = 0; ix < NS; ++ix) {
+            if (ix < x0 || ix >= x1) continue;
+            double tn[NP];
 #pragma unroll
-          for (int n = 0; n < NP; ++n) {
-            double s = 0.0;
+            for (int n = 0; n < NP; ++n) {
+              double s = 0.0;
 #pragma unroll
-            for (int m = 0; m < NP; ++m) s += md[m + NP * n] * interval_mean<N>(T, ix, m);
-            tn[n] = s;
-          }
+              for (int m = 0; m < NP; ++m) s += md[m + NP * n] * im(ix, m);
+              tn[n] = s;
+            }
 #pragma unroll
-          for (int iy = 0; iy < NS; ++iy) {
-            if (iy < y0 || iy >= y1) continue;
-            double s = 0.0;
+            for (int iy = 0; iy < NS; ++iy) {
+              if (iy < y0 || iy >= y1) continue;
+              double s = 0.0;
 #pragma unroll
-            for (int n = 0; n < NP; ++n) s += tn[n] * interval_mean<N>(T, iy, n);
-            st[iy][ix] = s;
+              for (int n = 0; n < NP; ++n) s += tn[n] * im(iy, n);
+              st[iy][ix] = s;
+            }
           }
         }
+    };
+    if constexpr (!BND) {
+      // the periodic/transmissive kernels (the hot ones): interval means and
+      // then each WENO phase's coefficients loaded when needed (tab_after), the
+      // rows of each sweep batched
+      const tab_sptr Ts = tab_after<N>((double)(int)cell);
+      double sb[N][NP];
+#pragma unroll
+      for (int k = 0; k < N; ++k)
+#pragma unroll
+        for (int n = 0; n < NP; ++n) sb[k][n] = Ts->sub[k][n];
+      const double b00 = Ts->b0[0];
+      fill_st([&](int k, int n) -> double {
+        if (k == N) return n == 0 ? b00 : 0.0;
+        return sb[k < N ? k : k - N - 1][n];
+      });
+      // x-sweeps: y-interval means at the x-points, vy[G][iy]; Q3 in two
+      // batches of rows (register file)
+      double vy[NG][NS];
+      double dep = st[N][N];
+      if constexpr (N == 3) {
+        dep = weno_rows<N, 0, 4>(st, vy, g.eps, raw, dep);
+        dep = weno_rows<N, 4, NS - 4>(st, vy, g.eps, raw, dep);
+      } else {
+        dep = weno_rows<N, 0, NS>(st, vy, g.eps, raw, dep);
       }
+      // y-sweeps at every x-point: uy[H][G] = u(x_G, y_H)
+      double uy[NG][NG];
+      dep = weno_rows<N, 0, NG>(vy, uy, g.eps, raw, dep);
+      // the tensor projection
+      const tab_sptr Tp = tab_after<N>(dep);
+      double wb[NP][NG];  // wg[G] psi_n(r_G)
+#pragma unroll
+      for (int n = 0; n < NP; ++n)
+#pragma unroll
+        for (int G = 0; G < NG; ++G) wb[n][G] = Tp->wg[G] * Tp->bg[n][G];
+      double sp[NG][NP];  // sp[G][n] = sum_H wg[H] u(G,H) psi_n(y_H)
+#pragma unroll
+      for (int G = 0; G < NG; ++G)
+#pragma unroll
+        for (int n = 0; n < NP; ++n) {
+          double acc = 0.0;
+#pragma unroll
+          for (int H = 0; H < NG; ++H) acc += Tp->wg[H] * uy[H][G] * Tp->bg[n][H];
+          sp[G][n] = acc;
+        }
+#pragma unroll
+      for (int q = 1; q < NM; ++q) {
+        const int m = q % NP, n = q / NP;
+        double acc = 0.0;
+#pragma unroll
+        for (int G = 0; G < NG; ++G) acc += wb[m][G] * sp[G][n];
+        side[(long)(v * NM + q) * plane + cell] = acc;
+      }
+      return;
+    } else {
+#pragma unroll
+      for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+        for (int cx = 0; cx < 3; ++cx) {
+          CellIdx ci = map_cell<BND>(g, i + cx - 1, j + cy - 1);
+          double md[NM];
+#pragma unroll
+          for (int q = 0; q < NM; ++q) md[q] = cell_mode<NP, NM, 2>(u, plane, g, ci, v, q);
+          const int x0 = cx == 0 ? 0 : (cx == 1 ? N : N + 1), x1 = cx == 0 ? N : (cx == 1 ? N + 1 : NS);
+          const int y0 = cy == 0 ? 0 : (cy == 1 ? N : N + 1), y1 = cy == 0 ? N : (cy == 1 ? N + 1 : NS);
+#pragma unroll
+          for (int ix = 0; ix < NS; ++ix) {
+            if (ix < x0 || ix >= x1) continue;
+            double tn[NP];
+#pragma unroll
+            for (int n = 0; n < NP; ++n) {
+              double s = 0.0;
+#pragma unroll
+              for (int m = 0; m < NP; ++m) s += md[m + NP * n] * interval_mean<N>(T, ix, m);
+              tn[n] = s;
+            }
+#pragma unroll
+            for (int iy = 0; iy < NS; ++iy) {
+              if (iy < y0 || iy >= y1) continue;
+              double s = 0.0;
+#pragma unroll
+              for (int n = 0; n < NP; ++n) s += tn[n] * interval_mean<N>(T, iy, n);
+              st[iy][ix] = s;
+            }
+          }
+        }
+    }
     // x-sweeps: y-interval means at the x-points
     double vy[NG][NS];
 #pragma unroll

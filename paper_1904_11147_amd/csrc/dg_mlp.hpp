@@ -617,8 +617,9 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
   const double k0 = T.b0[0] * T.b0[0];
   const f32x4_t *b1f = reinterpret_cast<const f32x4_t *>(par + 4 * gv);
   const f32x4_t *b2f = reinterpret_cast<const f32x4_t *>(par + kHidden + 4 * gv);
-  // Q1, Q2: the layer-2 weight fragments stay in registers for the whole strip
-  constexpr bool w2_regs = N <= 2;
+  // the layer-2 weight fragments are read from LDS per row (in registers they
+  // would cost the third wavefront per SIMD at Q2)
+  constexpr bool w2_regs = false;
   constexpr int FK = S::FK, KB2 = kHidden / (4 * FK);  // layer-2 k-blocks
   auto w2frag = [&](int nb, int kb) { return wl + S::W1 + ((nb * KB2 + kb) * 64 + lane) * FK; };
   bf16x4_t w2f[w2_regs ? 4 : 1][w2_regs ? 4 : 1];  // K = 8: [nb][2 kb + half]
@@ -799,7 +800,7 @@ struct WaveList {
 
 // Single mesh: grid (strip groups, row chunks of kLmRows); block = lm_waves(N) wavefronts.
 template <int N, int EQ, bool BND>
-__global__ __launch_bounds__(64 * lm_waves(N), 2) void k_indicator_learned(LimitArgs a, LearnedArgs L, int rows) {
+__global__ __launch_bounds__(64 * lm_waves(N), lm_occupancy(N)) void k_indicator_learned(LimitArgs a, LearnedArgs L, int rows) {
   static_assert(EQ == 1, "learned indicator: 2D Euler");
   using S = LmShape<N>;
   __shared__ __align__(16) uint16_t lds[S::LDS];
