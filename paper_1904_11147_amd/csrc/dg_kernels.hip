@@ -2364,18 +2364,36 @@ __device__ inline void csweno_char_cell(const double *__restrict__ u, double *__
         }
       }
       double cG[NV][NG];
+      if constexpr (!BND) {  // the fields' rows batched, coefficients by phase (weno_rows)
+        double ch[NV][NS], cGt[NG][NV];
 #pragma unroll
-      for (int f = 0; f < NV; ++f) {
-        double ch[NS];
+        for (int f = 0; f < NV; ++f)
 #pragma unroll
-        for (int ix = 0; ix < NS; ++ix) {
-          double s = 0.0;
+          for (int ix = 0; ix < NS; ++ix) {
+            double s = 0.0;
 #pragma unroll
-          for (int v = 0; v < NV; ++v) s += L[f][v] * a[v][ix];
-          ch[ix] = s;
+            for (int v = 0; v < NV; ++v) s += L[f][v] * a[v][ix];
+            ch[f][ix] = s;
+          }
+        weno_rows<N, 0, NV>(ch, cGt, g.eps, raw, ch[0][N]);
+#pragma unroll
+        for (int f = 0; f < NV; ++f)
+#pragma unroll
+          for (int G = 0; G < NG; ++G) cG[f][G] = cGt[G][f];
+      } else {
+#pragma unroll
+        for (int f = 0; f < NV; ++f) {
+          double ch[NS];
+#pragma unroll
+          for (int ix = 0; ix < NS; ++ix) {
+            double s = 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) s += L[f][v] * a[v][ix];
+            ch[ix] = s;
+          }
+          if (BND && g.wtx) weno_row<N>(g.wtx[i], ch, cG[f], g.eps, raw);
+          else weno_row<N>(T, ch, cG[f], g.eps, raw);
         }
-        if (BND && g.wtx) weno_row<N>(g.wtx[i], ch, cG[f], g.eps, raw);
-        else weno_row<N>(T, ch, cG[f], g.eps, raw);
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v)
@@ -2397,18 +2415,36 @@ __device__ inline void csweno_char_cell(const double *__restrict__ u, double *__
 #pragma unroll
     for (int G = 0; G < NG; ++G) {
       double cH[NV][NG];
+      if constexpr (!BND) {
+        double ch[NV][NS], cHt[NG][NV];
 #pragma unroll
-      for (int f = 0; f < NV; ++f) {
-        double ch[NS];
+        for (int f = 0; f < NV; ++f)
 #pragma unroll
-        for (int iy = 0; iy < NS; ++iy) {
-          double s = 0.0;
+          for (int iy = 0; iy < NS; ++iy) {
+            double s = 0.0;
 #pragma unroll
-          for (int v = 0; v < NV; ++v) s += L[f][v] * vy[v][iy][G];
-          ch[iy] = s;
+            for (int v = 0; v < NV; ++v) s += L[f][v] * vy[v][iy][G];
+            ch[f][iy] = s;
+          }
+        weno_rows<N, 0, NV>(ch, cHt, g.eps, raw, ch[0][N]);
+#pragma unroll
+        for (int f = 0; f < NV; ++f)
+#pragma unroll
+          for (int H = 0; H < NG; ++H) cH[f][H] = cHt[H][f];
+      } else {
+#pragma unroll
+        for (int f = 0; f < NV; ++f) {
+          double ch[NS];
+#pragma unroll
+          for (int iy = 0; iy < NS; ++iy) {
+            double s = 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) s += L[f][v] * vy[v][iy][G];
+            ch[iy] = s;
+          }
+          if (BND && g.wty) weno_row<N>(g.wty[j], ch, cH[f], g.eps, raw);  // this row's stencil
+          else weno_row<N>(T, ch, cH[f], g.eps, raw);
         }
-        if (BND && g.wty) weno_row<N>(g.wty[j], ch, cH[f], g.eps, raw);  // this row's stencil
-        else weno_row<N>(T, ch, cH[f], g.eps, raw);
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v)
