@@ -3,6 +3,8 @@ mixed batch of four-state Riemann problems, each to its final time: whole-run
 throughput and the final L1 error of every instance.
 
     python -m paper_1904_11147_amd.compare_l1 --count 24 --nmin 64 --nmax 128 --out result.json
+    python -m paper_1904_11147_amd.compare_l1 --count 256 --first-seed 10000 --nmin 64 --nmax 512 \
+        --max-side 256 --positivity --out result.json   # the benchmark batch's instances of side <= 256
 
 L1 is that of the density cell means against the plain method on the
 2x-refined mesh, averaged down (the refined run is the reference for every
@@ -44,10 +46,16 @@ def main():
     ap.add_argument("--t-end", type=float, default=0.25)
     ap.add_argument("--out", default=None)
     ap.add_argument("--positivity", action="store_true")
+    ap.add_argument("--max-side", type=int, default=None,
+                    help="keep only the drawn instances of at most this side (the draw itself is unchanged, so "
+                         "--count 256 --first-seed 10000 --nmin 64 --nmax 512 --max-side 256 gives the 256-instance "
+                         "benchmark batch's instances of side <= 256)")
     a = ap.parse_args()
     pos = {"positivity": 1} if a.positivity else {}
 
     wls = W.riemann2d_batch(count=a.count, first_seed=a.first_seed, nmin=a.nmin, nmax=a.nmax, t_end=a.t_end)
+    if a.max_side:
+        wls = [wl for wl in wls if wl.nx <= a.max_side]
     nets = {o: learned.MLP.load(os.path.join(HERE, "weights", f"indicator_q{o}.npz")) for o in (1, 2, 3)}
     rows = []
     # references and plain per-instance runs
@@ -78,7 +86,8 @@ def main():
         p.close()
         rows.append(r)
         print(f"instance {i}: n={wl.nx} Q{wl.order} plain {n} steps", flush=True)
-    res = {"count": a.count, "sizes": [a.nmin, a.nmax], "t_end": a.t_end, "positivity": bool(a.positivity),
+    res = {"count": a.count, "first_seed": a.first_seed, "sizes": [a.nmin, a.nmax], "max_side": a.max_side,
+           "instances_run": len(wls), "t_end": a.t_end, "positivity": bool(a.positivity),
            "plain_per_instance": {"seconds": t_plain, "dof_updates_per_s": dofs_plain / t_plain}}
     for kind in ("batched_plain", "batched_learned"):
         over = {"indicator": dg.IND_LEARNED} if kind == "batched_learned" else {}
