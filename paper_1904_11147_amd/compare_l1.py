@@ -46,6 +46,8 @@ def main():
     ap.add_argument("--t-end", type=float, default=0.25)
     ap.add_argument("--out", default=None)
     ap.add_argument("--positivity", action="store_true")
+    ap.add_argument("--weights", default=os.path.join(HERE, "weights"),
+                    help="folder with indicator_q<order>.npz")
     ap.add_argument("--max-side", type=int, default=None,
                     help="keep only the drawn instances of at most this side (the draw itself is unchanged, so "
                          "--count 256 --first-seed 10000 --nmin 64 --nmax 512 --max-side 256 gives the 256-instance "
@@ -56,7 +58,7 @@ def main():
     wls = W.riemann2d_batch(count=a.count, first_seed=a.first_seed, nmin=a.nmin, nmax=a.nmax, t_end=a.t_end)
     if a.max_side:
         wls = [wl for wl in wls if wl.nx <= a.max_side]
-    nets = {o: learned.MLP.load(os.path.join(HERE, "weights", f"indicator_q{o}.npz")) for o in (1, 2, 3)}
+    nets = {o: learned.MLP.load(os.path.join(a.weights, f"indicator_q{o}.npz")) for o in (1, 2, 3)}
     rows = []
     # references and plain per-instance runs
     t_plain = 0.0

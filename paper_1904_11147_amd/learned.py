@@ -7,10 +7,14 @@ Recipe (the workload's; the paper's own indicator is KXRCF):
 * data: plain FP64 runs (TVB M = 1 + CSWENO) of seeded 64 x 64 four-state
   Riemann problems (Q2 Euler) to t = 0.25; every `every`-th step, the state
   after one *unlimited* SSP-RK3 step from the current limited state is the
-  sample state.  Its features, its TVB flags (label) and the change the
-  limiter makes to each cell, w = 1 + |limited - unlimited|_1 / |unlimited|_1
-  (the sample weight), are recorded for equal numbers of random troubled and
-  untroubled cells (at most `cap` of each per sampled state);
+  sample state.  Its features, a label and the change the limiter makes to
+  each cell, c = |limited - unlimited|_1 / |unlimited|_1 (sample weight
+  1 + c), are recorded for equal numbers of random troubled and untroubled
+  cells (at most `cap` of each per sampled state).  The label is the TVB
+  flag, or, with min_change > 0, the TVB flag of cells with c > min_change
+  (the Q2 network: 3e-4; flagged cells below it are drawn first as
+  negatives), so that the network learns to leave out the flagged cells the
+  limiter hardly changes;
 * training: weighted binary cross-entropy, Adam (lr 1e-3), FP32 master
   weights with BF16 copies;
 * inference: p > 0.8 troubled, p < 0.2 untroubled, TVB in between.
@@ -143,10 +147,13 @@ SKIPPED = []  # (seed, time) of runs that met a non-physical state
 
 
 def generate_samples(seeds, n=64, order=2, t_end=0.25, every=10, device="cuda", max_steps=100000, gen_seed=0,
-                     cap=256):
+                     cap=256, min_change=0.0):
     """Training samples from plain runs (see the module docstring).  A run
     that meets a non-physical state (no positivity limiter is applied) stops
     there; its earlier samples are kept and the seed is recorded in SKIPPED.
+    min_change > 0: a TVB-flagged cell is labelled troubled only where the
+    limiter changes it by more than min_change (relative, the weight's ratio);
+    the flagged cells below it are the first negatives drawn.
     Returns (x bf16 [S][KP], y float [S], w float [S])."""
     g = torch.Generator(device="cpu").manual_seed(gen_seed)
     xs, ys, ws = [], [], []
@@ -165,19 +172,27 @@ def generate_samples(seeds, n=64, order=2, t_end=0.25, every=10, device="cuda", 
             lim.copy_(u)
             flags, _, _ = plain.limit(lim, want_margin=False)
             x = features(plain, u, bf16=True)
-            f = flags.reshape(-1).to(torch.float32)
+            flagged = flags.reshape(-1) != 0
             num = (lim - u).abs().sum(dim=(0, 1)).reshape(-1)
             den = u.abs().sum(dim=(0, 1)).reshape(-1).clamp_min(1e-300)
-            wgt = (1.0 + num / den).to(torch.float32)
+            chg = num / den
+            wgt = (1.0 + chg).to(torch.float32)
+            pos = flagged & (chg > min_change) if min_change > 0 else flagged
+            f = pos.to(torch.float32)
             # finite samples only (bf16 exponent all ones = inf/nan)
             ok = ((x & 0x7F80) != 0x7F80).all(dim=1) & torch.isfinite(wgt)
-            tr = torch.nonzero((f > 0.5) & ok).reshape(-1)
-            un = torch.nonzero((f < 0.5) & ok).reshape(-1)
-            m = min(tr.numel(), un.numel(), cap)
+            tr = torch.nonzero(pos & ok).reshape(-1)
+            hard = torch.nonzero(flagged & ~pos & ok).reshape(-1)  # flagged, small change
+            easy = torch.nonzero(~flagged & ok).reshape(-1)
+            m = min(tr.numel(), hard.numel() + easy.numel(), cap)
             if m > 0:
                 pt = torch.randperm(tr.numel(), generator=g)[:m].to(tr.device)
-                pu = torch.randperm(un.numel(), generator=g)[:m].to(un.device)
-                idx = torch.cat([tr[pt], un[pu]])
+                mh = min(hard.numel(), m)
+                parts = [tr[pt]]
+                if mh > 0:
+                    parts.append(hard[torch.randperm(hard.numel(), generator=g)[:mh].to(tr.device)])
+                parts.append(easy[torch.randperm(easy.numel(), generator=g)[:m - mh].to(tr.device)])
+                idx = torch.cat(parts)
                 xs.append(x[idx])
                 ys.append(f[idx])
                 ws.append(wgt[idx])

@@ -1,6 +1,8 @@
 """Train the learned troubled-cell indicator on plain runs and evaluate it.
 
     python -m paper_1904_11147_amd.train_indicator --seeds 0:200 --out weights.npz
+    python -m paper_1904_11147_amd.train_indicator --order 2 --epochs 30 --lr 2e-3 --lr-final 1e-4 \
+        --min-change 3e-4 --out indicator_q2.npz --eval-json eval_q2.json   # the committed Q2 network
 
 Data: seeded 64 x 64 four-state Riemann problems (2D Euler, Q1..Q3), see
 paper_1904_11147_amd.learned.  Progress is printed per seed block and per
@@ -34,6 +36,8 @@ def main():
     ap.add_argument("--eval-seeds", default="1000:1004")
     ap.add_argument("--eval-n", type=int, default=128)
     ap.add_argument("--eval-json", default=None)
+    ap.add_argument("--min-change", type=float, default=0.0,
+                    help="label a TVB-flagged cell troubled only above this relative limiter change")
     args = ap.parse_args()
     if args.out is None:
         args.out = f"indicator_q{args.order}.npz"
@@ -44,7 +48,7 @@ def main():
     block = 20
     for k in range(0, len(seeds), block):
         x, y, w = learned.generate_samples(seeds[k:k + block], n=args.n, order=args.order,
-                                           every=args.every)
+                                           every=args.every, min_change=args.min_change)
         xs.append(x)
         ys.append(y)
         ws.append(w)
