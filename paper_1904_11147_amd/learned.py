@@ -243,12 +243,14 @@ def _average_down(fine_means, factor):
     return fine_means.reshape(ny // factor, factor, nx // factor, factor).mean(dim=(1, 3))
 
 
-def evaluate(net, seeds, n=128, order=2, t_end=0.25, band=(0.2, 0.8), device="cuda", probe_every=50):
+def evaluate(net, seeds, n=128, order=2, t_end=0.25, band=(0.2, 0.8), device="cuda", probe_every=50, log=None):
     """Plain (TVB) vs learned runs of held-out problems: steps, troubled
     fraction, flag disagreement with TVB on the plain trajectory, and the L1
     error of the density means against the plain solution on the 2x-refined
-    mesh averaged down.  Returns a list of per-seed dicts."""
+    mesh averaged down.  Returns a list of per-seed dicts; log(text), if
+    given, receives a line per finished run."""
     out = []
+    say = log if log is not None else (lambda text: None)
     for seed in seeds:
         wl = W.riemann2d(n=n, order=order, seed=seed, t_end=t_end)
         res = {"seed": seed, "n": n}
@@ -268,6 +270,7 @@ def evaluate(net, seeds, n=128, order=2, t_end=0.25, band=(0.2, 0.8), device="cu
             res[kind + "_troubled_fraction"] = troubled / max(1, 3 * wl.cells * steps)
             finals[kind] = _density_means(state)
             prob.close()
+            say(f"eval seed {seed}: {kind} run, {steps} steps")
         # disagreement of the two indicators along the plain trajectory
         plain = dg.problem_from_workload(wl, device=device)
         learn = dg.problem_from_workload(wl, device=device, indicator=dg.IND_LEARNED)
@@ -281,10 +284,13 @@ def evaluate(net, seeds, n=128, order=2, t_end=0.25, band=(0.2, 0.8), device="cu
             fb, _, _ = learn.limit(b, want_margin=False)
             dis += int((fa != fb).sum().item())
             tot += fa.numel()
-            t, _ = plain.step(state, t, t_end, max_steps=probe_every, allow_nonphysical=True)
+            t, k = plain.step(state, t, t_end, max_steps=probe_every, allow_nonphysical=True)
+            if k == 0 or plain.status() != 0:  # a non-physical state stops the run
+                break
         res["flag_disagreement"] = dis / max(1, tot)
         plain.close()
         learn.close()
+        say(f"eval seed {seed}: flag disagreement {res['flag_disagreement']:.3f}")
         # reference: plain on the 2x-refined mesh, averaged down
         wf = W.riemann2d(n=2 * n, order=order, seed=seed, t_end=t_end)
         ref = dg.problem_from_workload(wf, device=device)

@@ -38,9 +38,19 @@ def main():
     ap.add_argument("--eval-json", default=None)
     ap.add_argument("--min-change", type=float, default=0.0,
                     help="label a TVB-flagged cell troubled only above this relative limiter change")
+    ap.add_argument("--eval-only", default=None, help="evaluate this saved network (no data, no training)")
     args = ap.parse_args()
     if args.out is None:
         args.out = f"indicator_q{args.order}.npz"
+    log = lambda s: print(s, flush=True)
+    if args.eval_only:
+        net = learned.MLP.load(args.eval_only)
+        ev = learned.evaluate(net, list(_range(args.eval_seeds)), n=args.eval_n, order=args.order, log=log)
+        for r in ev:
+            print(json.dumps(r), flush=True)
+        if args.eval_json:
+            json.dump({"eval": ev, "args": vars(args)}, open(args.eval_json, "w"), indent=1)
+        return
 
     seeds = list(_range(args.seeds))
     t0 = time.time()
@@ -69,7 +79,7 @@ def main():
           flush=True)
     net.save(args.out)
     print(f"saved {args.out}", flush=True)
-    ev = learned.evaluate(net, list(_range(args.eval_seeds)), n=args.eval_n, order=args.order)
+    ev = learned.evaluate(net, list(_range(args.eval_seeds)), n=args.eval_n, order=args.order, log=log)
     for r in ev:
         print(json.dumps(r), flush=True)
     if args.eval_json:
