@@ -76,15 +76,21 @@ def test_eno_property_at_jumps(oracle, N):
 
 
 @pytest.mark.parametrize("N", [1, 2, 3])
-def test_weights_tend_to_linear_on_smooth_data(oracle, N):
+@pytest.mark.parametrize("mode", ["raw", "split"])
+def test_weights_tend_to_linear_on_smooth_data(oracle, N, mode):
     """On smooth data with beta >> eps the nonlinear weights are within
     O(beta differences) of the linear ones; as eps grows (beta << eps) they
-    become exactly linear, so the value is the Q value gamma . p."""
+    become exactly linear, so the value is the Q value gamma . p.  With the
+    positive/negative split of the P3 inner points the same limit holds: the
+    two normalised groups recombine to the linear weights (gamma = sigma+
+    gamma+ - sigma- gamma-), so a wrong group sign, normalisation or factor
+    fails here."""
     t = oracle.weno_tables(N)
+    flag = oracle.NEGW_RAW if mode == "raw" else oracle.NEGW_SPLIT
     rng = np.random.default_rng(7 + N)
     for _ in range(5):
         a = 1.0 + 1e-4 * rng.normal(size=2 * N + 1)
         for G in range(len(t["rg"])):
             lin = t["gamma"][G] @ (t["rows"][G] @ a)
-            got = oracle.weno_eval(N, G, a, 1e10, oracle.NEGW_RAW)
-            assert abs(got - lin) <= 1e-13
+            got = oracle.weno_eval(N, G, a, 1e10, flag)
+            assert abs(got - lin) <= 1e-13, (N, G, mode, got - lin)
