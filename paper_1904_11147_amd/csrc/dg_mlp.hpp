@@ -534,49 +534,6 @@ __device__ __forceinline__ float max_nonneg(float a, float b) {
   return __uint_as_float(max(__float_as_uint(a), __float_as_uint(b)));
 }
 
-// Combinations over the four lanes r, r+16, r+32, r+48 (the four variables of
-// the cell in slot r) by the gfx950 lane swaps: permlane32_swap(x, x) gives
-// each lane the lower-half and the upper-half value of its position, and
-// permlane16_swap(x, x) those of the even and the odd row of its pair of
-// rows (VALU moves, no LDS round trip).  The result is the same in all four
-// lanes: every lane combines its values in the same order (lower half /
-// even row first).
-__device__ __forceinline__ uint32_t pl32_lo(uint32_t x, uint32_t &hi) {
-  const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
-  hi = r[1];
-  return r[0];
-}
-__device__ __forceinline__ uint32_t pl16_lo(uint32_t x, uint32_t &hi) {
-  const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
-  hi = r[1];
-  return r[0];
-}
-__device__ __forceinline__ float sum4_groups(float x) {
-  uint32_t h;
-  const uint32_t l = pl32_lo(__float_as_uint(x), h);
-  const float y = __uint_as_float(l) + __uint_as_float(h);
-  const uint32_t l2 = pl16_lo(__float_as_uint(y), h);
-  return __uint_as_float(l2) + __uint_as_float(h);
-}
-__device__ __forceinline__ int or4_groups(int x) {
-  uint32_t h;
-  const uint32_t l = pl32_lo((uint32_t)x, h);
-  const uint32_t y = l | h;
-  const uint32_t l2 = pl16_lo(y, h);
-  return (int)(l2 | h);
-}
-__device__ __forceinline__ double min4_groups(double x) {
-  const unsigned long long b = __double_as_longlong(x);
-  uint32_t hl, hh;
-  const uint32_t ll = pl32_lo((uint32_t)b, hl), lh = pl32_lo((uint32_t)(b >> 32), hh);
-  const double y = fmin(__longlong_as_double((long long)(((unsigned long long)lh << 32) | ll)),
-                        __longlong_as_double((long long)(((unsigned long long)hh << 32) | hl)));
-  const unsigned long long c = __double_as_longlong(y);
-  const uint32_t ml = pl16_lo((uint32_t)c, hl), mh = pl16_lo((uint32_t)(c >> 32), hh);
-  return fmin(__longlong_as_double((long long)(((unsigned long long)mh << 32) | ml)),
-              __longlong_as_double((long long)(((unsigned long long)hh << 32) | hl)));
-}
-
 typedef __bf16 bf16x2h_t __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
@@ -700,8 +657,12 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
         tflag |= tvb_test(upv - mean, dp, dm, Mh2, tmg);
         tflag |= tvb_test(mean - umv, dp, dm, Mh2, tmg);
       }
-      tflag = or4_groups(tflag ? 1 : 0) != 0;
-      tmg = min4_groups(tmg);
+      int fi = tflag ? 1 : 0;
+      fi |= __shfl_xor(fi, 16);
+      fi |= __shfl_xor(fi, 32);
+      tflag = fi != 0;
+      tmg = fmin(tmg, __shfl_xor(tmg, 16));
+      tmg = fmin(tmg, __shfl_xor(tmg, 32));
     };
     // features of variable gv: C, W, E, S, N, each with its modes; the
     // means relative to the centre's (whose own entry is 0); scaled by 1 / s
@@ -774,7 +735,8 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
         part += __uint_as_float(hb << 16) * par[2 * kHidden + k];
         part += __uint_as_float(hb & 0xffff0000u) * par[2 * kHidden + k + 1];
       }
-    part = sum4_groups(part);
+    part += __shfl_xor(part, 16);
+    part += __shfl_xor(part, 32);
     const float p = 1.f / (1.f + __expf(-(part + par[3 * kHidden])));
     bool flag = false;
     double mg = INFINITY;
