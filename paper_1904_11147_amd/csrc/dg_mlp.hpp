@@ -455,9 +455,10 @@ struct LmShape {
   static constexpr int FK = BV % 8 == 0 ? 8 : 4, KB = BV / FK;  // features per lane and k-block (MlpLayout::frag)
   static constexpr int KP = 4 * BV;  // padded input width (= (F + 15) / 16 * 16 for F = 4 FV)
   static constexpr int W1 = kHidden * KP, W2 = kHidden * kHidden;
-  static constexpr int PAR = 2 * (3 * kHidden + 2);  // b1 | b2 | w3 | b3 as floats (in bf16 slots)
+  static constexpr int W3 = kHidden;  // w3 in layer-3 fragment order [kb][g][e]
+  static constexpr int PAR = 2 * (2 * kHidden + 2);  // b1 | b2 | b3 as floats (in bf16 slots)
   static constexpr int WAVES = lm_waves(N);
-  static constexpr int LDS = W1 + W2 + PAR;
+  static constexpr int LDS = W1 + W2 + W3 + PAR;
 };
 
 // Copies the weights into LDS in fragment order (whole block), then a barrier.
@@ -486,13 +487,20 @@ __device__ inline void lm_load_weights(const LearnedArgs &L, uint16_t *wl) {
     }
     wl[S::W1 + k] = W2[(16 * nb + (ln & 15)) * kHidden + c];
   }
-  float *par = reinterpret_cast<float *>(wl + S::W1 + S::W2);
+  // w3 as the A fragment of layer 3 (every row of A the same): element e of
+  // lane group g, k-block kb is w3[c] with c the hidden unit of element e of
+  // that group's layer-2 B fragment (the column map of W2 above)
+  for (int k = tid; k < S::W3; k += nt) {
+    const int e = k % S::FK, gg = (k / S::FK) & 3, kb = k / (4 * S::FK);
+    const int c = S::FK == 8 ? 16 * (2 * kb + e / 4) + 4 * gg + e % 4 : 16 * kb + 4 * gg + e;
+    wl[S::W1 + S::W2 + k] = L.W[L.lay.w3() + c];
+  }
+  float *par = reinterpret_cast<float *>(wl + S::W1 + S::W2 + S::W3);
   for (int k = tid; k < kHidden; k += nt) {
     par[k] = L.M[L.lay.mb1() + k];
     par[kHidden + k] = L.M[L.lay.mb2() + k];
-    par[2 * kHidden + k] = bf2f(L.W[L.lay.w3() + k]);
   }
-  if (tid == 0) par[3 * kHidden] = L.M[L.lay.mb3()];
+  if (tid == 0) par[2 * kHidden] = L.M[L.lay.mb3()];
   __syncthreads();
 }
 
@@ -575,19 +583,36 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
   if (col > g.nx) col = g.nx;
   const bool owner = r >= 1 && r <= kLmStrip && col < g.nx;
   const long plane = (long)g.nx * g.ny;
-  const float *par = reinterpret_cast<const float *>(wl + S::W1 + S::W2);  // b1 | b2 | w3 | b3
+  const float *par = reinterpret_cast<const float *>(wl + S::W1 + S::W2 + S::W3);  // b1 | b2 | b3
   const double *__restrict__ up = u + (long)gv * NM * plane;
-  auto loadrow = [&](int jj, double (&R)[NM]) {
+  // Row jj's modes of the lane's variable.  On periodic and transmissive
+  // sides (!BND) a mirrored ghost's odd modes change sign: the loads are
+  // issued here and the signs fixed by fix_row once the values are needed
+  // (only where some lane of the wavefront holds such a ghost).
+  struct Flip {
+    bool fx, fy, any;
+  };
+  auto loadrow = [&](int jj, double (&R)[NM]) -> Flip {
     if (jj > g.ny) jj = g.ny;
     const CellIdx ci = map_cell<BND>(g, col, jj);
 #pragma unroll
     for (int q = 0; q < NM; ++q) {
-      if constexpr (BND) {
+      if constexpr (BND)
         R[q] = cell_mode<NP, NM, 2>(u, plane, g, ci, gv, q);
-      } else {  // periodic and transmissive sides: parity flips only
+      else
+        R[q] = up[(long)q * plane + ci.idx];
+    }
+    if constexpr (BND)
+      return Flip{false, false, false};
+    else
+      return Flip{ci.fx, ci.fy, __any(ci.fx || ci.fy) != 0};
+  };
+  auto fix_row = [&](const Flip &f, double (&R)[NM]) {
+    if (f.any) {
+#pragma unroll
+      for (int q = 0; q < NM; ++q) {
         const int m = q % NP, n = q / NP;
-        const double v = up[(long)q * plane + ci.idx];
-        R[q] = ((ci.fx && (m & 1)) != (ci.fy && (n & 1))) ? -v : v;
+        if ((f.fx && (m & 1)) != (f.fy && (n & 1))) R[q] = -R[q];
       }
     }
   };
@@ -605,12 +630,12 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
   float S32[NH], C32[NH], N32[NH], hS, hC, hN;
   {
     double Sv[NM];
-    loadrow(j0 - 1, Sv);
+    fix_row(loadrow(j0 - 1, Sv), Sv);
     Sm = Sv[0];
     hS = to32(Sv, S32);
   }
-  loadrow(j0, Cv);
-  loadrow(j0 + 1, Nv);
+  fix_row(loadrow(j0, Cv), Cv);
+  fix_row(loadrow(j0 + 1, Nv), Nv);
   hC = to32(Cv, C32);
   hN = to32(Nv, N32);
   const float Mh2 = (float)g.tvb_Mx;
@@ -632,7 +657,7 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
   }
   for (int j = j0; j < j1; ++j) {
     double Pv[NM];
-    loadrow(j + 2, Pv);  // in flight while this row is evaluated
+    const Flip fp = loadrow(j + 2, Pv);  // in flight while this row is evaluated
     // TVB decision of this variable (the expressions of tvb_cell), combined
     // over the cell's lanes; only needed for a probability inside the band
     auto tvb_decision = [&](bool &tflag, double &tmg) {
@@ -672,7 +697,7 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
     float mx = max_nonneg(max_nonneg(Mh2, hC), max_nonneg(hS, hN));
     mx = max_nonneg(mx, max_nonneg(row_shift0<true>(hC), row_shift0<false>(hC)));
     mx = max_nonneg(mx, max_nonneg(max_nonneg(fabsf(dW), fabsf(dE)), max_nonneg(fabsf(dS), fabsf(dN))));
-    const float inv = 1.0f / mx;
+    const float inv = __builtin_amdgcn_rcpf(mx);
     auto feature = [&](int f) -> float {
       if (f >= FV) return 0.f;  // padding
       const int c = f / NM, q = f % NM;
@@ -724,20 +749,24 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
           h[nb] = mfma16(w2_regs ? w2f[w2_regs ? nb : 0][w2_regs ? kb : 0] : load4(w2frag(nb, kb)), h1[kb], h[nb]);
         }
       }
-    // layer 3 (on the BF16-rounded activations) and the decision
-    float part = 0.f;
+    // layer 3 on the BF16-rounded activations, as one more MFMA layer: w3
+    // is the A fragment with all 16 rows the same and b3 the accumulator's
+    // start, so every element of the lane's result is its cell's logit
+    bf16x4_t h2[4];
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb)
+      h2[nb] = pk4_bf16(relu_bits(h[nb][0]), relu_bits(h[nb][1]), relu_bits(h[nb][2]), relu_bits(h[nb][3]));
+    const float b3 = par[2 * kHidden];
+    f32x4_t z{b3, b3, b3, b3};
+    const uint16_t *w3f = wl + S::W1 + S::W2 + gv * FK;
+    if constexpr (FK == 8) {
 #pragma unroll
-      for (int e = 0; e < 4; e += 2) {
-        const int k = 16 * nb + 4 * gv + e;
-        const uint32_t hb = pk_bf16(relu_bits(h[nb][e]), relu_bits(h[nb][e + 1]));
-        part += __uint_as_float(hb << 16) * par[2 * kHidden + k];
-        part += __uint_as_float(hb & 0xffff0000u) * par[2 * kHidden + k + 1];
-      }
-    part += __shfl_xor(part, 16);
-    part += __shfl_xor(part, 32);
-    const float p = 1.f / (1.f + __expf(-(part + par[3 * kHidden])));
+      for (int kb = 0; kb < KB2; ++kb) z = mfma32(load8(w3f + 32 * kb), cat8(h2[2 * kb], h2[2 * kb + 1]), z);
+    } else {
+#pragma unroll
+      for (int kb = 0; kb < KB2; ++kb) z = mfma16(load4(w3f + 16 * kb), h2[kb], z);
+    }
+    const float p = __builtin_amdgcn_rcpf(1.f + __expf(-z[0]));
     bool flag = false;
     double mg = INFINITY;
     const bool in_band = !(p > L.band_hi) && !(p < L.band_lo);
@@ -753,6 +782,7 @@ __device__ inline void lm_strip(const double *__restrict__ u, const Geometry &g,
     if (p > L.band_hi) flag = true;
     emit(owner && gv == 0, flag, mg, p, (long)j * g.nx + col);
     Sm = c0;
+    fix_row(fp, Pv);
 #pragma unroll
     for (int q = 0; q < NM; ++q) {
       Cv[q] = Nv[q];
