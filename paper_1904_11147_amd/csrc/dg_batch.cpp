@@ -95,6 +95,10 @@ struct dg_batch {
   BatchCtx ctx{};
   DevScalars *sc = nullptr;  // device [n]
   hipStream_t user_stream = nullptr, capture_stream = nullptr;
+  // per-order branches of the captured step (orders after the first present
+  // one run on their own stream between a fork and a join event)
+  hipStream_t branch[kMaxN + 1] = {};
+  hipEvent_t fork = nullptr, join[kMaxN + 1] = {};
   hipGraphExec_t graph = nullptr;
   int present[kMaxN + 1] = {};
   int rows[kMaxN + 1] = {};
@@ -179,23 +183,69 @@ int write_scalars(dg_batch *b, const double *t, const double *t_end, int32_t max
 }
 
 // One batched SSP-RK3 step (enqueue only): time-step decisions and queues,
-// then per stage the stage kernels of all orders and their limiter passes.
+// then the three stages, each followed by its limiter pass.  The orders
+// touch disjoint instances, queues and lists, so their chains are
+// independent.  With the learned indicator (whose passes leave most of the
+// GPU idle: few blocks, each holding a network in LDS) the first present
+// order runs on the step's stream and each other one on a branch stream
+// forked after the decision and joined at the end (parallel branches of the
+// captured graph, which the GPU may run at once).  Otherwise one stream runs
+// each stage of all orders, then their limiter passes (concurrent stage
+// kernels, each sized to fill the GPU, only contend).
 int enqueue_batch_step(dg_batch *b) {
   int rc = dg::batch_launch_decide(b->ctx, 1);
-  for (int stage = 1; stage <= 3 && !rc; ++stage) {
-    for (int o = 1; o <= kMaxN && !rc; ++o)
-      if (b->present[o]) rc = dg::batch_launch_stage(b->ctx, o, stage, b->grid[o]);
-    if (b->ctx.limiter == DG_LIM_NONE && !b->ctx.positivity) continue;
-    for (int o = 1; o <= kMaxN && !rc; ++o)
-      if (b->present[o]) rc = dg::batch_launch_limit(b->ctx, o, stage - 1);
+  const bool limit = b->ctx.limiter != DG_LIM_NONE || b->ctx.positivity;
+  if (b->ctx.indicator != DG_IND_LEARNED) {
+    for (int stage = 1; stage <= 3 && !rc; ++stage) {
+      for (int o = 1; o <= kMaxN && !rc; ++o)
+        if (b->present[o]) rc = dg::batch_launch_stage(b->ctx, o, stage, b->grid[o]);
+      if (!limit) continue;
+      for (int o = 1; o <= kMaxN && !rc; ++o)
+        if (b->present[o]) rc = dg::batch_launch_limit(b->ctx, o, stage - 1);
+    }
+    return rc;
+  }
+  if (rc) return rc;
+  const hipStream_t st0 = (hipStream_t)b->ctx.stream;
+  int first = 0;
+  for (int o = 1; o <= kMaxN && !first; ++o)
+    if (b->present[o]) first = o;
+  if (hipEventRecord(b->fork, st0) != hipSuccess) return DG_ERR_HIP;
+  for (int o = 1; o <= kMaxN && !rc; ++o) {
+    if (!b->present[o]) continue;
+    dg::BatchCtx c = b->ctx;
+    if (o != first) {
+      if (hipStreamWaitEvent(b->branch[o], b->fork, 0) != hipSuccess) return DG_ERR_HIP;
+      c.stream = b->branch[o];
+    }
+    for (int stage = 1; stage <= 3 && !rc; ++stage) {
+      rc = dg::batch_launch_stage(c, o, stage, b->grid[o]);
+      if (!rc && limit) rc = dg::batch_launch_limit(c, o, stage - 1);
+    }
+    if (!rc && o != first) {
+      if (hipEventRecord(b->join[o], b->branch[o]) != hipSuccess || hipStreamWaitEvent(st0, b->join[o], 0) != hipSuccess)
+        return DG_ERR_HIP;
+    }
   }
   return rc;
+}
+
+// Streams and events of the per-order branches (created once, default priority).
+int make_branches(dg_batch *b) {
+  if (!b->fork && hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) return DG_ERR_HIP;
+  for (int o = 1; o <= kMaxN; ++o) {
+    if (!b->branch[o] && hipStreamCreateWithFlags(&b->branch[o], hipStreamNonBlocking) != hipSuccess) return DG_ERR_HIP;
+    if (!b->join[o] && hipEventCreateWithFlags(&b->join[o], hipEventDisableTiming) != hipSuccess) return DG_ERR_HIP;
+  }
+  return DG_OK;
 }
 
 int build_batch_graph(dg_batch *b) {
   drop_graph(b);
   if (!b->capture_stream && hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess)
     return DG_ERR_HIP;
+  if (b->ctx.indicator == DG_IND_LEARNED)
+    if (int r = make_branches(b)) return r;
   void *saved = b->ctx.stream;
   b->ctx.stream = b->capture_stream;
   if (hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -309,6 +359,11 @@ int dg_batch_destroy(dg_batch *b) {
   if (!b) return DG_OK;
   drop_graph(b);
   if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+  for (int o = 1; o <= kMaxN; ++o) {
+    if (b->branch[o]) (void)hipStreamDestroy(b->branch[o]);
+    if (b->join[o]) (void)hipEventDestroy(b->join[o]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
   delete b;
   return DG_OK;
 }
