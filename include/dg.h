@@ -306,18 +306,23 @@ int dg_set_learned(dg_problem *p, const uint16_t *w_bf16, const float *master, d
  * mode for all) advanced together, each with its own CFL time step
  * (Section 2's scheme and Section 3's limiter applied to every instance as
  * dg_step applies them to one).  A step of the batch is one SSP-RK3 step of
- * every instance still short of its end time: per RK stage one persistent
- * kernel per order walks a device-side queue of (instance, tile) work items,
- * followed by the limiter pass of that stage; finished instances leave the
- * queue on the device.  Each instance's results are identical, bit for bit,
- * to dg_step on the same problem.
+ * every instance still short of its end time: per RK stage one kernel per
+ * order whose wavefronts take the (instance, tile) work items of a
+ * device-side queue (a grid of the order's full tile count; wavefronts past
+ * the live count exit at once), followed by the limiter pass of that stage;
+ * finished instances leave the queue on the device.  The step is one
+ * captured graph; with the learned indicator each order's chain is its own
+ * branch of it.  Each instance's results are identical, bit for bit, to
+ * dg_step on the same problem.
  *
  * Memory: the caller owns one device buffer `states` holding every
  * instance's state (layout of dg_project, FP64) at element offsets
  * offsets[i] (host int64 array, multiples of 32), and one workspace of
  * dg_batch_workspace_bytes (256-byte aligned) that holds per-instance stage
  * buffers (two state volumes each), scalars, descriptors, the work queues and
- * the troubled-cell lists.  The library allocates nothing.
+ * the troubled-cell lists.  The library allocates no device memory; it
+ * creates a capture stream (with the learned indicator also one stream and
+ * event per order), released by dg_batch_destroy.
  * ------------------------------------------------------------------------ */
 typedef struct dg_batch dg_batch;
 
