@@ -176,6 +176,42 @@ def indicator_leg(wl, state0, t0, steps, warmup, indicator=0, net=None, limiter=
             "troubled_fraction": troubled / max(1, 3 * wl.cells * n)}
 
 
+def full_run_leg(wl, indicator=0, net=None, chunk=2000):
+    """The whole run of the 2D Euler problem: from the projected and limited
+    initial state to t_end by dg_step (captured step graph), wall time over
+    every step (tile height autotuned first, untimed); troubled fraction over
+    all limiter passes; progress on stderr after every `chunk` steps."""
+    import torch
+    from paper_1904_11147_amd import dg, learned
+    prob = dg.problem_from_workload(wl, device="cuda:0", indicator=indicator)
+    if net is not None:
+        learned.attach(prob, net)
+    state = dg.initial_state(prob, wl, limit=True)
+    prob.autotune(state)
+    torch.cuda.synchronize()
+    t, total, troubled, status = 0.0, 0, 0, "ok"
+    prob.profile_read(reset=True)
+    a = time.perf_counter()
+    while t < wl.t_end:
+        try:
+            t, n = prob.step(state, t, wl.t_end, max_steps=chunk)
+        except dg.DGError as e:
+            status = str(e)
+            break
+        total += n
+        troubled += prob.profile_read(reset=True)[1]
+        print(f"full run ({'learned' if net is not None else 'plain'}): t = {t:.5f} after {total} steps, "
+              f"{time.perf_counter() - a:.1f} s", file=sys.stderr, flush=True)
+        if n == 0:
+            break
+    torch.cuda.synchronize()
+    el = time.perf_counter() - a
+    prob.close()
+    return {"t_end": wl.t_end, "t_reached": t, "steps": total, "seconds": el, "status": status,
+            "ms_per_step": 1e3 * el / max(1, total), "value": wl.dofs * total / el, "unit": "cell-DOF updates/s",
+            "troubled_fraction": troubled / max(1, 3 * wl.cells * total)}
+
+
 def timed_steps(prob, state, t, t_end, steps, profile):
     """steps of dg_step from t; with profile: kernel events on.  Returns
     (t, steps taken, seconds, per-kind kernel times, troubled cells)."""
@@ -413,6 +449,9 @@ def main():
                     help="run only the double Mach reflection leg and print its record (for profiling)")
     ap.add_argument("--double-mach-to-end", action="store_true",
                     help="also run the double Mach reflection to t = 0.2 (about a minute)")
+    ap.add_argument("--full-run", action="store_true",
+                    help="only run the 2D Euler problem to t_end, plain and with the learned indicator, and print "
+                         "their records (a few minutes)")
     ap.add_argument("--no-late", action="store_true", help="skip the late-time window of the 2D Euler run")
     ap.add_argument("--late-t", type=float, default=0.05, help="time at which the late window starts")
     ap.add_argument("--no-burgers2d", action="store_true", help="skip the 2D Burgers 1024^2 leg")
@@ -434,6 +473,15 @@ def main():
               flush=True)
         return
     wl = W.riemann2d(n=args.n, order=2, seed=args.seed)
+    if args.full_run:
+        nets = learned_nets("cuda:0")
+        res = {"workload": f"{wl.name}: 2D Euler four-state Riemann problem, {wl.nx}x{wl.ny} cells, Q2, "
+                           f"TVB M=1 + CSWENO, CFL {wl.cfl}, to t = {wl.t_end}",
+               "plain": full_run_leg(wl)}
+        if 2 in nets:
+            res["learned"] = full_run_leg(wl, dg.IND_LEARNED, nets[2])
+        print(json.dumps({"full_run": res}), flush=True)
+        return
     prob = dg.problem_from_workload(wl, device="cuda:0")
     state = dg.initial_state(prob, wl, limit=True)
     tuned_rows, tuned_ms = prob.autotune(state)
