@@ -171,9 +171,15 @@ def indicator_leg(wl, state0, t0, steps, warmup, indicator=0, net=None, limiter=
     torch.cuda.synchronize()
     el = time.perf_counter() - a
     _, troubled = prob.profile_read(reset=True)
+    # the next steps once more with kernel events, for the per-kind times
+    prob.profile(True)
+    t, n2 = prob.step(state, t, wl.t_end, max_steps=steps)
+    prof, _ = prob.profile_read(reset=True)
+    prob.profile(False)
     prob.close()
     return {"value": wl.dofs * n / el, "ms_per_step": 1e3 * el / n, "steps": n,
-            "troubled_fraction": troubled / max(1, 3 * wl.cells * n)}
+            "troubled_fraction": troubled / max(1, 3 * wl.cells * n),
+            "kernels_ms_per_step": {k: v[0] / max(1, n2) for k, v in prof.items()}}
 
 
 def full_run_leg(wl, indicator=0, net=None, chunk=2000):
@@ -239,7 +245,14 @@ def late_window_leg(prob, wl, state, t, t_late, steps, net=None):
     from paper_1904_11147_amd import dg
     torch.cuda.synchronize()
     a = time.perf_counter()
-    t, n_adv = prob.step(state, t, t_late)
+    n_adv = 0
+    while t < t_late:  # in chunks, with progress on stderr
+        t, n = prob.step(state, t, t_late, max_steps=2000)
+        n_adv += n
+        print(f"late window: advanced to t = {t:.5f} ({n_adv} steps, {time.perf_counter() - a:.1f} s)",
+              file=sys.stderr, flush=True)
+        if n == 0:
+            break
     torch.cuda.synchronize()
     adv_s = time.perf_counter() - a
     late = state.clone()

@@ -145,6 +145,30 @@ def fp64(path, kernel, cmd, out):
     print(json.dumps(res, indent=1))
 
 
+def legs(path, before, window, cmd, out):
+    """Per-kernel mean durations in the last two legs of one kernel trace
+    (rocprofv3 kernel_trace.csv): the `window` dispatches that end two
+    dispatches after the last one matching `before` (that leg's last limiter
+    pass: indicator, reconstruction, scatter), and every dispatch after them
+    (the next leg)."""
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"]))
+    last = max(i for i, r in enumerate(rows) if re.search(before, r["Kernel_Name"]))
+    cut = min(len(rows), last + 3)
+    lines = ["# rocprofv3 kernel trace, per-kernel mean durations of two legs", f"# command: {cmd}",
+             f"# first leg: the {window} dispatches up to the last limiter pass after {before!r}; second leg: the rest", "#"]
+    for label, part in (("first leg", rows[max(0, cut - window):cut]), ("second leg", rows[cut:])):
+        acc = {}
+        for r in part:
+            acc.setdefault(short_name(r["Kernel_Name"]), []).append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        lines.append(f"== {label}: {len(part)} dispatches")
+        lines.append(f"{'kernel':<60} {'calls':>7} {'avg_us':>10} {'total_ms':>10}")
+        for k, v in sorted(acc.items(), key=lambda kv: -sum(kv[1])):
+            lines.append(f"{k[:60]:<60} {len(v):>7} {sum(v) / len(v):>10.1f} {sum(v) / 1e3:>10.2f}")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -164,13 +188,21 @@ def main():
     c.add_argument("csv")
     c.add_argument("--cmd", required=True)
     c.add_argument("--out", required=True)
+    g = sub.add_parser("legs")
+    g.add_argument("csv")
+    g.add_argument("--before", required=True, help="regular expression on the kernel name")
+    g.add_argument("--window", type=int, required=True)
+    g.add_argument("--cmd", required=True)
+    g.add_argument("--out", required=True)
     f = sub.add_parser("fp64")
     f.add_argument("csv")
     f.add_argument("--kernel", required=True, help="regular expression on the kernel name")
     f.add_argument("--cmd", required=True)
     f.add_argument("--out", required=True)
     a = ap.parse_args()
-    if a.what == "fp64":
+    if a.what == "legs":
+        legs(a.csv, a.before, a.window, a.cmd, a.out)
+    elif a.what == "fp64":
         fp64(a.csv, a.kernel, a.cmd, a.out)
     elif a.what == "stats":
         stats(a.csv, a.cmd, a.out)
