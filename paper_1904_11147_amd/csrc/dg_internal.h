@@ -74,7 +74,8 @@ struct DevScalars {
   int32_t status;
   int32_t count[4];  // troubled-cell counts: stage 1..3, standalone limiter
   unsigned long long troubled_total;  // all troubled cells flagged since the last reset
-  int32_t pad[4];
+  int32_t count_scratch;  // the learned pass's own list (rebuilt in row order after it)
+  int32_t pad[3];
   double tn;  // start time of the current step
   double tb;  // time of the boundary data of the kernels running now
 };

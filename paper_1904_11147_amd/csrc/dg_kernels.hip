@@ -1388,6 +1388,8 @@ __global__ void k_reset(DevScalars *sc, int what) {
   if (threadIdx.x != 0) return;
   if (what == 0) {  // standalone limiter count
     sc->count[3] = 0;
+  } else if (what == 2) {  // the learned pass's own list
+    sc->count_scratch = 0;
   } else {  // speed accumulators
     sc->smax[0] = 0ull;
     sc->smax[1] = 0ull;
@@ -1730,8 +1732,9 @@ __device__ inline bool kxrcf_cell(const double *__restrict__ u, const Geometry &
 
 // Appends the flagged cells of a block to the troubled list (every thread of
 // the block calls it): one atomic per block, since one per wavefront contends
-// for the counter once most wavefronts flag a cell.
-__device__ inline void append_troubled_block(const LimitArgs &a, bool flag, long cell) {
+// for the counter once most wavefronts flag a cell.  total: also add them to
+// the run's count of troubled cells.
+__device__ inline void append_troubled_block(const LimitArgs &a, bool flag, long cell, bool total = true) {
   __shared__ int s_cnt[kBlock / 64];
   __shared__ int s_base;
   const unsigned long long ballot = __ballot(flag);
@@ -1740,10 +1743,10 @@ __device__ inline void append_troubled_block(const LimitArgs &a, bool flag, long
   if (lane == 0) s_cnt[wave] = __popcll(ballot);
   __syncthreads();
   if (wave == 0 && lane == 0) {
-    int total = 0;
-    for (int w = 0; w < waves; ++w) total += s_cnt[w];
-    s_base = total ? atomicAdd(a.count, total) : 0;
-    if (total) atomicAdd(&a.sc->troubled_total, (unsigned long long)total);
+    int n = 0;
+    for (int w = 0; w < waves; ++w) n += s_cnt[w];
+    s_base = n ? atomicAdd(a.count, n) : 0;
+    if (n && total) atomicAdd(&a.sc->troubled_total, (unsigned long long)n);
   }
   __syncthreads();
   if (flag) {
@@ -2694,6 +2697,21 @@ int launch_scratch_init(const LaunchCtx &c, double tb) {
   return check_launch();
 }
 
+// The troubled list rebuilt in row order from the flags the learned pass has
+// written: that pass appends its cells per wavefront in 14-cell pieces of its
+// strip, so the 64 consecutive entries a reconstruction or scatter wavefront
+// takes would span about five rows.  The same cells; counted once, by the
+// learned pass.
+__global__ __launch_bounds__(kBlock) void k_list_from_flags(LimitArgs a) {
+  const Geometry &g = a.geo;
+  if (a.check_done && a.sc->done) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const long cell = (long)j * g.nx + i;
+  const bool flag = i < g.nx && j < g.ny && a.flags[cell] != 0;
+  append_troubled_block(a, flag, cell, false);
+}
+
 int launch_limit(const LaunchCtx &c, double *u, double *side, int count_slot, uint8_t *flags, double *margin,
                  const uint8_t *flags_override) {
   LimitArgs a;
@@ -2721,8 +2739,18 @@ int launch_limit(const LaunchCtx &c, double *u, double *side, int count_slot, ui
                       (float)c.band_hi, c.mlp_prob};
         constexpr int waves = lm_waves(n);
         const int groups = ((c.geo.nx + kLmStrip - 1) / kLmStrip + waves - 1) / waves;
+        // the pass writes its flags (the problem's flag buffer if the caller
+        // passed none) and its own list on a counter of its own; the list the
+        // limiter reads is then rebuilt from the flags in row order
+        LimitArgs al = a;
+        if (!al.flags) al.flags = c.flags;
+        al.count = &c.sc->count_scratch;
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, S(c), c.sc, 2);
         hipLaunchKernelGGL((k_indicator_learned<n, e, false>), dim3(groups, (c.geo.ny + kLmRows - 1) / kLmRows),
-                           dim3(64 * waves), 0, S(c), a, L, kLmRows);
+                           dim3(64 * waves), 0, S(c), al, L, kLmRows);
+        LimitArgs ar = a;
+        ar.flags = al.flags;
+        hipLaunchKernelGGL(k_list_from_flags, grid, block, 0, S(c), ar);
         learned = true;
       }
     }
